@@ -1,0 +1,148 @@
+"""Multigrid step and Bethe-lattice DMFT step (oracle side).
+
+TEST INFRASTRUCTURE ONLY: nothing in the product path imports this module.
+
+The multigrid HF-QMC method (section "Multigrid HF-QMC method", Fig. 1(c))
+solves the impurity problem at a fixed bath for several dtau_i, then
+  (i)  interpolates each discrete estimate G_dtau_i(tau_k) onto a common fine
+       tau grid with the help of a reference model, and
+  (ii) performs, on that grid, a least-squares fit that is quadratic in
+       dtau^2 and keeps its dtau -> 0 value.
+The paper delegates the details of (i) to other work; the readings taken here:
+  * reference model  G_ref(i w) = 1 / (1/Bath(i w) - U^2 / (4 i w)), the
+    half-filled atomic self-energy on top of the bath.  It has the exact
+    1/(i w)^3 moment (m3 + U^2/4) and reproduces U = 0 and the atomic limit;
+  * interpolation    natural cubic spline of G_i - G_ref through all L_i + 1
+    points tau_k = k beta / L_i (tau_L = beta-), plus G_ref on the fine grid;
+    errors are interpolated linearly;
+  * extrapolation    weighted least squares G_i = c0 + c1 x_i + c2 x_i^2,
+    x_i = dtau_i^2, weights 1/sigma_i^2 (sigma floored at SIGMA_FLOOR); the
+    result is c0 with error sqrt([(X^T W X)^{-1}]_00).
+The DMFT closure for the Bethe lattice with hopping t (semi-elliptic DOS,
+W = 4t) is Bath_new(i w) = 1/(i w - t^2 G(i w)), with G(i w) obtained as
+G_ref(i w) plus the exact Fourier integral of the cubic spline of G - G_ref.
+"""
+import numpy as np
+from scipy.interpolate import CubicSpline
+
+from . import bath as B
+from . import hfqmc as H
+
+SIGMA_FLOOR = 1e-14
+
+
+def reference_iw(bath_iw, U, beta):
+    """Reference model on the Matsubara axis."""
+    w = B.matsubara(beta, bath_iw.shape[0])
+    return 1.0 / (1.0 / bath_iw - U * U / (4.0 * 1j * w))
+
+
+def reference_tau(bath_iw, m3, U, beta, tau):
+    """Reference model at imaginary times (tail moment m3 + U^2/4)."""
+    return B.iw_to_tau(reference_iw(bath_iw, U, beta), m3 + 0.25 * U * U, beta, tau)
+
+
+def grid_lengths(beta, dtaus):
+    """Trotter numbers L_i = round(beta / dtau_i); the exact dtau_i = beta / L_i is used."""
+    Ls = [int(round(beta / d)) for d in dtaus]
+    return Ls, [beta / L for L in Ls]
+
+
+def fine_grid(beta, n_fine):
+    """Common fine grid tau_j = j beta / (n_fine - 1), endpoints included (tau = beta-)."""
+    return np.arange(n_fine) * (beta / (n_fine - 1))
+
+
+def interpolate_grid(g_grid, err_grid, beta, gref_grid, gref_fine, tau_fine):
+    """Step (i): spline G_i - G_ref over tau_k = k beta / L, add G_ref back."""
+    L = g_grid.shape[0] - 1
+    tau_k = np.arange(L + 1) * (beta / L)
+    cs = CubicSpline(tau_k, g_grid - gref_grid, bc_type="natural")
+    g_f = gref_fine + cs(tau_fine)
+    e_f = np.interp(tau_fine, tau_k, err_grid)
+    return g_f, e_f
+
+
+def extrapolate(dtaus, g_interp, e_interp):
+    """Step (ii): per fine point, weighted quadratic-in-dtau^2 least squares.
+
+    g_interp, e_interp: [n_grids, n_fine].  Returns (c0 [n_fine], err [n_fine]).
+    """
+    x = np.asarray(dtaus, dtype=np.float64) ** 2
+    X = np.stack([np.ones_like(x), x, x * x], axis=1)
+    n_fine = g_interp.shape[1]
+    c0 = np.empty(n_fine)
+    err = np.empty(n_fine)
+    for j in range(n_fine):
+        sig = np.maximum(e_interp[:, j], SIGMA_FLOOR)
+        w = 1.0 / sig ** 2
+        A = X.T @ (w[:, None] * X)
+        b = X.T @ (w * g_interp[:, j])
+        cov = np.linalg.inv(A)
+        coef = cov @ b
+        c0[j] = coef[0]
+        err[j] = np.sqrt(max(cov[0, 0], 0.0))
+    return c0, err
+
+
+def multigrid_solve(bath_iw, m3, U, beta, dtaus, seed, n_chains, warmup, sweeps,
+                    n_rec=100, n_fine=200):
+    """Oracle multigrid solve: one fixed-dtau solve per grid (grid_id = i), then (i), (ii)."""
+    Ls, dts = grid_lengths(beta, dtaus)
+    tau_f = fine_grid(beta, n_fine)
+    gref_f = reference_tau(bath_iw, m3, U, beta, tau_f)
+    gi, ei, per = [], [], []
+    for i, L in enumerate(Ls):
+        g_tau = B.bath_to_tau(bath_iw, m3, beta, L)
+        r = H.solve(g_tau, U, beta, seed, n_chains=n_chains, warmup=warmup,
+                    sweeps=sweeps, n_rec=n_rec, grid_id=i)
+        tau_k = np.arange(L + 1) * (beta / L)
+        gref_k = reference_tau(bath_iw, m3, U, beta, tau_k)
+        g_f, e_f = interpolate_grid(r["g"], r["g_err"], beta, gref_k, gref_f, tau_f)
+        gi.append(g_f)
+        ei.append(e_f)
+        per.append(r)
+    c0, err = extrapolate(dts, np.array(gi), np.array(ei))
+    return dict(g=c0, g_err=err, tau=tau_f, grids=per, g_interp=np.array(gi),
+                e_interp=np.array(ei), Ls=Ls, dtaus=dts)
+
+
+def spline_fourier(tau, values, beta, n_iw):
+    """Exact int_0^beta e^{i w_n tau} S(tau) d tau for the natural cubic spline S.
+
+    On each interval the integral of e^{i w tau} p(tau) for a cubic p is
+    [e^{i w tau} sum_{m=0}^{3} (-1)^m p^{(m)}(tau) / (i w)^{m+1}] between its ends.
+    """
+    cs = CubicSpline(tau, values, bc_type="natural")
+    c = cs.c  # c[m, i]: coefficient of (tau - tau_i)^(3-m)
+    h = np.diff(tau)
+    a3, a2, a1, a0 = c[0], c[1], c[2], c[3]
+    # derivatives at the left ends
+    dl = [a0, a1, 2 * a2, 6 * a3]
+    # derivatives at the right ends
+    dr = [a0 + a1 * h + a2 * h ** 2 + a3 * h ** 3,
+          a1 + 2 * a2 * h + 3 * a3 * h ** 2,
+          2 * a2 + 6 * a3 * h,
+          6 * a3]
+    w = B.matsubara(beta, n_iw)
+    iw = 1j * w
+    out = np.zeros(n_iw, dtype=np.complex128)
+    for m in range(4):
+        coef = (-1.0) ** m / iw ** (m + 1)
+        right = np.exp(1j * np.outer(w, tau[1:])) @ dr[m]
+        left = np.exp(1j * np.outer(w, tau[:-1])) @ dl[m]
+        out += coef * (right - left)
+    return out
+
+
+def g_tau_to_iw(g_fine, tau_fine, bath_iw, m3, U, beta):
+    """G(i w) = G_ref(i w) - FT[spline(G - G_ref)] (positive tau convention)."""
+    gref_f = reference_tau(bath_iw, m3, U, beta, tau_fine)
+    delta = spline_fourier(tau_fine, np.asarray(g_fine) - gref_f, beta, bath_iw.shape[0])
+    return reference_iw(bath_iw, U, beta) - delta
+
+
+def dmft_bethe_step(g_fine, tau_fine, bath_iw, m3, U, beta, t):
+    """One Bethe-lattice self-consistency step: the new bath on the same frequencies."""
+    g_iw = g_tau_to_iw(g_fine, tau_fine, bath_iw, m3, U, beta)
+    return B.bethe_step_iw(g_iw, beta, t)
