@@ -1,0 +1,163 @@
+/* hfqmc.h -- C ABI of the MI355X Hirsch-Fye QMC library (libhfqmc.so).
+ *
+ * Method: multigrid Hirsch-Fye quantum Monte Carlo for dynamical mean-field
+ * theory (N. Bluemer, arXiv:0801.1222).  The impurity problem is solved at a
+ * fixed bath on several Trotter grids dtau_i by Monte Carlo sampling of a
+ * binary Hubbard-Stratonovich field (Introduction; section "Multigrid HF-QMC
+ * method"), the grid results are interpolated onto a common fine tau grid
+ * with a reference model and extrapolated quadratically in dtau^2 to dtau -> 0
+ * (same section, steps (i) and (ii)); the DMFT cycle is closed on the Bethe
+ * lattice with semi-elliptic DOS, W = 4t (Fig. 1 and "Benchmark results").
+ *
+ * General conventions
+ *  - Every pointer argument is owned by the caller and is only read or
+ *    written during the call; the library never keeps it.  All pointers are
+ *    HOST pointers.  Device memory is allocated inside the context.
+ *  - FP64 everywhere on the interface.  Complex arrays are interleaved
+ *    (re, im) doubles.
+ *  - Imaginary-time Green functions use the positive convention
+ *    G(tau) = <T c(tau) c^dag(0)>, 0 <= tau < beta, G(0) meaning G(0+) =
+ *    1 - n; the point tau = beta means beta- and equals 1 - G(0+).
+ *  - Matsubara arrays hold n = 0..n_iw-1 at w_n = (2n+1) pi / beta with the
+ *    standard sign, G(i w) ~ 1/(i w).
+ *  - Return value: HFQMC_OK (0) or a negative error code; on error the
+ *    outputs are unspecified and hfqmc_last_error() describes the failure.
+ *  - Calls on one context are not thread safe; use one context per thread.
+ */
+#ifndef HFQMC_H
+#define HFQMC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  HFQMC_OK = 0,
+  HFQMC_EINVAL = -1,        /* bad argument (null pointer, size, parameter range) */
+  HFQMC_ENOMEM = -2,        /* device or host allocation failed */
+  HFQMC_EDEVICE = -3,       /* HIP runtime error or no usable gfx950 device */
+  HFQMC_ENUMERIC = -4,      /* NaN/Inf result or singular Dyson matrix */
+  HFQMC_EDRIFT = -5,        /* drift at a recompute exceeded opts.drift_limit */
+  HFQMC_EUNSUPPORTED = -6   /* option combination not implemented */
+};
+
+/* Opaque context: device, stream, device buffers and autotune cache. */
+typedef struct hfqmc_ctx hfqmc_ctx;
+
+/* Create a context on HIP device `device`.  EDEVICE if the device is absent
+ * or is not gfx950. */
+int hfqmc_create(hfqmc_ctx **out, int device);
+void hfqmc_destroy(hfqmc_ctx *ctx);
+/* Launch all device work on `stream` (a hipStream_t; NULL = the null
+ * stream).  The stream must outlive its use by the context. */
+int hfqmc_set_stream(hfqmc_ctx *ctx, void *stream);
+/* Message for the last nonzero return on the calling thread. */
+const char *hfqmc_last_error(void);
+
+/* Update scheme of the Metropolis sweep. */
+enum {
+  HFQMC_MODE_RANK1 = 0,        /* FP64 Sherman-Morrison rank-1 update per accepted flip */
+  HFQMC_MODE_DELAYED_FP64 = 1, /* delayed rank-k updates, FP64 flush */
+  HFQMC_MODE_MIXED = 2         /* delayed rank-k updates, flush as FP32 MFMA GEMM with
+                                  FP32 accumulation; ratios, acceptance and the LU
+                                  recompute stay FP64 */
+};
+
+typedef struct {
+  int32_t n_chains;         /* independent chains per grid; chain c uses Philox key (seed + c, grid) */
+  int32_t mode;             /* HFQMC_MODE_* */
+  int64_t warmup;           /* unmeasured sweeps per chain */
+  int64_t sweeps;           /* measured sweeps per chain (>= 1) */
+  int32_t recompute_every;  /* accepted flips between FP64 Dyson recomputes;
+                               0 -> 100 (rank-1) or 4*k (delayed) */
+  int32_t delay_k;          /* delayed modes: max pending flips k (2..64); 0 -> autotune */
+  int32_t n_bins;           /* measurement bins per chain; 0 -> 20 if n_chains == 1 else 1 */
+  int32_t reserved;
+  double drift_limit;       /* 0: report only; > 0: HFQMC_EDRIFT if any recompute drift exceeds it */
+  /* Optional test hooks (NULL to disable).  Flip codes are sweep * L + l. */
+  int64_t *flip_log;        /* [n_grids][n_chains][flip_cap] accepted flips, in order */
+  int64_t *flip_count;      /* [n_grids][n_chains] number of accepted flips (may exceed flip_cap) */
+  int64_t flip_cap;
+  const int64_t *replay_log;   /* [n_grids][n_chains][replay_cap]: accept exactly these flips */
+  const int64_t *replay_count; /* [n_grids][n_chains] */
+  int64_t replay_cap;
+  double *chain_g;          /* [n_grids][n_chains][n_bins][L_i+1] per-bin sums of G(tau_k) */
+  double *chain_d;          /* [n_grids][n_chains][n_bins] per-bin sums of D */
+  int64_t *chain_n;         /* [n_grids][n_chains][n_bins] measurements per bin */
+  double *chain_drift;      /* [n_grids][n_chains] max elementwise drift at recomputes */
+  double *final_green;      /* single grid only: [n_chains][2][L][L] G_up, G_dn after the last sweep */
+} hfqmc_opts;
+
+typedef struct {
+  double acc_rate;          /* accepted / proposed */
+  double max_drift;         /* max elementwise |G_updated - G_recomputed| over recomputes */
+  double seconds_total;     /* wall time of the call */
+  double seconds_kernel;    /* HIP-event time of the persistent sweep kernel */
+  int64_t n_proposed, n_accepted, n_recomputes, n_bad_ratio, n_singular;
+  int32_t delay_k;          /* k actually used (delayed modes) */
+  int32_t recompute_every;  /* recompute interval actually used */
+  int32_t n_workgroups;     /* persistent workgroups launched */
+  int32_t reserved;
+} hfqmc_stats;
+
+/* Fixed-dtau solve: hfqmc_solve(G0(tau), U, beta, dtau, sweeps, seed) -> G(tau).
+ * Hirsch-Fye QMC for the half-filled single-band Anderson impurity with bath
+ * g0_tau[k] = G0(k dtau), k = 0..L-1, interaction U >= 0, inverse temperature
+ * beta, L = beta/dtau slices (|beta/dtau - L| <= 1e-9 L), HS coupling
+ * cosh(lambda) = exp(dtau U/2).  Outputs (host): g_tau[L+1] on tau_k = k dtau,
+ * k = 0..L (tau_L = beta-); g_err[L+1] (or NULL) standard error over chains
+ * (or bins); docc[2] (or NULL) double occupancy and its error; stats (or NULL). */
+int hfqmc_solve(hfqmc_ctx *ctx, const double *g0_tau, int32_t L, double U, double beta,
+                double dtau, uint64_t seed, const hfqmc_opts *opts,
+                double *g_tau, double *g_err, double *docc, hfqmc_stats *stats);
+
+/* Batched solve of several grids in ONE persistent launch (the data-parallel
+ * core of a multigrid step): grid i has L[i] slices, bath g0_tau (concatenated,
+ * sum L[i] values), dtau_i = beta / L[i], Philox grid key i.  opts.n_chains
+ * chains per grid.  Outputs are concatenated per grid: g_tau and g_err hold
+ * sum (L[i]+1) values; docc holds 2 per grid; stats holds n_grids entries
+ * (may be NULL). */
+int hfqmc_solve_grids(hfqmc_ctx *ctx, int32_t n_grids, const int32_t *L, const double *g0_tau,
+                      double U, double beta, uint64_t seed, const hfqmc_opts *opts,
+                      double *g_tau, double *g_err, double *docc, hfqmc_stats *stats);
+
+/* Multigrid solve: multigrid_solve(list of dtau) -> G(tau) extrapolated to dtau -> 0.
+ * bath_iw[2 n_iw]: bath on the Matsubara axis with high-frequency moment
+ * bath_m3 (bath ~ 1/(i w) + m3/(i w)^3, particle-hole symmetric).  For each
+ * dtau_i (n_grids >= 3) L_i = round(beta/dtau_i); all grids and chains run
+ * in one persistent launch; each grid estimate is interpolated onto
+ * tau_j = j beta/(n_fine-1), j = 0..n_fine-1, with the reference model
+ * G_ref = 1/(1/bath - U^2/(4 i w)) and a natural cubic spline of G - G_ref,
+ * then fitted per tau_j by weighted least squares c0 + c1 dtau^2 + c2 dtau^4.
+ * Outputs: g_fine[n_fine], g_fine_err[n_fine] (or NULL); g_grids (or NULL)
+ * concatenated raw grid estimates, sum (L_i+1) values; per_grid[n_grids]
+ * stats (or NULL). */
+int multigrid_solve(hfqmc_ctx *ctx, const double *bath_iw, int32_t n_iw, double bath_m3,
+                    double U, double beta, const double *dtaus, int32_t n_grids, uint64_t seed,
+                    const hfqmc_opts *opts, int32_t n_fine, double *g_fine, double *g_fine_err,
+                    double *g_grids, hfqmc_stats *per_grid);
+
+/* One Bethe-lattice DMFT self-consistency step (host only, no device):
+ * G(i w) = G_ref(i w) - int_0^beta e^{i w tau} S(tau) d tau, S the natural
+ * cubic spline of g_fine - G_ref on tau_j = j beta/(n_fine-1); then
+ * bath_new(i w) = 1/(i w - t^2 G(i w)) on the same n_iw frequencies.
+ * G_ref is built from bath_iw_prev (moment bath_m3) and U. */
+int dmft_bethe_step(const double *g_fine, int32_t n_fine, const double *bath_iw_prev,
+                    int32_t n_iw, double bath_m3, double U, double beta, double t,
+                    double *bath_iw_new);
+
+/* U = 0 starting bath: Bethe-lattice local Green function, half-bandwidth 2t. */
+int bethe_semicircle_bath(double beta, double t, int32_t n_iw, double *bath_iw);
+
+/* Bath on a Trotter grid: g_tau[k] = G(k beta/L), k = 0..L-1, by the
+ * Matsubara sum with the 1/(i w) + m3/(i w)^3 tail handled in closed form. */
+int bath_to_tau(const double *bath_iw, int32_t n_iw, double m3, double beta, int32_t L,
+                double *g_tau);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HFQMC_H */

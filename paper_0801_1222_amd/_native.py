@@ -1,0 +1,99 @@
+"""ctypes binding of libhfqmc.so (argument marshalling only).
+
+Every computation happens in the native library; this module only converts
+NumPy arrays to pointers and back.  Importing it fails loudly when the
+library has not been built.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libhfqmc.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        "libhfqmc.so is not built; run `python -m paper_0801_1222_amd.build` "
+        "(the HIP library is required, there is no fallback)")
+
+lib = C.CDLL(LIB_PATH)
+
+_i32, _i64, _u64, _f64 = C.c_int32, C.c_int64, C.c_uint64, C.c_double
+_pd = C.POINTER(C.c_double)
+_pi64 = C.POINTER(C.c_int64)
+_pi32 = C.POINTER(C.c_int32)
+
+
+class Opts(C.Structure):
+    _fields_ = [
+        ("n_chains", _i32), ("mode", _i32),
+        ("warmup", _i64), ("sweeps", _i64),
+        ("recompute_every", _i32), ("delay_k", _i32), ("n_bins", _i32), ("reserved", _i32),
+        ("drift_limit", _f64),
+        ("flip_log", _pi64), ("flip_count", _pi64), ("flip_cap", _i64),
+        ("replay_log", _pi64), ("replay_count", _pi64), ("replay_cap", _i64),
+        ("chain_g", _pd), ("chain_d", _pd), ("chain_n", _pi64), ("chain_drift", _pd),
+        ("final_green", _pd),
+    ]
+
+
+class Stats(C.Structure):
+    _fields_ = [
+        ("acc_rate", _f64), ("max_drift", _f64), ("seconds_total", _f64), ("seconds_kernel", _f64),
+        ("n_proposed", _i64), ("n_accepted", _i64), ("n_recomputes", _i64),
+        ("n_bad_ratio", _i64), ("n_singular", _i64),
+        ("delay_k", _i32), ("recompute_every", _i32), ("n_workgroups", _i32), ("reserved", _i32),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+
+
+_ctx_p = C.c_void_p
+
+lib.hfqmc_create.argtypes = [C.POINTER(_ctx_p), C.c_int]
+lib.hfqmc_create.restype = C.c_int
+lib.hfqmc_destroy.argtypes = [_ctx_p]
+lib.hfqmc_destroy.restype = None
+lib.hfqmc_set_stream.argtypes = [_ctx_p, C.c_void_p]
+lib.hfqmc_set_stream.restype = C.c_int
+lib.hfqmc_last_error.argtypes = []
+lib.hfqmc_last_error.restype = C.c_char_p
+lib.hfqmc_solve.argtypes = [_ctx_p, _pd, _i32, _f64, _f64, _f64, _u64, C.POINTER(Opts),
+                            _pd, _pd, _pd, C.POINTER(Stats)]
+lib.hfqmc_solve.restype = C.c_int
+lib.hfqmc_solve_grids.argtypes = [_ctx_p, _i32, _pi32, _pd, _f64, _f64, _u64, C.POINTER(Opts),
+                                  _pd, _pd, _pd, C.POINTER(Stats)]
+lib.hfqmc_solve_grids.restype = C.c_int
+lib.multigrid_solve.argtypes = [_ctx_p, _pd, _i32, _f64, _f64, _f64, _pd, _i32, _u64,
+                                C.POINTER(Opts), _i32, _pd, _pd, _pd, C.POINTER(Stats)]
+lib.multigrid_solve.restype = C.c_int
+lib.dmft_bethe_step.argtypes = [_pd, _i32, _pd, _i32, _f64, _f64, _f64, _f64, _pd]
+lib.dmft_bethe_step.restype = C.c_int
+lib.bethe_semicircle_bath.argtypes = [_f64, _f64, _i32, _pd]
+lib.bethe_semicircle_bath.restype = C.c_int
+lib.bath_to_tau.argtypes = [_pd, _i32, _f64, _f64, _i32, _pd]
+lib.bath_to_tau.restype = C.c_int
+
+EXPORTED = ["hfqmc_create", "hfqmc_destroy", "hfqmc_set_stream", "hfqmc_last_error",
+            "hfqmc_solve", "hfqmc_solve_grids", "multigrid_solve", "dmft_bethe_step",
+            "bethe_semicircle_bath", "bath_to_tau"]
+
+
+def ptr(a, ctype=C.c_double):
+    if a is None:
+        return None
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def check(rc, what):
+    if rc != 0:
+        msg = lib.hfqmc_last_error().decode(errors="replace")
+        raise HFQMCError(rc, "%s failed (%d): %s" % (what, rc, msg))
+
+
+class HFQMCError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(msg)
+        self.code = code

@@ -1,0 +1,235 @@
+"""Python face of libhfqmc with the C-ABI's names (marshalling only).
+
+  ctx = Context(0)
+  out = hfqmc_solve(ctx, g0_tau, U, beta, dtau, seed, n_chains=..., ...)
+  out = hfqmc_solve_grids(ctx, Ls, [g0_tau_i], U, beta, seed, ...)
+  out = multigrid_solve(ctx, bath_iw, m3, U, beta, dtaus, seed, n_fine, ...)
+  new_bath = dmft_bethe_step(g_fine, bath_iw, m3, U, beta, t)
+"""
+import ctypes as C
+
+import numpy as np
+
+from . import _native as N
+from ._native import HFQMCError  # noqa: F401
+
+MODES = {"rank1": 0, "delayed": 1, "mixed": 2}
+
+
+class Context:
+    """Owns one hfqmc_ctx (device buffers, stream binding)."""
+
+    def __init__(self, device=0):
+        self._p = C.c_void_p()
+        N.check(N.lib.hfqmc_create(C.byref(self._p), int(device)), "hfqmc_create")
+
+    def set_stream(self, stream):
+        """Bind a HIP stream: a torch.cuda.Stream, a raw handle (int) or None."""
+        handle = getattr(stream, "cuda_stream", stream)
+        N.check(N.lib.hfqmc_set_stream(self._p, C.c_void_p(handle or 0)), "hfqmc_set_stream")
+
+    @property
+    def handle(self):
+        return self._p
+
+    def close(self):
+        if self._p:
+            N.lib.hfqmc_destroy(self._p)
+            self._p = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drift_limit):
+    o = N.Opts()
+    o.n_chains = int(n_chains)
+    o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
+    o.warmup = int(warmup)
+    o.sweeps = int(sweeps)
+    o.recompute_every = int(recompute_every)
+    o.delay_k = int(delay_k)
+    o.n_bins = int(n_bins)
+    o.drift_limit = float(drift_limit)
+    return o
+
+
+class _Hooks:
+    """Host buffers of the optional test hooks, kept alive for the call."""
+
+    def __init__(self, o, n_grids, n_chains, Ls, n_bins, flip_cap, replay, want_chain, want_green):
+        self.keep = []
+        self.n_grids, self.n_chains, self.Ls = n_grids, n_chains, list(Ls)
+        nb = n_bins if n_bins > 0 else (20 if n_chains == 1 else 1)
+        self.n_bins = nb
+        self.flip_log = self.flip_count = None
+        if flip_cap:
+            self.flip_log = np.zeros((n_grids, n_chains, flip_cap), dtype=np.int64)
+            self.flip_count = np.zeros((n_grids, n_chains), dtype=np.int64)
+            o.flip_log = N.ptr(self.flip_log, C.c_int64)
+            o.flip_count = N.ptr(self.flip_count, C.c_int64)
+            o.flip_cap = int(flip_cap)
+        if replay is not None:
+            # replay: nested lists [grid][chain] -> sequence of flip codes sweep*L + l
+            cap = max(1, max(len(c) for g in replay for c in g))
+            rl = np.zeros((n_grids, n_chains, cap), dtype=np.int64)
+            rc = np.zeros((n_grids, n_chains), dtype=np.int64)
+            for gi, g in enumerate(replay):
+                for ci, c in enumerate(g):
+                    rl[gi, ci, :len(c)] = c
+                    rc[gi, ci] = len(c)
+            self.keep += [rl, rc]
+            o.replay_log = N.ptr(rl, C.c_int64)
+            o.replay_count = N.ptr(rc, C.c_int64)
+            o.replay_cap = cap
+        self.chain_g = self.chain_d = self.chain_n = self.chain_drift = None
+        if want_chain:
+            tot = sum(L + 1 for L in Ls)
+            self.chain_g = np.zeros(n_chains * nb * tot)
+            self.chain_d = np.zeros((n_grids, n_chains, nb))
+            self.chain_n = np.zeros((n_grids, n_chains, nb), dtype=np.int64)
+            self.chain_drift = np.zeros((n_grids, n_chains))
+            o.chain_g = N.ptr(self.chain_g)
+            o.chain_d = N.ptr(self.chain_d)
+            o.chain_n = N.ptr(self.chain_n, C.c_int64)
+            o.chain_drift = N.ptr(self.chain_drift)
+        self.green = None
+        if want_green:
+            L = Ls[0]
+            self.green = np.zeros((n_chains, 2, L, L))
+            o.final_green = N.ptr(self.green)
+
+    def results(self):
+        out = {}
+        if self.flip_log is not None:
+            out["flips"] = [[self.flip_log[g, c, :min(self.flip_count[g, c], self.flip_log.shape[2])].copy()
+                             for c in range(self.n_chains)] for g in range(self.n_grids)]
+            out["flip_count"] = self.flip_count.copy()
+        if self.chain_g is not None:
+            per = []
+            off = 0
+            for L in self.Ls:
+                n = self.n_chains * self.n_bins * (L + 1)
+                per.append(self.chain_g[off:off + n].reshape(self.n_chains, self.n_bins, L + 1).copy())
+                off += n
+            out["chain_g"] = per
+            out["chain_d"] = self.chain_d.copy()
+            out["chain_n"] = self.chain_n.copy()
+            out["chain_drift"] = self.chain_drift.copy()
+        if self.green is not None:
+            out["green"] = self.green
+        return out
+
+
+def hfqmc_solve(ctx, g0_tau, U, beta, dtau, seed, n_chains=1, warmup=0, sweeps=1,
+                mode="rank1", recompute_every=0, delay_k=0, n_bins=0, drift_limit=0.0,
+                flip_cap=0, replay=None, want_chain=False, want_green=False):
+    """Fixed-dtau solve; returns dict(g, g_err, D, D_err, stats, [hooks])."""
+    g0 = np.ascontiguousarray(g0_tau, dtype=np.float64)
+    L = g0.shape[0]
+    o = _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drift_limit)
+    hk = _Hooks(o, 1, n_chains, [L], n_bins, flip_cap,
+                [replay] if replay is not None else None, want_chain, want_green)
+    g = np.zeros(L + 1)
+    ge = np.zeros(L + 1)
+    d = np.zeros(2)
+    st = N.Stats()
+    rc = N.lib.hfqmc_solve(ctx.handle, N.ptr(g0), L, float(U), float(beta), float(dtau),
+                           int(seed), C.byref(o), N.ptr(g), N.ptr(ge), N.ptr(d), C.byref(st))
+    N.check(rc, "hfqmc_solve")
+    out = dict(g=g, g_err=ge, D=d[0], D_err=d[1], stats=st.as_dict())
+    r = hk.results()
+    for k in ("flips", "chain_g"):
+        if k in r:
+            r[k] = r[k][0]
+    for k in ("flip_count", "chain_d", "chain_n", "chain_drift"):
+        if k in r:
+            r[k] = r[k][0]
+    out.update(r)
+    return out
+
+
+def hfqmc_solve_grids(ctx, Ls, g0_taus, U, beta, seed, n_chains=1, warmup=0, sweeps=1,
+                      mode="rank1", recompute_every=0, delay_k=0, n_bins=0, drift_limit=0.0,
+                      flip_cap=0, replay=None, want_chain=False):
+    """Several grids in one persistent launch; per-grid lists in the result."""
+    Ls = [int(L) for L in Ls]
+    n = len(Ls)
+    Larr = np.array(Ls, dtype=np.int32)
+    g0 = np.ascontiguousarray(np.concatenate([np.asarray(x, dtype=np.float64) for x in g0_taus]))
+    assert g0.shape[0] == sum(Ls)
+    o = _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drift_limit)
+    hk = _Hooks(o, n, n_chains, Ls, n_bins, flip_cap, replay, want_chain, False)
+    P = sum(L + 1 for L in Ls)
+    g = np.zeros(P)
+    ge = np.zeros(P)
+    d = np.zeros(2 * n)
+    st = (N.Stats * n)()
+    rc = N.lib.hfqmc_solve_grids(ctx.handle, n, N.ptr(Larr, C.c_int32), N.ptr(g0), float(U),
+                                 float(beta), int(seed), C.byref(o), N.ptr(g), N.ptr(ge),
+                                 N.ptr(d), st)
+    N.check(rc, "hfqmc_solve_grids")
+    gs, es, off = [], [], 0
+    for L in Ls:
+        gs.append(g[off:off + L + 1].copy())
+        es.append(ge[off:off + L + 1].copy())
+        off += L + 1
+    out = dict(g=gs, g_err=es, D=d[0::2].copy(), D_err=d[1::2].copy(),
+               stats=[st[i].as_dict() for i in range(n)])
+    out.update(hk.results())
+    return out
+
+
+def multigrid_solve(ctx, bath_iw, bath_m3, U, beta, dtaus, seed, n_fine=200, n_chains=1,
+                    warmup=0, sweeps=1, mode="rank1", recompute_every=0, delay_k=0, n_bins=0,
+                    drift_limit=0.0):
+    """dtau -> 0 extrapolated G(tau_j), tau_j = j beta/(n_fine-1)."""
+    b = np.ascontiguousarray(np.asarray(bath_iw, dtype=np.complex128)).view(np.float64)
+    n_iw = b.shape[0] // 2
+    dt = np.ascontiguousarray(dtaus, dtype=np.float64)
+    o = _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drift_limit)
+    Ls = [int(round(beta / x)) for x in dt]
+    gf = np.zeros(n_fine)
+    ef = np.zeros(n_fine)
+    gg = np.zeros(sum(L + 1 for L in Ls))
+    st = (N.Stats * len(Ls))()
+    rc = N.lib.multigrid_solve(ctx.handle, N.ptr(b), n_iw, float(bath_m3), float(U), float(beta),
+                               N.ptr(dt), len(Ls), int(seed), C.byref(o), int(n_fine), N.ptr(gf),
+                               N.ptr(ef), N.ptr(gg), st)
+    N.check(rc, "multigrid_solve")
+    grids, off = [], 0
+    for L in Ls:
+        grids.append(gg[off:off + L + 1].copy())
+        off += L + 1
+    return dict(g=gf, g_err=ef, tau=np.arange(n_fine) * (beta / (n_fine - 1)), Ls=Ls,
+                g_grids=grids, stats=[st[i].as_dict() for i in range(len(Ls))])
+
+
+def dmft_bethe_step(g_fine, bath_iw_prev, bath_m3, U, beta, t):
+    """New bath 1/(i w - t^2 G(i w)) on the frequencies of bath_iw_prev."""
+    g = np.ascontiguousarray(g_fine, dtype=np.float64)
+    b = np.ascontiguousarray(np.asarray(bath_iw_prev, dtype=np.complex128)).view(np.float64)
+    n_iw = b.shape[0] // 2
+    out = np.zeros(2 * n_iw)
+    rc = N.lib.dmft_bethe_step(N.ptr(g), g.shape[0], N.ptr(b), n_iw, float(bath_m3), float(U),
+                               float(beta), float(t), N.ptr(out))
+    N.check(rc, "dmft_bethe_step")
+    return out.view(np.complex128)
+
+
+def bethe_semicircle_bath(beta, t, n_iw):
+    out = np.zeros(2 * int(n_iw))
+    N.check(N.lib.bethe_semicircle_bath(float(beta), float(t), int(n_iw), N.ptr(out)),
+            "bethe_semicircle_bath")
+    return out.view(np.complex128)
+
+
+def bath_to_tau(bath_iw, m3, beta, L):
+    b = np.ascontiguousarray(np.asarray(bath_iw, dtype=np.complex128)).view(np.float64)
+    out = np.zeros(int(L))
+    N.check(N.lib.bath_to_tau(N.ptr(b), b.shape[0] // 2, float(m3), float(beta), int(L), N.ptr(out)),
+            "bath_to_tau")
+    return out

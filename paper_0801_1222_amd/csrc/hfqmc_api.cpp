@@ -1,0 +1,526 @@
+// C-ABI of libhfqmc: argument checking, device memory, launch orchestration.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "hfqmc.h"
+#include "hfqmc_host.h"
+#include "hfqmc_internal.h"
+
+using namespace hfqmc;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHK(x)                                                                      \
+  do {                                                                                 \
+    hipError_t e_ = (x);                                                               \
+    if (e_ != hipSuccess) return fail(HFQMC_EDEVICE, "%s: %s", #x, hipGetErrorString(e_)); \
+  } while (0)
+
+// Grow-only device buffer.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  int ensure(size_t need) {
+    if (need <= bytes) return HFQMC_OK;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+    hipError_t e = hipMalloc(&p, need);
+    if (e != hipSuccess) {
+      p = nullptr;
+      return fail(HFQMC_ENOMEM, "hipMalloc(%zu bytes): %s", need, hipGetErrorString(e));
+    }
+    bytes = need;
+    return HFQMC_OK;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+};
+
+// Bump allocator over a byte count (first pass sizes, second pass assigns).
+struct Bump {
+  char* base;
+  size_t off = 0;
+  explicit Bump(void* b) : base((char*)b) {}
+  template <typename T>
+  T* take(size_t n) {
+    off = (off + 255) & ~(size_t)255;
+    T* r = base ? (T*)(base + off) : nullptr;
+    off += n * sizeof(T);
+    return r;
+  }
+};
+
+}  // namespace
+
+struct hfqmc_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int n_cu = 0;
+  int lds_max = 0;  // bytes of LDS a workgroup may allocate
+  DevBuf work;
+  DevBuf arena;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+extern "C" const char* hfqmc_last_error(void) { return g_err.c_str(); }
+
+extern "C" int hfqmc_create(hfqmc_ctx** out, int device) {
+  if (!out) return fail(HFQMC_EINVAL, "hfqmc_create: out is NULL");
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n <= 0)
+    return fail(HFQMC_EDEVICE, "hfqmc_create: no HIP device");
+  if (device < 0 || device >= n) return fail(HFQMC_EINVAL, "hfqmc_create: device %d of %d", device, n);
+  hipDeviceProp_t prop;
+  HIPCHK(hipGetDeviceProperties(&prop, device));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(HFQMC_EDEVICE, "hfqmc_create: device %d is %s, this library is built for gfx950",
+                device, prop.gcnArchName);
+  HIPCHK(hipSetDevice(device));
+  hfqmc_ctx* c = new hfqmc_ctx;
+  c->device = device;
+  c->n_cu = prop.multiProcessorCount;
+  c->lds_max = (int)prop.sharedMemPerBlock;
+  if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+    delete c;
+    return fail(HFQMC_EDEVICE, "hfqmc_create: hipEventCreate failed");
+  }
+  *out = c;
+  return HFQMC_OK;
+}
+
+extern "C" void hfqmc_destroy(hfqmc_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  c->work.release();
+  c->arena.release();
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
+  delete c;
+}
+
+extern "C" int hfqmc_set_stream(hfqmc_ctx* c, void* stream) {
+  if (!c) return fail(HFQMC_EINVAL, "hfqmc_set_stream: ctx is NULL");
+  c->stream = (hipStream_t)stream;
+  return HFQMC_OK;
+}
+
+namespace {
+
+struct Resolved {
+  int n_chains, mode, n_rec, delay_k, window_b, n_bins;
+  long long warmup, sweeps;
+};
+
+int resolve_opts(const hfqmc_opts* o, Resolved* r) {
+  if (!o) return fail(HFQMC_EINVAL, "opts is NULL");
+  if (o->n_chains < 1 || o->n_chains >= (1 << 20)) return fail(HFQMC_EINVAL, "n_chains=%d", o->n_chains);
+  if (o->sweeps < 1 || o->warmup < 0) return fail(HFQMC_EINVAL, "warmup=%lld sweeps=%lld",
+                                                  (long long)o->warmup, (long long)o->sweeps);
+  if (o->mode < 0 || o->mode > 2) return fail(HFQMC_EINVAL, "mode=%d", o->mode);
+  if (o->recompute_every < 0) return fail(HFQMC_EINVAL, "recompute_every=%d", o->recompute_every);
+  if (o->n_bins < 0) return fail(HFQMC_EINVAL, "n_bins=%d", o->n_bins);
+  if (o->drift_limit < 0) return fail(HFQMC_EINVAL, "drift_limit < 0");
+  if (o->flip_log && (!o->flip_count || o->flip_cap < 1)) return fail(HFQMC_EINVAL, "flip_log needs flip_count and flip_cap >= 1");
+  if (o->replay_log && (!o->replay_count || o->replay_cap < 1)) return fail(HFQMC_EINVAL, "replay_log needs replay_count and replay_cap >= 1");
+  r->n_chains = o->n_chains;
+  r->mode = o->mode;
+  r->warmup = o->warmup;
+  r->sweeps = o->sweeps;
+  if (o->mode == MODE_RANK1) {
+    r->delay_k = 1;
+    r->window_b = 1;
+  } else {
+    int k = o->delay_k == 0 ? 32 : o->delay_k;
+    if (k < 2 || k > kMaxK) return fail(HFQMC_EINVAL, "delay_k=%d (2..%d)", k, kMaxK);
+    r->delay_k = k;
+    r->window_b = 64;
+  }
+  r->n_rec = o->recompute_every > 0 ? o->recompute_every
+                                    : (o->mode == MODE_RANK1 ? 100 : 4 * r->delay_k);
+  r->n_bins = o->n_bins > 0 ? o->n_bins : (o->n_chains == 1 ? 20 : 1);
+  if (r->n_bins > r->sweeps) return fail(HFQMC_EINVAL, "n_bins=%d > sweeps", r->n_bins);
+  if (r->mode != MODE_RANK1) return fail(HFQMC_EUNSUPPORTED, "delayed modes are not built yet");
+  return HFQMC_OK;
+}
+
+struct GridHost {
+  int L;
+  double lam;
+};
+
+// Shared implementation of hfqmc_solve / hfqmc_solve_grids / multigrid_solve.
+int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double* g0_tau, double U,
+                     double beta, uint64_t seed, const hfqmc_opts* opts, double* g_tau,
+                     double* g_err, double* docc, hfqmc_stats* stats) {
+  const auto t_start = std::chrono::steady_clock::now();
+  if (!c) return fail(HFQMC_EINVAL, "ctx is NULL");
+  if (!Ls || !g0_tau || !g_tau) return fail(HFQMC_EINVAL, "null input/output pointer");
+  if (n_grids < 1) return fail(HFQMC_EINVAL, "n_grids=%d", n_grids);
+  if (!(U >= 0.0) || !(beta > 0.0) || !std::isfinite(U) || !std::isfinite(beta))
+    return fail(HFQMC_EINVAL, "U=%g beta=%g", U, beta);
+  Resolved r;
+  int rc = resolve_opts(opts, &r);
+  if (rc) return rc;
+  int Lmax = 0;
+  long long Lsum = 0;
+  for (int i = 0; i < n_grids; ++i) {
+    if (Ls[i] < 2 || Ls[i] > 4096) return fail(HFQMC_EINVAL, "L[%d]=%d (2..4096)", i, Ls[i]);
+    Lmax = std::max(Lmax, (int)Ls[i]);
+    Lsum += Ls[i];
+  }
+  if (opts->final_green && n_grids != 1) return fail(HFQMC_EINVAL, "final_green needs a single grid");
+  for (long long q = 0; q < Lsum; ++q)
+    if (!std::isfinite(g0_tau[q])) return fail(HFQMC_EINVAL, "g0_tau[%lld] not finite", q);
+
+  HIPCHK(hipSetDevice(c->device));
+  hipStream_t st = c->stream;
+  const int nch = r.n_chains, nbin = r.n_bins;
+
+  // ---- device memory layout (two passes: size, then assign)
+  std::vector<GridDev> gd(n_grids);
+  int* d_units = nullptr;
+  int* d_queue = nullptr;
+  GridDev* d_grids = nullptr;
+  double* d_gtau = nullptr;
+  auto layout = [&](Bump& b) {
+    d_grids = b.take<GridDev>(n_grids);
+    d_units = b.take<int>((size_t)n_grids * nch);
+    d_queue = b.take<int>(64);
+    d_gtau = b.take<double>(Lsum);
+    for (int i = 0; i < n_grids; ++i) {
+      const int L = Ls[i];
+      GridDev& g = gd[i];
+      g.G0 = b.take<double>((size_t)L * L);
+      g.acc_g = b.take<double>((size_t)nch * nbin * (L + 1));
+      g.acc_d = b.take<double>((size_t)nch * nbin);
+      g.acc_n = b.take<long long>((size_t)nch * nbin);
+      g.cstats = b.take<long long>((size_t)nch * NSTAT);
+      g.cdrift = b.take<double>(nch);
+      g.flip_log = opts->flip_log ? b.take<long long>((size_t)nch * opts->flip_cap) : nullptr;
+      g.replay = opts->replay_log ? b.take<long long>((size_t)nch * opts->replay_cap) : nullptr;
+      g.replay_n = opts->replay_log ? b.take<long long>(nch) : nullptr;
+      g.g_final = opts->final_green ? b.take<double>((size_t)nch * 2 * L * L) : nullptr;
+      g.g_out = b.take<double>(L + 1);
+      g.g_err = b.take<double>(L + 1);
+      g.d_out = b.take<double>(2);
+    }
+  };
+  Bump sizing(nullptr);
+  layout(sizing);
+  rc = c->arena.ensure(sizing.off + 256);
+  if (rc) return rc;
+  Bump assign(c->arena.p);
+  layout(assign);
+
+  // ---- per-grid constants (transcendentals on the host)
+  std::vector<GridHost> gh(n_grids);
+  long long off = 0;
+  for (int i = 0; i < n_grids; ++i) {
+    const int L = Ls[i];
+    const double dtau = beta / L;
+    const double lam = std::acosh(std::exp(0.5 * dtau * U));
+    gh[i] = {L, lam};
+    GridDev& g = gd[i];
+    g.L = L;
+    g.n_chains = nch;
+    g.grid_id = i;
+    g.unit_base = i * nch;
+    g.gp = std::expm1(2.0 * lam);
+    g.gm = std::expm1(-2.0 * lam);
+    g.ep = std::expm1(lam);
+    g.em = std::expm1(-lam);
+    HIPCHK(hipMemcpyAsync(d_gtau + off, g0_tau + off, sizeof(double) * L, hipMemcpyHostToDevice, st));
+    HIPCHK(launch_build_g0(d_gtau + off, L, const_cast<double*>(g.G0), st));
+    HIPCHK(launch_zero(g.acc_g, (long long)nch * nbin * (L + 1), st));
+    HIPCHK(launch_zero(g.acc_d, (long long)nch * nbin, st));
+    HIPCHK(launch_zero_i64(g.acc_n, (long long)nch * nbin, st));
+    HIPCHK(launch_zero_i64(g.cstats, (long long)nch * NSTAT, st));
+    HIPCHK(launch_zero(g.cdrift, nch, st));
+    if (g.replay) {
+      HIPCHK(hipMemcpyAsync((void*)g.replay, opts->replay_log + (size_t)i * nch * opts->replay_cap,
+                            sizeof(long long) * nch * opts->replay_cap, hipMemcpyHostToDevice, st));
+      HIPCHK(hipMemcpyAsync((void*)g.replay_n, opts->replay_count + (size_t)i * nch,
+                            sizeof(long long) * nch, hipMemcpyHostToDevice, st));
+    }
+    off += L;
+  }
+  // ---- dispatch order: longest chains first (cost per sweep ~ L^3), then grid, chain
+  std::vector<int> units;
+  units.reserve((size_t)n_grids * nch);
+  std::vector<int> order(n_grids);
+  for (int i = 0; i < n_grids; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return Ls[a] > Ls[b]; });
+  for (int i : order)
+    for (int ch = 0; ch < nch; ++ch) units.push_back((i << 20) | ch);
+  HIPCHK(hipMemcpyAsync(d_units, units.data(), sizeof(int) * units.size(), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(d_grids, gd.data(), sizeof(GridDev) * n_grids, hipMemcpyHostToDevice, st));
+  HIPCHK(launch_zero_i32(d_queue, 64, st));
+
+  // ---- launch shape
+  int lu_nb = 0, scratch = 0;
+  const int lds = lds_bytes(Lmax, r.mode, r.delay_k, r.window_b, &lu_nb, &scratch);
+  if (lds + 1024 > c->lds_max)
+    return fail(HFQMC_EUNSUPPORTED, "L=%d needs %d bytes of LDS, device allows %d", Lmax, lds, c->lds_max);
+  // workgroups per CU: limited by LDS (160 KiB per CU) and by 2048 threads per CU
+  const int occ = std::max(1, std::min(c->lds_max / (lds + 1024), 2048 / kThreads));
+  const int n_units = (int)units.size();
+  int n_wg = std::min(n_units, c->n_cu * occ);
+  const long long wstride = workspace_doubles(Lmax, r.mode == MODE_RANK1 ? 1 : kMaxK);
+  rc = c->work.ensure((size_t)n_wg * wstride * sizeof(double));
+  if (rc) return rc;
+
+  SweepParams p;
+  std::memset(&p, 0, sizeof p);
+  p.grids = d_grids;
+  p.n_grids = n_grids;
+  p.units = d_units;
+  p.n_units = n_units;
+  p.queue = d_queue;
+  p.seed = seed;
+  p.warmup = r.warmup;
+  p.sweeps = r.sweeps;
+  p.n_rec = r.n_rec;
+  p.mode = r.mode;
+  p.delay_k = r.delay_k;
+  p.window_b = r.window_b;
+  p.n_bins = nbin;
+  p.lu_nb = lu_nb;
+  p.flip_cap = opts->flip_log ? opts->flip_cap : 0;
+  p.replay_cap = opts->replay_log ? opts->replay_cap : 0;
+  p.work = (double*)c->work.p;
+  p.work_stride = wstride;
+  p.Lmax = Lmax;
+  p.lds_scratch_bytes = scratch;
+
+  HIPCHK(hipEventRecord(c->ev0, st));
+  {
+    hipError_t e = launch_sweeps(p, n_wg, lds, st);
+    if (e != hipSuccess)
+      return fail(HFQMC_EDEVICE, "sweep kernel launch (%d workgroups, %d B LDS, device LDS %d B): %s",
+                  n_wg, lds, c->lds_max, hipGetErrorString(e));
+  }
+  HIPCHK(hipEventRecord(c->ev1, st));
+  HIPCHK(launch_reduce(d_grids, n_grids, nbin, st));
+
+  // ---- results back
+  std::vector<long long> cst((size_t)nch * NSTAT);
+  std::vector<double> cdr(nch);
+  long long goff = 0;
+  double max_drift = 0.0;
+  bool numeric_bad = false;
+  hfqmc_stats tot;
+  std::memset(&tot, 0, sizeof tot);
+  for (int i = 0; i < n_grids; ++i) {
+    const int L = Ls[i];
+    const GridDev& g = gd[i];
+    HIPCHK(hipMemcpyAsync(g_tau + goff, g.g_out, sizeof(double) * (L + 1), hipMemcpyDeviceToHost, st));
+    if (g_err) HIPCHK(hipMemcpyAsync(g_err + goff, g.g_err, sizeof(double) * (L + 1), hipMemcpyDeviceToHost, st));
+    if (docc) HIPCHK(hipMemcpyAsync(docc + 2 * i, g.d_out, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(cst.data(), g.cstats, sizeof(long long) * cst.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(cdr.data(), g.cdrift, sizeof(double) * nch, hipMemcpyDeviceToHost, st));
+    const size_t cb = (size_t)i * nch;
+    if (opts->flip_log) {
+      HIPCHK(hipMemcpyAsync(opts->flip_log + cb * opts->flip_cap, g.flip_log,
+                            sizeof(long long) * nch * opts->flip_cap, hipMemcpyDeviceToHost, st));
+    }
+    if (opts->chain_g)
+      HIPCHK(hipMemcpyAsync(opts->chain_g + (size_t)nch * nbin * (goff), g.acc_g,
+                            sizeof(double) * nch * nbin * (L + 1), hipMemcpyDeviceToHost, st));
+    if (opts->chain_d)
+      HIPCHK(hipMemcpyAsync(opts->chain_d + cb * nbin, g.acc_d, sizeof(double) * nch * nbin, hipMemcpyDeviceToHost, st));
+    if (opts->chain_n)
+      HIPCHK(hipMemcpyAsync((long long*)opts->chain_n + cb * nbin, g.acc_n, sizeof(long long) * nch * nbin, hipMemcpyDeviceToHost, st));
+    if (opts->final_green)
+      HIPCHK(hipMemcpyAsync(opts->final_green, g.g_final, sizeof(double) * nch * 2 * L * L, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    hfqmc_stats gs;
+    std::memset(&gs, 0, sizeof gs);
+    double gdrift = 0.0;
+    for (int ch = 0; ch < nch; ++ch) {
+      const long long* s = &cst[(size_t)ch * NSTAT];
+      gs.n_proposed += s[ST_PROPOSED];
+      gs.n_accepted += s[ST_ACCEPTED];
+      gs.n_recomputes += s[ST_RECOMPUTES];
+      gs.n_bad_ratio += s[ST_BAD];
+      gs.n_singular += s[ST_SINGULAR];
+      gdrift = std::max(gdrift, cdr[ch]);
+      if (!(cdr[ch] == cdr[ch])) gdrift = INFINITY;
+      if (opts->flip_count) opts->flip_count[cb + ch] = s[ST_FLIPS];
+      if (opts->chain_drift) opts->chain_drift[cb + ch] = cdr[ch];
+    }
+    gs.max_drift = gdrift;
+    gs.acc_rate = gs.n_proposed ? (double)gs.n_accepted / gs.n_proposed : 0.0;
+    gs.delay_k = r.delay_k;
+    gs.recompute_every = r.n_rec;
+    gs.n_workgroups = n_wg;
+    if (stats && n_grids > 1) stats[i] = gs;
+    tot.n_proposed += gs.n_proposed;
+    tot.n_accepted += gs.n_accepted;
+    tot.n_recomputes += gs.n_recomputes;
+    tot.n_bad_ratio += gs.n_bad_ratio;
+    tot.n_singular += gs.n_singular;
+    max_drift = std::max(max_drift, gdrift);
+    for (int k = 0; k <= L; ++k)
+      if (!std::isfinite(g_tau[goff + k])) numeric_bad = true;
+    goff += L + 1;
+  }
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+  const double wall =
+      std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  tot.max_drift = max_drift;
+  tot.acc_rate = tot.n_proposed ? (double)tot.n_accepted / tot.n_proposed : 0.0;
+  tot.seconds_kernel = ms * 1e-3;
+  tot.seconds_total = wall;
+  tot.delay_k = r.delay_k;
+  tot.recompute_every = r.n_rec;
+  tot.n_workgroups = n_wg;
+  if (stats) {
+    if (n_grids == 1) {
+      stats[0] = tot;
+    } else {
+      for (int i = 0; i < n_grids; ++i) {
+        stats[i].seconds_kernel = tot.seconds_kernel;
+        stats[i].seconds_total = wall;
+      }
+    }
+  }
+  if (tot.n_singular) return fail(HFQMC_ENUMERIC, "singular Dyson matrix in %lld recomputes", (long long)tot.n_singular);
+  if (numeric_bad || !(max_drift < INFINITY)) return fail(HFQMC_ENUMERIC, "non-finite Green function");
+  if (opts->drift_limit > 0 && max_drift > opts->drift_limit)
+    return fail(HFQMC_EDRIFT, "recompute drift %.3e exceeds limit %.3e", max_drift, opts->drift_limit);
+  return HFQMC_OK;
+}
+
+}  // namespace
+
+extern "C" int hfqmc_solve(hfqmc_ctx* c, const double* g0_tau, int32_t L, double U, double beta,
+                           double dtau, uint64_t seed, const hfqmc_opts* opts, double* g_tau,
+                           double* g_err, double* docc, hfqmc_stats* stats) {
+  if (!(dtau > 0.0) || !(beta > 0.0)) return fail(HFQMC_EINVAL, "dtau=%g beta=%g", dtau, beta);
+  if (std::fabs(beta / dtau - L) > 1e-9 * L) return fail(HFQMC_EINVAL, "beta/dtau=%.12g != L=%d", beta / dtau, L);
+  const int32_t Ls[1] = {L};
+  return solve_grids_impl(c, 1, Ls, g0_tau, U, beta, seed, opts, g_tau, g_err, docc, stats);
+}
+
+extern "C" int hfqmc_solve_grids(hfqmc_ctx* c, int32_t n_grids, const int32_t* L,
+                                 const double* g0_tau, double U, double beta, uint64_t seed,
+                                 const hfqmc_opts* opts, double* g_tau, double* g_err,
+                                 double* docc, hfqmc_stats* stats) {
+  return solve_grids_impl(c, n_grids, L, g0_tau, U, beta, seed, opts, g_tau, g_err, docc, stats);
+}
+
+extern "C" int bethe_semicircle_bath(double beta, double t, int32_t n_iw, double* bath_iw) {
+  if (!bath_iw || !(beta > 0) || !(t > 0) || n_iw < 1) return fail(HFQMC_EINVAL, "bethe_semicircle_bath: bad argument");
+  host::semicircle(beta, t, n_iw, bath_iw);
+  return HFQMC_OK;
+}
+
+extern "C" int bath_to_tau(const double* bath_iw, int32_t n_iw, double m3, double beta, int32_t L,
+                           double* g_tau) {
+  if (!bath_iw || !g_tau || n_iw < 16 || L < 2 || !(beta > 0)) return fail(HFQMC_EINVAL, "bath_to_tau: bad argument");
+  std::vector<double> tau(L);
+  for (int k = 0; k < L; ++k) tau[k] = k * (beta / L);
+  host::iw_to_tau(bath_iw, n_iw, m3, beta, tau.data(), L, g_tau);
+  return HFQMC_OK;
+}
+
+extern "C" int multigrid_solve(hfqmc_ctx* c, const double* bath_iw, int32_t n_iw, double bath_m3,
+                               double U, double beta, const double* dtaus, int32_t n_grids,
+                               uint64_t seed, const hfqmc_opts* opts, int32_t n_fine,
+                               double* g_fine, double* g_fine_err, double* g_grids,
+                               hfqmc_stats* per_grid) {
+  if (!bath_iw || !dtaus || !g_fine) return fail(HFQMC_EINVAL, "multigrid_solve: null pointer");
+  if (n_grids < 3) return fail(HFQMC_EINVAL, "multigrid_solve: n_grids=%d < 3", n_grids);
+  if (n_fine < 4) return fail(HFQMC_EINVAL, "multigrid_solve: n_fine=%d < 4", n_fine);
+  if (n_iw < 16) return fail(HFQMC_EINVAL, "multigrid_solve: n_iw=%d < 16", n_iw);
+  if (!(beta > 0) || !(U >= 0)) return fail(HFQMC_EINVAL, "multigrid_solve: U=%g beta=%g", U, beta);
+  std::vector<int32_t> Ls(n_grids);
+  std::vector<double> dts(n_grids);
+  long long Lsum = 0, Psum = 0;
+  for (int i = 0; i < n_grids; ++i) {
+    if (!(dtaus[i] > 0)) return fail(HFQMC_EINVAL, "dtau[%d]=%g", i, dtaus[i]);
+    Ls[i] = (int32_t)std::lround(beta / dtaus[i]);
+    dts[i] = beta / Ls[i];
+    Lsum += Ls[i];
+    Psum += Ls[i] + 1;
+  }
+  std::vector<double> g0(Lsum), gg(Psum), ge(Psum);
+  long long off = 0;
+  for (int i = 0; i < n_grids; ++i) {
+    int rc = bath_to_tau(bath_iw, n_iw, bath_m3, beta, Ls[i], g0.data() + off);
+    if (rc) return rc;
+    off += Ls[i];
+  }
+  int rc = solve_grids_impl(c, n_grids, Ls.data(), g0.data(), U, beta, seed, opts, gg.data(),
+                            ge.data(), nullptr, per_grid);
+  if (rc) return rc;
+  // (i) interpolation onto the fine grid with the reference model
+  std::vector<double> tf(n_fine), gref_f(n_fine);
+  for (int j = 0; j < n_fine; ++j) tf[j] = j * (beta / (n_fine - 1));
+  host::reference_tau(bath_iw, n_iw, bath_m3, U, beta, tf.data(), n_fine, gref_f.data());
+  std::vector<double> gi((size_t)n_grids * n_fine), ei((size_t)n_grids * n_fine);
+  off = 0;
+  for (int i = 0; i < n_grids; ++i) {
+    const int L = Ls[i];
+    std::vector<double> tk(L + 1), gref_k(L + 1), d(L + 1);
+    for (int k = 0; k <= L; ++k) tk[k] = k * (beta / L);
+    host::reference_tau(bath_iw, n_iw, bath_m3, U, beta, tk.data(), L + 1, gref_k.data());
+    for (int k = 0; k <= L; ++k) d[k] = gg[off + k] - gref_k[k];
+    host::Spline sp(tk.data(), d.data(), L + 1);
+    for (int j = 0; j < n_fine; ++j) {
+      gi[(size_t)i * n_fine + j] = gref_f[j] + sp(tf[j]);
+      // linear interpolation of the error bars
+      const double x = tf[j] / (beta / L);
+      int k0 = (int)std::floor(x);
+      if (k0 < 0) k0 = 0;
+      if (k0 > L - 1) k0 = L - 1;
+      const double fr = x - k0;
+      ei[(size_t)i * n_fine + j] = ge[off + k0] * (1.0 - fr) + ge[off + k0 + 1] * fr;
+    }
+    off += L + 1;
+  }
+  // (ii) quadratic-in-dtau^2 least squares per fine point
+  std::vector<double> err(n_fine);
+  host::extrapolate(dts.data(), n_grids, gi.data(), ei.data(), n_fine, g_fine, err.data());
+  if (g_fine_err) std::memcpy(g_fine_err, err.data(), sizeof(double) * n_fine);
+  if (g_grids) std::memcpy(g_grids, gg.data(), sizeof(double) * Psum);
+  return HFQMC_OK;
+}
+
+extern "C" int dmft_bethe_step(const double* g_fine, int32_t n_fine, const double* bath_iw_prev,
+                               int32_t n_iw, double bath_m3, double U, double beta, double t,
+                               double* bath_iw_new) {
+  if (!g_fine || !bath_iw_prev || !bath_iw_new) return fail(HFQMC_EINVAL, "dmft_bethe_step: null pointer");
+  if (n_fine < 4 || n_iw < 16 || !(beta > 0) || !(t > 0) || !(U >= 0))
+    return fail(HFQMC_EINVAL, "dmft_bethe_step: bad size or parameter");
+  for (int j = 0; j < n_fine; ++j)
+    if (!std::isfinite(g_fine[j])) return fail(HFQMC_EINVAL, "dmft_bethe_step: g_fine[%d] not finite", j);
+  return host::bethe_step(g_fine, n_fine, bath_iw_prev, n_iw, bath_m3, U, beta, t, bath_iw_new);
+}

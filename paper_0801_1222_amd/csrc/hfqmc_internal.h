@@ -1,0 +1,82 @@
+// Internal interface between the C-ABI layer and the gfx950 kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hfqmc {
+
+// Per-chain counters written by the sweep kernel.
+enum {
+  ST_PROPOSED = 0,
+  ST_ACCEPTED = 1,
+  ST_RECOMPUTES = 2,
+  ST_BAD = 3,       // proposals whose ratio was <= 0 or NaN (rejected)
+  ST_SINGULAR = 4,  // zero or non-finite pivots met in a Dyson recompute
+  ST_FLIPS = 5,     // entries written to the flip log (may exceed its capacity)
+  ST_REPLAYED = 6,  // replay entries consumed
+  NSTAT = 8
+};
+
+enum { MODE_RANK1 = 0, MODE_DELAYED_FP64 = 1, MODE_MIXED = 2 };
+
+// One Trotter grid of a (possibly batched) launch.  All pointers are device pointers.
+struct GridDev {
+  int L;
+  int n_chains;
+  int grid_id;            // Philox key word 1
+  int unit_base;          // index of chain 0 of this grid in the per-launch chain arrays
+  double gp, gm;          // e^{2 lambda} - 1, e^{-2 lambda} - 1  (flip factors gamma)
+  double ep, em;          // e^{lambda} - 1,   e^{-lambda} - 1    (Dyson matrix diagonal)
+  const double* G0;       // L x L bath matrix, row-major
+  double* acc_g;          // [n_chains][n_bins][L+1] sums of G(tau_k)
+  double* acc_d;          // [n_chains][n_bins] sums of D
+  long long* acc_n;       // [n_chains][n_bins] measurement counts
+  long long* cstats;      // [n_chains][NSTAT]
+  double* cdrift;         // [n_chains] max elementwise recompute drift
+  long long* flip_log;    // [n_chains][flip_cap] or null
+  const long long* replay;    // [n_chains][replay_cap] or null
+  const long long* replay_n;  // [n_chains] or null
+  double* g_final;        // [n_chains][2][L][L] or null
+  double* g_out;          // [L+1] chain-reduced G(tau)
+  double* g_err;          // [L+1]
+  double* d_out;          // [2] D and its error
+};
+
+struct SweepParams {
+  const GridDev* grids;
+  int n_grids;
+  const int* units;       // dispatch order, entry = (grid << 20) | chain
+  int n_units;
+  int* queue;             // work-queue counter (zeroed before launch)
+  unsigned long long seed;
+  long long warmup, sweeps;
+  int n_rec;              // accepted flips between recomputes
+  int mode;
+  int delay_k;            // max pending flips (delayed modes)
+  int window_b;           // max slices per window (delayed modes)
+  int n_bins;
+  int lu_nb;              // LU panel width
+  long long flip_cap, replay_cap;
+  double* work;           // per-workgroup workspace
+  long long work_stride;  // doubles per workgroup
+  int Lmax;
+  int lds_scratch_bytes;  // bytes of the phase-shared LDS region
+};
+
+constexpr int kThreads = 512;   // threads per persistent workgroup (8 wave64)
+constexpr int kNBMax = 32;      // largest LU panel width
+constexpr int kMaxK = 64;       // largest delayed rank
+
+// Workspace (doubles) needed per workgroup for chains of length up to Lmax.
+long long workspace_doubles(int Lmax, int kmax);
+// Dynamic LDS bytes of the persistent kernel and the LU panel width for Lmax.
+int lds_bytes(int Lmax, int mode, int k, int b, int* lu_nb, int* scratch_bytes);
+
+hipError_t launch_build_g0(const double* g_tau, int L, double* G0, hipStream_t s);
+hipError_t launch_zero(double* p, long long n, hipStream_t s);
+hipError_t launch_zero_i64(long long* p, long long n, hipStream_t s);
+hipError_t launch_zero_i32(int* p, long long n, hipStream_t s);
+hipError_t launch_sweeps(const SweepParams& p, int n_wg, int lds, hipStream_t s);
+hipError_t launch_reduce(const GridDev* grids, int n_grids, int n_bins, hipStream_t s);
+
+}  // namespace hfqmc

@@ -1,0 +1,187 @@
+"""GPU parity of the FP64 rank-1 path against the CPU oracle (through the C ABI).
+
+Bar: identical accepted-flip sequences (same Philox stream) and per-chain
+G(tau) accumulators within 1e-10 absolute; Monte Carlo results within their
+statistical error of exact enumeration or closed forms.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import bath as OB
+from oracle import hfqmc as OH
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_0801_1222_amd as P
+    c = P.Context(0)
+    yield c
+    c.close()
+
+
+def _bath(beta, L, t=1.0):
+    return OB.bath_to_tau(OB.semicircle_iw(beta, t, 20000), t * t, beta, L)
+
+
+def _codes(ref, L):
+    return [sw * L + l for sw, l in ref["flips"]]
+
+
+def _check_chains(out, g0, U, beta, seed, chains, warmup, sweeps, n_rec=100, grid_id=0, L=None):
+    L = g0.shape[0]
+    for c in chains:
+        ref = OH.run_chain(g0, U, beta, seed, chain=c, grid_id=grid_id, warmup=warmup,
+                           sweeps=sweeps, n_rec=n_rec)
+        assert list(out["flips"][c]) == _codes(ref, L), "chain %d flips differ" % c
+        n = out["chain_n"][c][0]
+        assert n == ref["bins_n"][0]
+        got = out["chain_g"][c][0] / n
+        exp = ref["bins_g"][0] / ref["bins_n"][0]
+        assert np.abs(got - exp).max() < 1e-10
+        assert abs(out["chain_d"][c][0] / n - ref["bins_d"][0] / ref["bins_n"][0]) < 1e-10
+
+
+def test_u0_green_is_bath(ctx):
+    import paper_0801_1222_amd as P
+    beta, L = 10.0, 20
+    g0 = _bath(beta, L)
+    out = P.hfqmc_solve(ctx, g0, 0.0, beta, beta / L, 0, n_chains=3, warmup=1, sweeps=4)
+    assert np.abs(out["g"][:L] - g0).max() < 1e-14
+    assert abs(out["g"][L] - (1 - g0[0])) < 1e-14
+    assert out["stats"]["n_accepted"] == out["stats"]["n_proposed"]
+
+
+def test_flips_and_accumulators_match_oracle_small(ctx):
+    import paper_0801_1222_amd as P
+    beta, U, L, seed = 10.0, 4.0, 20, 0
+    g0 = _bath(beta, L)
+    out = P.hfqmc_solve(ctx, g0, U, beta, beta / L, seed, n_chains=4, warmup=20, sweeps=300,
+                        flip_cap=20000, want_chain=True)
+    _check_chains(out, g0, U, beta, seed, range(4), 20, 300)
+    st = out["stats"]
+    assert st["n_bad_ratio"] == 0 and st["n_singular"] == 0
+    assert st["max_drift"] < 1e-11
+
+
+def test_ragged_length_and_odd_L(ctx):
+    # odd L exercises the element-pair tail of the update and the LU panel tail
+    import paper_0801_1222_amd as P
+    beta, U, L, seed = 7.0, 5.0, 37, 11
+    g0 = _bath(beta, L)
+    out = P.hfqmc_solve(ctx, g0, U, beta, beta / L, seed, n_chains=3, warmup=3, sweeps=25,
+                        recompute_every=17, flip_cap=20000, want_chain=True)
+    _check_chains(out, g0, U, beta, seed, range(3), 3, 25, n_rec=17)
+
+
+def test_final_green_matches_exact_recompute(ctx):
+    import paper_0801_1222_amd as P
+    beta, U, L, seed = 10.0, 4.0, 50, 5
+    g0 = _bath(beta, L)
+    out = P.hfqmc_solve(ctx, g0, U, beta, beta / L, seed, n_chains=2, warmup=2, sweeps=3,
+                        recompute_every=37, flip_cap=20000, want_green=True)
+    lam = OH.hs_lambda(U, beta / L)
+    G0 = OH.g0_matrix(g0)
+    for c in range(2):
+        ref = OH.run_chain(g0, U, beta, seed, chain=c, warmup=2, sweeps=3, n_rec=37)
+        Gu, Gd = OH.green_from_field(G0, ref["field"], lam)
+        assert np.abs(out["green"][c, 0] - Gu).max() < 1e-10
+        assert np.abs(out["green"][c, 1] - Gd).max() < 1e-10
+        # particle-hole identity holds per configuration
+        assert np.abs(out["green"][c, 1] - (np.eye(L) - out["green"][c, 0].T)).max() < 1e-10
+
+
+def test_c1_against_exact_enumeration(ctx):
+    """beta=10, U=4, dtau=0.5 (L=20), one chain, seed 0, 1000 + 20000 sweeps."""
+    import paper_0801_1222_amd as P
+    fx = {}
+    with open(os.path.join(HERE, "golden", "bethe_b10_u4_L20.txt")) as f:
+        for line in f:
+            if line.startswith("#"):
+                continue
+            parts = line.split()
+            if parts[0] == "D":
+                fx["D"] = float(parts[1])
+            else:
+                fx[int(parts[1])] = float(parts[2])
+    beta, U, L = 10.0, 4.0, 20
+    g0 = _bath(beta, L)
+    out = P.hfqmc_solve(ctx, g0, U, beta, 0.5, 0, n_chains=1, warmup=1000, sweeps=20000)
+    exact = np.array([fx[k] for k in range(L + 1)])
+    z = np.abs(out["g"] - exact)[1:L] / out["g_err"][1:L]
+    assert z.max() < 4.0, z
+    assert abs(out["D"] - fx["D"]) < 4.0 * out["D_err"]
+    assert np.abs(out["g"][1:L] - out["g"][1:L][::-1]).max() < 1e-12
+    assert out["stats"]["max_drift"] < 1e-11
+
+
+def test_atomic_limit(ctx):
+    import paper_0801_1222_amd as P
+    beta, U, L = 4.0, 4.0, 10
+    out = P.hfqmc_solve(ctx, np.full(L, 0.5), U, beta, beta / L, 3, n_chains=16, warmup=50,
+                        sweeps=800)
+    tau = np.arange(L + 1) * beta / L
+    z = np.abs(out["g"] - OH.atomic_limit_g(U, beta, tau))[1:L] / out["g_err"][1:L]
+    assert z.max() < 4.0
+    assert abs(out["D"] - OH.atomic_limit_d(U, beta)) < 4.0 * out["D_err"]
+
+
+def test_replay_follows_given_flips(ctx):
+    import paper_0801_1222_amd as P
+    beta, U, L, seed = 10.0, 4.0, 20, 2
+    g0 = _bath(beta, L)
+    refs = [OH.run_chain(g0, U, beta, seed, chain=c, warmup=0, sweeps=30) for c in range(2)]
+    out = P.hfqmc_solve(ctx, g0, U, beta, beta / L, seed, n_chains=2, warmup=0, sweeps=30,
+                        replay=[_codes(r, L) for r in refs], flip_cap=5000, want_chain=True)
+    for c in range(2):
+        assert list(out["flips"][c]) == _codes(refs[c], L)
+        got = out["chain_g"][c][0] / out["chain_n"][c][0]
+        assert np.abs(got - refs[c]["bins_g"][0] / refs[c]["bins_n"][0]).max() < 1e-10
+
+
+def test_batched_uneven_grids(ctx):
+    """Several L in one persistent launch; grid i uses Philox grid key i."""
+    import paper_0801_1222_amd as P
+    beta, U, seed = 5.0, 4.8, 1
+    Ls = [10, 25, 16, 40]
+    g0s = [_bath(beta, L) for L in Ls]
+    out = P.hfqmc_solve_grids(ctx, Ls, g0s, U, beta, seed, n_chains=3, warmup=2, sweeps=10,
+                              flip_cap=20000, want_chain=True)
+    for i, L in enumerate(Ls):
+        for c in range(3):
+            ref = OH.run_chain(g0s[i], U, beta, seed, chain=c, grid_id=i, warmup=2, sweeps=10)
+            assert list(out["flips"][i][c]) == _codes(ref, L)
+            got = out["chain_g"][i][c][0] / out["chain_n"][i, c, 0]
+            assert np.abs(got - ref["bins_g"][0] / ref["bins_n"][0]).max() < 1e-10
+
+
+def test_c2_shape_sampled_chains(ctx):
+    """Production shape (beta=40, U=4.5, L=400, 256 chains, recompute every 100),
+    shortened to 1 + 2 sweeps; chains 0, 97 and 255 checked one by one."""
+    import paper_0801_1222_amd as P
+    beta, U, L = 40.0, 4.5, 400
+    g0 = _bath(beta, L)
+    out = P.hfqmc_solve(ctx, g0, U, beta, 0.1, 0, n_chains=256, warmup=1, sweeps=2,
+                        flip_cap=4096, want_chain=True)
+    _check_chains(out, g0, U, beta, 0, [0, 97, 255], 1, 2)
+    st = out["stats"]
+    assert st["n_bad_ratio"] == 0 and st["n_singular"] == 0
+    assert 0.45 < st["acc_rate"] < 0.65
+
+
+def test_invalid_arguments_raise(ctx):
+    import paper_0801_1222_amd as P
+    g0 = _bath(10.0, 20)
+    with pytest.raises(P.HFQMCError):
+        P.hfqmc_solve(ctx, g0, 4.0, 10.0, 0.3, 0)          # beta/dtau != L
+    with pytest.raises(P.HFQMCError):
+        P.hfqmc_solve(ctx, g0, -1.0, 10.0, 0.5, 0)         # U < 0
+    with pytest.raises(P.HFQMCError):
+        P.hfqmc_solve(ctx, g0, 4.0, 10.0, 0.5, 0, sweeps=0)
+    with pytest.raises(P.HFQMCError):
+        P.hfqmc_solve(ctx, g0[:1], 4.0, 0.5, 0.5, 0)        # L < 2

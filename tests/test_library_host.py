@@ -1,0 +1,73 @@
+"""CPU checks of the native library: it loads, exports every declared symbol,
+and its host-only routines agree with the oracle."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import bath as OB
+from oracle import multigrid as OMG
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "hfqmc.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?(?:int|void|char\s*\*|const char\s*\*)\s*\*?\s*(\w+)\s*\(",
+                       src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_0801_1222_amd import _native as N
+    names = _declared()
+    assert "hfqmc_solve" in names and "multigrid_solve" in names and "dmft_bethe_step" in names
+    for n in names:
+        assert hasattr(N.lib, n), n
+    assert sorted(N.EXPORTED) == names
+
+
+def test_context_without_gpu_reports_device_error():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    import paper_0801_1222_amd as P
+    with pytest.raises(P.HFQMCError) as e:
+        P.Context(0)
+    assert e.value.code == -3
+
+
+def test_semicircle_and_bath_transform_match_oracle():
+    import paper_0801_1222_amd as P
+    for beta, L in [(10.0, 20), (40.0, 400), (20.0, 57)]:
+        b = P.bethe_semicircle_bath(beta, 1.0, 8000)
+        bo = OB.semicircle_iw(beta, 1.0, 8000)
+        assert np.abs(b - bo).max() < 1e-15
+        g = P.bath_to_tau(b, 1.0, beta, L)
+        go = OB.bath_to_tau(bo, 1.0, beta, L)
+        assert np.abs(g - go).max() < 1e-12
+
+
+def test_bethe_step_matches_oracle_and_fixed_point():
+    import paper_0801_1222_amd as P
+    beta, t = 10.0, 1.0
+    b = OB.semicircle_iw(beta, t, 3000)
+    tf = OMG.fine_grid(beta, 200)
+    gf = OB.iw_to_tau(b, 1.0, beta, tf)
+    # U = 0: fixed point
+    assert np.abs(P.dmft_bethe_step(gf, b, 1.0, 0.0, beta, t) - b).max() < 1e-12
+    # U > 0 with a perturbed G: same result as the oracle's spline transform
+    gp = gf + 0.01 * np.sin(np.pi * tf / beta) ** 2
+    new = P.dmft_bethe_step(gp, b, 1.0, 3.0, beta, t)
+    ref = OMG.dmft_bethe_step(gp, tf, b, 1.0, 3.0, beta, t)
+    assert np.abs(new - ref).max() < 1e-11
+
+
+def test_host_argument_errors():
+    import paper_0801_1222_amd as P
+    with pytest.raises(P.HFQMCError):
+        P.bath_to_tau(np.zeros(4, dtype=complex), 1.0, 10.0, 20)   # n_iw < 16
+    with pytest.raises(P.HFQMCError):
+        P.dmft_bethe_step(np.zeros(3), np.zeros(100, dtype=complex), 1.0, 0.0, 10.0, 1.0)
