@@ -159,13 +159,12 @@ int resolve_opts(const hfqmc_opts* o, Resolved* r) {
     int k = o->delay_k == 0 ? 32 : o->delay_k;
     if (k < 2 || k > kMaxK) return fail(HFQMC_EINVAL, "delay_k=%d (2..%d)", k, kMaxK);
     r->delay_k = k;
-    r->window_b = 64;
+    r->window_b = 64;  // slices per window; the kernel's diagonal block edge
   }
   r->n_rec = o->recompute_every > 0 ? o->recompute_every
                                     : (o->mode == MODE_RANK1 ? 100 : 4 * r->delay_k);
   r->n_bins = o->n_bins > 0 ? o->n_bins : (o->n_chains == 1 ? 20 : 1);
   if (r->n_bins > r->sweeps) return fail(HFQMC_EINVAL, "n_bins=%d > sweeps", r->n_bins);
-  if (r->mode != MODE_RANK1) return fail(HFQMC_EUNSUPPORTED, "delayed modes are not built yet");
   return HFQMC_OK;
 }
 

@@ -424,6 +424,390 @@ __device__ void measure(const Chain& ch, int bin) {
   }
 }
 
+// ---------------------------------------------------------- proposals ----
+
+struct Counters {
+  long long n_prop, n_acc, n_rec, n_bad, n_flips, rep_i;
+  double drift;
+  int acc_since;
+  int singular;
+};
+
+// Metropolis decision for flipping s_l, evaluated identically by every thread
+// of the workgroup (uniform branch).  In replay mode the decision is read from
+// the given flip list instead of u < R.
+struct Flip {
+  double g_up, g_dn, r_up, r_dn;
+  bool accept;
+};
+
+__device__ __forceinline__ Flip propose(double gul, double gdl, int sl, double gp, double gm,
+                                       double u, const long long* rlog, long long rlen,
+                                       long long code, Counters& k) {
+  Flip f;
+  f.g_up = sl > 0 ? gm : gp;
+  f.g_dn = sl > 0 ? gp : gm;
+  f.r_up = ratio_factor(f.g_up, gul);
+  f.r_dn = ratio_factor(f.g_dn, gdl);
+  const double R = mul_nc(f.r_up, f.r_dn);
+  ++k.n_prop;
+  const bool bad = !(R > 0.0);
+  k.n_bad += bad ? 1 : 0;
+  if (rlog) {
+    f.accept = k.rep_i < rlen && rlog[k.rep_i] == code;
+    k.rep_i += f.accept ? 1 : 0;
+  } else {
+    f.accept = !bad && u < R;
+  }
+  return f;
+}
+
+struct ChainIO {
+  long long* flog;
+  const long long* rlog;
+  long long rlen;
+  long long flip_cap;
+  double gp, gm;
+};
+
+__device__ __forceinline__ void log_flip(const ChainIO& io, Counters& k, long long code) {
+  if (io.flog && threadIdx.x == 0 && k.n_flips < io.flip_cap) io.flog[k.n_flips] = code;
+  ++k.n_flips;
+}
+
+__device__ void recompute_both(const SweepParams& p, const Chain& ch, Counters& k) {
+  const double d1 = dyson_recompute(ch, +1, ch.Gu, p.lu_nb, &k.singular);
+  const double d2 = dyson_recompute(ch, -1, ch.Gd, p.lu_nb, &k.singular);
+  k.drift = fmax(k.drift, fmax(d1, d2));
+  ++k.n_rec;
+  k.acc_since = 0;
+}
+
+// ------------------------------------------------- plain rank-1 sweep ----
+// Every accepted flip applies G <- G + (G(:,l) - e_l)(gamma/R_sigma) G(l,:) to
+// both L x L matrices in HBM: 32 L^2 bytes of traffic per accepted flip.
+__device__ void sweep_rank1(const SweepParams& p, const Chain& ch, long long sw, Counters& k,
+                            const ChainIO& io) {
+  const int L = ch.L;
+  const long long L2 = (long long)L * L;
+  double* xu = reinterpret_cast<double*>(ch.scratch);
+  double* xd = xu + p.Lmax;
+  double* yu = xd + p.Lmax;
+  double* yd = yu + p.Lmax;
+  for (int l = 0; l < L; ++l) {
+    const long long dl = (long long)l * L + l;
+    const int sl = ch.s[l];
+    const Flip f = propose(ch.Gu[dl], ch.Gd[dl], sl, io.gp, io.gm, ch.u[l], io.rlog, io.rlen,
+                           sw * L + l, k);
+    if (!f.accept) continue;
+    ++k.n_acc;
+    log_flip(io, k, sw * L + l);
+    // update vectors x = G(:,l) - e_l and y = (gamma/R_sigma) G(l,:)
+    const double cu = f.g_up / f.r_up, cd = f.g_dn / f.r_dn;
+    for (int i = threadIdx.x; i < L; i += kThreads) {
+      const long long ci = (long long)i * L + l;
+      xu[i] = ch.Gu[ci] - (i == l ? 1.0 : 0.0);
+      xd[i] = ch.Gd[ci] - (i == l ? 1.0 : 0.0);
+      yu[i] = mul_nc(cu, ch.Gu[(long long)l * L + i]);
+      yd[i] = mul_nc(cd, ch.Gd[(long long)l * L + i]);
+    }
+    __syncthreads();
+    // G += x y^T, both spins, two consecutive elements per thread
+    {
+      long long idx = 2 * (long long)threadIdx.x;
+      int i = (int)(idx / L), j = (int)(idx - (long long)i * L);
+      const long long step = 2 * (long long)kThreads;
+      const int di = (int)(step / L), dj = (int)(step - (long long)di * L);
+      for (; idx < L2; idx += step) {
+        int i1 = i, j1 = j + 1;
+        if (j1 == L) {
+          j1 = 0;
+          ++i1;
+        }
+        ch.Gu[idx] = axpy_nc(ch.Gu[idx], xu[i], yu[j]);
+        ch.Gd[idx] = axpy_nc(ch.Gd[idx], xd[i], yd[j]);
+        if (idx + 1 < L2) {
+          ch.Gu[idx + 1] = axpy_nc(ch.Gu[idx + 1], xu[i1], yu[j1]);
+          ch.Gd[idx + 1] = axpy_nc(ch.Gd[idx + 1], xd[i1], yd[j1]);
+        }
+        i += di;
+        j += dj;
+        if (j >= L) {
+          j -= L;
+          ++i;
+        }
+      }
+    }
+    if (threadIdx.x == 0) ch.s[l] = (int8_t)(-sl);
+    __syncthreads();
+    if (++k.acc_since == p.n_rec) recompute_both(p, ch, k);
+  }
+}
+
+// -------------------------------------------- windowed delayed update ----
+//
+// The sweep visits l = l0, l0+1, ... inside a window of at most kWin
+// consecutive slices.  Deciding and updating inside the window only needs
+// the kWin x kWin diagonal blocks of G_up and G_dn, which live in LDS and get
+// the exact rank-1 updates of each accepted flip.  The window closes after
+// delay_k accepted flips (or at the recompute point, or the sweep end); the
+// m accepted flips are then applied to the full matrices as one rank-m update
+//   G <- G + X Y,   X = [x_1..x_m] (L x m),  Y = [y_1..y_m]^T (m x L),
+// the delayed-update form of m successive Sherman-Morrison steps.  Their full
+// vectors follow from the untouched G and the in-window values:
+//   x_j = G(:, f_j) - e_{f_j} + sum_{i<j} x_i y_i(f_j)
+//   y_j = c_j (G(f_j, :) + sum_{i<j} x_i(f_j) y_i),  c_j = gamma_j / R_j.
+// The rank-m product runs in FP64 (MODE_DELAYED_FP64) or with FP32 inputs and
+// FP32 accumulation on the matrix cores (MODE_MIXED); ratios, decisions and
+// the in-window updates are FP64 in both.
+
+constexpr int kWin = 64;        // slices per window (diagonal block edge)
+constexpr int kWP = kWin + 1;   // LDS row stride of the window blocks
+constexpr int kKP = kMaxK + 1;  // LDS row stride of the m x m coefficient blocks
+constexpr int kSmall = 1536;    // bytes for flip positions and coefficients
+constexpr int kTile = 64;       // flush output tile edge
+constexpr int kTP = kTile + 4;  // FP64 tile row stride
+constexpr int kXS = kMaxK + 1;  // FP32 X tile row stride
+constexpr int kYS = kTile + 1;  // FP32 Y tile row stride
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// G += X Y for one spin. X: [L][kMaxK] row-major, Y: [kMaxK][L] row-major, m used columns.
+template <bool MIXED>
+__device__ void flush_gemm(double* __restrict__ G, const double* __restrict__ X,
+                           const double* __restrict__ Y, int L, int m, char* lds) {
+  const int t = threadIdx.x;
+  if constexpr (MIXED) {
+    float* Xs = reinterpret_cast<float*>(lds);          // [kTile][kXS]
+    float* Ys = Xs + kTile * kXS;                        // [kMaxK][kYS]
+    const int m4 = (m + 3) & ~3;
+    const int w = t >> 6, lane = t & 63;
+    for (int r0 = 0; r0 < L; r0 += kTile) {
+      for (int idx = t; idx < kTile * m4; idx += kThreads) {
+        const int r = idx / m4, kk = idx - r * m4;
+        const int row = r0 + r;
+        Xs[r * kXS + kk] = (row < L && kk < m) ? (float)X[(long long)row * kMaxK + kk] : 0.f;
+      }
+      for (int c0 = 0; c0 < L; c0 += kTile) {
+        for (int idx = t; idx < m4 * kTile; idx += kThreads) {
+          const int kk = idx / kTile, c = idx - kk * kTile;
+          const int col = c0 + c;
+          Ys[kk * kYS + c] = (col < L && kk < m) ? (float)Y[(long long)kk * L + col] : 0.f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int blk = 2 * w + h;
+          const int br = blk >> 2, bc = blk & 3;
+          floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+          for (int k0 = 0; k0 < m4; k0 += 4) {
+            const float a = Xs[(br * 16 + (lane & 15)) * kXS + k0 + (lane >> 4)];
+            const float b = Ys[(k0 + (lane >> 4)) * kYS + bc * 16 + (lane & 15)];
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+          }
+          const int col = c0 + bc * 16 + (lane & 15);
+#pragma unroll
+          for (int rr = 0; rr < 4; ++rr) {
+            const int row = r0 + br * 16 + 4 * (lane >> 4) + rr;
+            if (row < L && col < L) G[(long long)row * L + col] += (double)acc[rr];
+          }
+        }
+        __syncthreads();
+      }
+    }
+  } else {
+    double* Xt = reinterpret_cast<double*>(lds);        // [kMaxK][kTP]  (k-major)
+    double* Yt = Xt + kMaxK * kTP;                      // [kMaxK][kTP]
+    const int tr = t >> 4, tc = t & 15;                 // 32 x 16 threads, 2 x 4 outputs each
+    for (int r0 = 0; r0 < L; r0 += kTile) {
+      for (int idx = t; idx < kTile * m; idx += kThreads) {
+        const int r = idx / m, kk = idx - r * m;
+        const int row = r0 + r;
+        Xt[kk * kTP + r] = row < L ? X[(long long)row * kMaxK + kk] : 0.0;
+      }
+      for (int c0 = 0; c0 < L; c0 += kTile) {
+        for (int idx = t; idx < m * kTile; idx += kThreads) {
+          const int kk = idx / kTile, c = idx - kk * kTile;
+          const int col = c0 + c;
+          Yt[kk * kTP + c] = col < L ? Y[(long long)kk * L + col] : 0.0;
+        }
+        __syncthreads();
+        double acc[2][4] = {{0.0}};
+        for (int kk = 0; kk < m; ++kk) {
+          const double x0 = Xt[kk * kTP + 2 * tr], x1 = Xt[kk * kTP + 2 * tr + 1];
+          const double* yv = Yt + kk * kTP + 4 * tc;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            acc[0][q] = fma(x0, yv[q], acc[0][q]);
+            acc[1][q] = fma(x1, yv[q], acc[1][q]);
+          }
+        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+          const int row = r0 + 2 * tr + a;
+          if (row >= L) continue;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int col = c0 + 4 * tc + q;
+            if (col < L) G[(long long)row * L + col] += acc[a][q];
+          }
+        }
+        __syncthreads();
+      }
+    }
+  }
+}
+
+template <bool MIXED>
+__device__ void flush_window(const Chain& ch, int l0, int m) {
+  const int L = ch.L;
+  const int t = threadIdx.x;
+  const int* F = reinterpret_cast<const int*>(ch.scratch);
+  const double* cU = reinterpret_cast<const double*>(ch.scratch + 256);
+  const double* cD = cU + kMaxK;
+  char* un = ch.scratch + kSmall;
+  double* ULu = reinterpret_cast<double*>(un);
+  double* ULd = ULu + kMaxK * kKP;
+  const double* Xrec = ch.wbuf;                       // [2][kMaxK][kWin]
+  const double* Yrec = Xrec + 2 * kMaxK * kWin;       // [2][kMaxK][kWin]
+  double* X = ch.wbuf + 4 * kMaxK * kWin;             // [2][L][kMaxK]
+  double* Y = X + 2LL * L * kMaxK;                    // [2][kMaxK][L]
+  // in-window coefficients: U(i,j) = y_i(f_j) (i < j) above, x_j(f_i) (i > j) below
+  for (int idx = t; idx < m * m; idx += kThreads) {
+    const int i = idx / m, j = idx - i * m;
+    double vu = 0.0, vd = 0.0;
+    if (i < j) {
+      vu = Yrec[(0 * kMaxK + i) * kWin + F[j]];
+      vd = Yrec[(1 * kMaxK + i) * kWin + F[j]];
+    } else if (i > j) {
+      vu = Xrec[(0 * kMaxK + j) * kWin + F[i]];
+      vd = Xrec[(1 * kMaxK + j) * kWin + F[i]];
+    }
+    ULu[i * kKP + j] = vu;
+    ULd[i * kKP + j] = vd;
+  }
+  __syncthreads();
+  // full update vectors: one row of X or one column of Y per item
+  for (int item = t; item < 4 * L; item += kThreads) {
+    const int sp = item / (2 * L);
+    const int rem = item - sp * 2 * L;
+    const double* G = sp ? ch.Gd : ch.Gu;
+    const double* UL = sp ? ULd : ULu;
+    if (rem < L) {
+      const int q = rem;
+      double* xs = X + (long long)sp * L * kMaxK + (long long)q * kMaxK;
+      for (int j = 0; j < m; ++j) {
+        const int fj = l0 + F[j];
+        double acc = G[(long long)q * L + fj] - (q == fj ? 1.0 : 0.0);
+        for (int i = 0; i < j; ++i) acc = fma(xs[i], UL[i * kKP + j], acc);
+        xs[j] = acc;
+      }
+    } else {
+      const int r = rem - L;
+      double* ys = Y + (long long)sp * kMaxK * L;
+      const double* c = sp ? cD : cU;
+      for (int j = 0; j < m; ++j) {
+        const int fj = l0 + F[j];
+        double acc = G[(long long)fj * L + r];
+        for (int i = 0; i < j; ++i) acc = fma(UL[j * kKP + i], ys[(long long)i * L + r], acc);
+        ys[(long long)j * L + r] = c[j] * acc;
+      }
+    }
+  }
+  __syncthreads();
+  flush_gemm<MIXED>(ch.Gu, X, Y, L, m, un);
+  flush_gemm<MIXED>(ch.Gd, X + (long long)L * kMaxK, Y + (long long)kMaxK * L, L, m, un);
+  __syncthreads();
+}
+
+template <bool MIXED>
+__device__ void sweep_window(const SweepParams& p, const Chain& ch, long long sw, Counters& k,
+                             const ChainIO& io) {
+  const int L = ch.L;
+  const int t = threadIdx.x;
+  int* F = reinterpret_cast<int*>(ch.scratch);
+  double* cU = reinterpret_cast<double*>(ch.scratch + 256);
+  double* cD = cU + kMaxK;
+  char* un = ch.scratch + kSmall;
+  double* Wu = reinterpret_cast<double*>(un);
+  double* Wd = Wu + kWin * kWP;
+  double* xu = Wd + kWin * kWP;
+  double* yu = xu + kWin;
+  double* xd = yu + kWin;
+  double* yd = xd + kWin;
+  double* Xrec = ch.wbuf;
+  double* Yrec = Xrec + 2 * kMaxK * kWin;
+  int l0 = 0;
+  while (l0 < L) {
+    const int b = min(kWin, L - l0);
+    for (int idx = t; idx < kWin * kWin; idx += kThreads) {
+      const int q = idx >> 6, r = idx & 63;
+      if (q < b && r < b) {
+        const long long o = (long long)(l0 + q) * L + l0 + r;
+        Wu[q * kWP + r] = ch.Gu[o];
+        Wd[q * kWP + r] = ch.Gd[o];
+      }
+    }
+    __syncthreads();
+    int m = 0, pos = 0;
+    bool close = false;
+    while (pos < b && !close) {
+      const int l = l0 + pos;
+      const int sl = ch.s[l];
+      const Flip f = propose(Wu[pos * kWP + pos], Wd[pos * kWP + pos], sl, io.gp, io.gm, ch.u[l],
+                             io.rlog, io.rlen, sw * L + l, k);
+      if (f.accept) {
+        ++k.n_acc;
+        log_flip(io, k, sw * L + l);
+        const double cu = f.g_up / f.r_up, cd = f.g_dn / f.r_dn;
+        // in-window parts of x = G(:,l) - e_l and y = c G(l,:), kept for the flush
+        if (t < b) {
+          const double v = Wu[t * kWP + pos] - (t == pos ? 1.0 : 0.0);
+          xu[t] = v;
+          Xrec[(0 * kMaxK + m) * kWin + t] = v;
+        } else if (t >= 64 && t < 64 + b) {
+          const int r = t - 64;
+          const double v = mul_nc(cu, Wu[pos * kWP + r]);
+          yu[r] = v;
+          Yrec[(0 * kMaxK + m) * kWin + r] = v;
+        } else if (t >= 128 && t < 128 + b) {
+          const int q = t - 128;
+          const double v = Wd[q * kWP + pos] - (q == pos ? 1.0 : 0.0);
+          xd[q] = v;
+          Xrec[(1 * kMaxK + m) * kWin + q] = v;
+        } else if (t >= 192 && t < 192 + b) {
+          const int r = t - 192;
+          const double v = mul_nc(cd, Wd[pos * kWP + r]);
+          yd[r] = v;
+          Yrec[(1 * kMaxK + m) * kWin + r] = v;
+        }
+        if (t == 0) {
+          F[m] = pos;
+          cU[m] = cu;
+          cD[m] = cd;
+        }
+        __syncthreads();
+        for (int idx = t; idx < kWin * kWin; idx += kThreads) {
+          const int q = idx >> 6, r = idx & 63;
+          if (q < b && r < b) {
+            Wu[q * kWP + r] = axpy_nc(Wu[q * kWP + r], xu[q], yu[r]);
+            Wd[q * kWP + r] = axpy_nc(Wd[q * kWP + r], xd[q], yd[r]);
+          }
+        }
+        if (t == 0) ch.s[l] = (int8_t)(-sl);
+        ++m;
+        ++k.acc_since;
+        __syncthreads();
+        close = (m == p.delay_k) || (k.acc_since == p.n_rec);
+      }
+      ++pos;
+    }
+    if (m > 0) flush_window<MIXED>(ch, l0, m);
+    if (k.acc_since == p.n_rec) recompute_both(p, ch, k);
+    l0 += pos;
+  }
+}
+
 // ----------------------------------------------------------- the chain ----
 
 __device__ void run_chain(const SweepParams& p, const GridDev* gd, int chain, double* ws,
@@ -458,100 +842,32 @@ __device__ void run_chain(const SweepParams& p, const GridDev* gd, int chain, do
     ch.s[l] = uniform53(ch.key0, (uint64_t)gd->grid_id, (uint64_t)l, 0ull, 1ull) < 0.5 ? 1 : -1;
   __syncthreads();
 
-  int singular = 0;
-  dyson_recompute(ch, +1, ch.Gu, p.lu_nb, &singular);
-  dyson_recompute(ch, -1, ch.Gd, p.lu_nb, &singular);
+  Counters k = {0, 0, 0, 0, 0, 0, 0.0, 0, 0};
+  dyson_recompute(ch, +1, ch.Gu, p.lu_nb, &k.singular);
+  dyson_recompute(ch, -1, ch.Gd, p.lu_nb, &k.singular);
 
-  long long n_prop = 0, n_acc = 0, n_rec = 0, n_bad = 0, n_flips = 0, rep_i = 0;
-  double drift = 0.0;
-  int acc_since = 0;
+  ChainIO io;
+  io.flog = gd->flip_log ? gd->flip_log + (long long)chain * p.flip_cap : nullptr;
+  io.rlog = gd->replay ? gd->replay + (long long)chain * p.replay_cap : nullptr;
+  io.rlen = gd->replay ? min(gd->replay_n[chain], p.replay_cap) : 0;
+  io.flip_cap = p.flip_cap;
+  io.gp = gd->gp;
+  io.gm = gd->gm;
+
   const long long total = p.warmup + p.sweeps;
-  long long* flog = gd->flip_log ? gd->flip_log + (long long)chain * p.flip_cap : nullptr;
-  const long long* rlog = gd->replay ? gd->replay + (long long)chain * p.replay_cap : nullptr;
-  const long long rlen = gd->replay ? min(gd->replay_n[chain], p.replay_cap) : 0;
-  const double gp = gd->gp, gm = gd->gm;
-
-  double* xu = reinterpret_cast<double*>(ch.scratch);
-  double* xd = xu + p.Lmax;
-  double* yu = xd + p.Lmax;
-  double* yd = yu + p.Lmax;
-
   for (long long sw = 0; sw < total; ++sw) {
     for (int l = threadIdx.x; l < L; l += kThreads)
       ch.u[l] = uniform53(ch.key0, (uint64_t)gd->grid_id, (uint64_t)l, (uint64_t)sw, 0ull);
     __syncthreads();
-    for (int l = 0; l < L; ++l) {
-      const long long dl = (long long)l * L + l;
-      const double gul = ch.Gu[dl], gdl = ch.Gd[dl];
-      const int sl = ch.s[l];
-      const double g_up = sl > 0 ? gm : gp;
-      const double g_dn = sl > 0 ? gp : gm;
-      const double r_up = ratio_factor(g_up, gul);
-      const double r_dn = ratio_factor(g_dn, gdl);
-      const double R = mul_nc(r_up, r_dn);
-      ++n_prop;
-      const bool bad = !(R > 0.0);
-      n_bad += bad ? 1 : 0;
-      bool accept;
-      if (rlog) {
-        accept = rep_i < rlen && rlog[rep_i] == sw * L + l;
-        rep_i += accept ? 1 : 0;
-      } else {
-        accept = !bad && ch.u[l] < R;
-      }
-      if (!accept) continue;
-      ++n_acc;
-      if (flog && threadIdx.x == 0 && n_flips < p.flip_cap) flog[n_flips] = sw * L + l;
-      ++n_flips;
-      // update vectors x = G(:,l) - e_l and y = (gamma/R_sigma) G(l,:)
-      const double cu = g_up / r_up, cd = g_dn / r_dn;
-      for (int i = threadIdx.x; i < L; i += kThreads) {
-        const long long ci = (long long)i * L + l;
-        xu[i] = ch.Gu[ci] - (i == l ? 1.0 : 0.0);
-        xd[i] = ch.Gd[ci] - (i == l ? 1.0 : 0.0);
-        yu[i] = mul_nc(cu, ch.Gu[(long long)l * L + i]);
-        yd[i] = mul_nc(cd, ch.Gd[(long long)l * L + i]);
-      }
-      __syncthreads();
-      // G += x y^T, both spins, two consecutive elements per thread
-      {
-        long long idx = 2 * (long long)threadIdx.x;
-        int i = (int)(idx / L), j = (int)(idx - (long long)i * L);
-        const long long step = 2 * (long long)kThreads;
-        const int di = (int)(step / L), dj = (int)(step - (long long)di * L);
-        for (; idx < L2; idx += step) {
-          int i1 = i, j1 = j + 1;
-          if (j1 == L) {
-            j1 = 0;
-            ++i1;
-          }
-          ch.Gu[idx] = axpy_nc(ch.Gu[idx], xu[i], yu[j]);
-          ch.Gd[idx] = axpy_nc(ch.Gd[idx], xd[i], yd[j]);
-          if (idx + 1 < L2) {
-            ch.Gu[idx + 1] = axpy_nc(ch.Gu[idx + 1], xu[i1], yu[j1]);
-            ch.Gd[idx + 1] = axpy_nc(ch.Gd[idx + 1], xd[i1], yd[j1]);
-          }
-          i += di;
-          j += dj;
-          if (j >= L) {
-            j -= L;
-            ++i;
-          }
-        }
-      }
-      if (threadIdx.x == 0) ch.s[l] = (int8_t)(-sl);
-      __syncthreads();
-      if (++acc_since == p.n_rec) {
-        const double d1 = dyson_recompute(ch, +1, ch.Gu, p.lu_nb, &singular);
-        const double d2 = dyson_recompute(ch, -1, ch.Gd, p.lu_nb, &singular);
-        drift = fmax(drift, fmax(d1, d2));
-        ++n_rec;
-        acc_since = 0;
-      }
-    }
+    if (p.mode == MODE_RANK1)
+      sweep_rank1(p, ch, sw, k, io);
+    else if (p.mode == MODE_MIXED)
+      sweep_window<true>(p, ch, sw, k, io);
+    else
+      sweep_window<false>(p, ch, sw, k, io);
     if (sw >= p.warmup) {
-      const long long m = sw - p.warmup;
-      const int bin = (int)((m * nb) / p.sweeps);
+      const long long msw = sw - p.warmup;
+      const int bin = (int)((msw * nb) / p.sweeps);
       measure(ch, bin);
     }
     __syncthreads();
@@ -559,14 +875,14 @@ __device__ void run_chain(const SweepParams& p, const GridDev* gd, int chain, do
 
   if (threadIdx.x == 0) {
     long long* st = gd->cstats + (long long)chain * NSTAT;
-    st[ST_PROPOSED] = n_prop;
-    st[ST_ACCEPTED] = n_acc;
-    st[ST_RECOMPUTES] = n_rec;
-    st[ST_BAD] = n_bad;
-    st[ST_SINGULAR] = singular;
-    st[ST_FLIPS] = n_flips;
-    st[ST_REPLAYED] = rep_i;
-    gd->cdrift[chain] = drift;
+    st[ST_PROPOSED] = k.n_prop;
+    st[ST_ACCEPTED] = k.n_acc;
+    st[ST_RECOMPUTES] = k.n_rec;
+    st[ST_BAD] = k.n_bad;
+    st[ST_SINGULAR] = k.singular;
+    st[ST_FLIPS] = k.n_flips;
+    st[ST_REPLAYED] = k.rep_i;
+    gd->cdrift[chain] = k.drift;
   }
   if (gd->g_final) {
     double* out = gd->g_final + (long long)chain * 2 * L2;
@@ -637,12 +953,12 @@ __global__ void k_reduce(const GridDev* grids, int n_bins) {
 
 long long workspace_doubles(int Lmax, int kmax) {
   const long long L2 = (long long)Lmax * Lmax;
-  long long w = 4 * L2 + 4LL * Lmax * kmax + 256;
+  long long w = 4 * L2 + 256;
+  if (kmax > 1) w += 4LL * kMaxK * kWin + 4LL * Lmax * kMaxK;
   return (w + 63) & ~63LL;
 }
 
 int lds_bytes(int Lmax, int mode, int k, int b, int* lu_nb, int* scratch_bytes) {
-  (void)mode;
   (void)k;
   (void)b;
   int nb = 12288 / (Lmax > 0 ? Lmax : 1);
@@ -650,8 +966,20 @@ int lds_bytes(int Lmax, int mode, int k, int b, int* lu_nb, int* scratch_bytes) 
   if (nb < 4) nb = 4;
   *lu_nb = nb;
   const long long lu = (long long)Lmax * (nb + 1) * 8 + 64 * 4;
-  const long long r1 = 4LL * Lmax * 8;
-  long long sc = lu > r1 ? lu : r1;
+  long long sc = lu;
+  if (mode == MODE_RANK1) {
+    const long long r1 = 4LL * Lmax * 8;
+    sc = sc > r1 ? sc : r1;
+  } else {
+    const long long win = kSmall + (2LL * kWin * kWP + 4LL * kWin) * 8;
+    const long long ul = kSmall + 2LL * kMaxK * kKP * 8;
+    const long long t64 = kSmall + 2LL * kMaxK * kTP * 8;
+    const long long t32 = kSmall + (1LL * kTile * kXS + 1LL * kMaxK * kYS) * 4;
+    long long w = win > ul ? win : ul;
+    w = w > t64 ? w : t64;
+    w = w > t32 ? w : t32;
+    sc = sc > w ? sc : w;
+  }
   sc = (sc + 15) & ~15LL;
   *scratch_bytes = (int)sc;
   const long long head = ((Lmax + 15) & ~15) + (long long)Lmax * 8 + 64 * 8;
