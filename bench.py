@@ -176,6 +176,10 @@ def main():
         "rank1_fp64": rank1,
         "cpu_baseline": cpu,
         "checks": checks,
+        "phases_chain_s": {k: st[k] for k in ("chain_s_sweep", "chain_s_flush",
+                                              "chain_s_recompute", "chain_s_measure",
+                                              "chain_s_lu_build", "chain_s_lu_panel",
+                                              "chain_s_lu_strip", "chain_s_lu_back")},
     }
     print(json.dumps(line), flush=True)
 

@@ -96,6 +96,13 @@ typedef struct {
   double seconds_total;     /* wall time of the call */
   double seconds_kernel;    /* HIP-event time of the persistent sweep kernel */
   int64_t n_proposed, n_accepted, n_recomputes, n_bad_ratio, n_singular;
+  /* per-phase time inside the sweep kernel, summed over chains (chain-seconds,
+     from the device wall clock): sweeping excluding flushes and recomputes,
+     delayed-update flushes, Dyson recomputes (initial ones included), measurement */
+  double chain_s_sweep, chain_s_flush, chain_s_recompute, chain_s_measure;
+  /* recompute breakdown (chain-seconds): matrix build, panel factorizations,
+     forward strip passes, back substitution + copy */
+  double chain_s_lu_build, chain_s_lu_panel, chain_s_lu_strip, chain_s_lu_back;
   int32_t delay_k;          /* k actually used (delayed modes) */
   int32_t recompute_every;  /* recompute interval actually used */
   int32_t n_workgroups;     /* persistent workgroups launched */

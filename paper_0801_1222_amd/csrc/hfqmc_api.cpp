@@ -81,6 +81,7 @@ struct hfqmc_ctx {
   hipStream_t stream = nullptr;
   int n_cu = 0;
   int lds_max = 0;  // bytes of LDS a workgroup may allocate
+  double wall_hz = 1e8;  // device wall-clock rate
   DevBuf work;
   DevBuf arena;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -105,6 +106,11 @@ extern "C" int hfqmc_create(hfqmc_ctx** out, int device) {
   c->device = device;
   c->n_cu = prop.multiProcessorCount;
   c->lds_max = (int)prop.sharedMemPerBlock;
+  {
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && khz > 0)
+      c->wall_hz = khz * 1e3;
+  }
   if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
     delete c;
     return fail(HFQMC_EDEVICE, "hfqmc_create: hipEventCreate failed");
@@ -368,6 +374,15 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
       gs.n_recomputes += s[ST_RECOMPUTES];
       gs.n_bad_ratio += s[ST_BAD];
       gs.n_singular += s[ST_SINGULAR];
+      const double f = 1.0 / c->wall_hz;
+      gs.chain_s_sweep += s[ST_T_SWEEP] * f;
+      gs.chain_s_flush += s[ST_T_FLUSH] * f;
+      gs.chain_s_recompute += s[ST_T_REC] * f;
+      gs.chain_s_measure += s[ST_T_MEAS] * f;
+      gs.chain_s_lu_build += s[ST_T_LU_BUILD] * f;
+      gs.chain_s_lu_panel += s[ST_T_LU_PANEL] * f;
+      gs.chain_s_lu_strip += s[ST_T_LU_STRIP] * f;
+      gs.chain_s_lu_back += s[ST_T_LU_BACK] * f;
       gdrift = std::max(gdrift, cdr[ch]);
       if (!(cdr[ch] == cdr[ch])) gdrift = INFINITY;
       if (opts->flip_count) opts->flip_count[cb + ch] = s[ST_FLIPS];
@@ -384,6 +399,14 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
     tot.n_recomputes += gs.n_recomputes;
     tot.n_bad_ratio += gs.n_bad_ratio;
     tot.n_singular += gs.n_singular;
+    tot.chain_s_sweep += gs.chain_s_sweep;
+    tot.chain_s_flush += gs.chain_s_flush;
+    tot.chain_s_recompute += gs.chain_s_recompute;
+    tot.chain_s_measure += gs.chain_s_measure;
+    tot.chain_s_lu_build += gs.chain_s_lu_build;
+    tot.chain_s_lu_panel += gs.chain_s_lu_panel;
+    tot.chain_s_lu_strip += gs.chain_s_lu_strip;
+    tot.chain_s_lu_back += gs.chain_s_lu_back;
     max_drift = std::max(max_drift, gdrift);
     for (int k = 0; k <= L; ++k)
       if (!std::isfinite(g_tau[goff + k])) numeric_bad = true;

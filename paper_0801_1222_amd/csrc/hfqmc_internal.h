@@ -14,7 +14,15 @@ enum {
   ST_SINGULAR = 4,  // zero or non-finite pivots met in a Dyson recompute
   ST_FLIPS = 5,     // entries written to the flip log (may exceed its capacity)
   ST_REPLAYED = 6,  // replay entries consumed
-  NSTAT = 8
+  ST_T_SWEEP = 8,   // wall-clock ticks spent in sweeps, flushes and recomputes excluded
+  ST_T_FLUSH = 9,   // ... in delayed-update flushes
+  ST_T_REC = 10,    // ... in Dyson recomputes (initial ones included)
+  ST_T_MEAS = 11,   // ... in measurements
+  ST_T_LU_BUILD = 12,  // recompute breakdown: building [M | G0]
+  ST_T_LU_PANEL = 13,  // ... panel factorizations
+  ST_T_LU_STRIP = 14,  // ... forward strip passes (interchanges, U12, trailing update)
+  ST_T_LU_BACK = 15,   // ... back substitution and the copy into G
+  NSTAT = 16
 };
 
 enum { MODE_RANK1 = 0, MODE_DELAYED_FP64 = 1, MODE_MIXED = 2 };

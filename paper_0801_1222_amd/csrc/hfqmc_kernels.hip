@@ -159,230 +159,454 @@ struct Chain {
   double* red;     // reduction scratch, LDS
 };
 
+struct Counters {
+  long long n_prop, n_acc, n_rec, n_bad, n_flips, rep_i;
+  double drift;
+  int acc_since;
+  int singular;
+  long long t_sweep, t_flush, t_rec, t_meas;        // constant-rate wall-clock ticks
+  long long t_lu_build, t_lu_panel, t_lu_strip, t_lu_back;
+};
+
 // ------------------------------------------------ Dyson recompute (LU) ----
 //
 // Solve [1 + (1 - G0) diag(e^{V_sigma} - 1)] G_sigma = G0 for one spin with
-// the augmented matrix A = [M | G0] (L x 2L, row-major, in the workspace):
-// right-looking blocked LU with partial pivoting (panel of width nb held in
-// LDS and factorized by wave 0), forward elimination applied to the
-// right-hand side columns in the same trailing updates, then blocked back
-// substitution.  Writes the new G into Gs and returns the largest
-// elementwise change (drift) against the G it replaces.
+// the augmented matrix A = [M | G0] in the workspace, padded to np = a
+// multiple of the panel width NB (identity rows/columns and zero right-hand
+// sides in the padding, which never become pivots).  Right-looking blocked
+// LU with partial pivoting, then blocked back substitution:
+//   panel   all waves; each thread keeps its panel rows in registers, one
+//           pivot search (workgroup argmax) and one row exchange per column;
+//           L11, U11 and L21 end in LDS, U11 also in A;
+//   strip   each thread owns a column pair right of the panel: row
+//           interchanges, U12 = L11^{-1} A12 in registers, then
+//           A22 -= L21 U12 streamed over the trailing rows (right-hand side
+//           included) in prefetched chunks;
+//   back    per block from the bottom: X_b = U11^{-1} Y_b in registers, then
+//           Y_above -= U01 X_b streamed the same way.
+// Writes the new G into Gs and returns the largest elementwise change
+// (drift) against the G it replaces.
 
-// C[i][c] -= sum_j P[i - prow0][j] * A[brow + j][c] for i in [r0, r1), c in [c0, c1).
-// P (LDS, row stride ps) holds the left operand; the B rows must not overlap C.
-__device__ void lu_gemm_sub(double* __restrict__ A, int lda, int r0, int r1, int c0, int c1,
-                            const double* __restrict__ P, int ps, int prow0, int brow, int nb) {
-  // each thread owns column pairs (c, c+1), all lanes walk the same rows so the
-  // P reads are LDS broadcasts
-  for (int c = c0 + 2 * threadIdx.x; c < c1; c += 2 * kThreads) {
-    const bool two = (c + 1) < c1;
-    double u0[kNBMax], u1[kNBMax];
+constexpr int kRowChunk = 4;   // rows in flight per thread in the strip passes
+
+// C[i][c] -= sum_j Q[i - qrow0][j] * u[j] for i in [r0, r1); Q in LDS (row stride qs,
+// 16-byte aligned rows, read as broadcast pairs).
+template <int NB>
+__device__ __forceinline__ void strip_stream(double* __restrict__ A, int lda, int r0, int r1, int c,
+                                             const double* __restrict__ Q, int qs, int qrow0,
+                                             const double (&u)[NB]) {
+  double cur[kRowChunk], nxt[kRowChunk];
 #pragma unroll
-    for (int j = 0; j < kNBMax; ++j) {
-      if (j < nb) {
-        const double* b = A + (long long)(brow + j) * lda + c;
-        u0[j] = b[0];
-        u1[j] = two ? b[1] : 0.0;
+  for (int b = 0; b < kRowChunk; ++b)
+    if (r0 + b < r1) cur[b] = A[(r0 + b) * lda + c];
+#pragma unroll 1
+  for (int i0 = r0; i0 < r1; i0 += kRowChunk) {
+    const int i1 = i0 + kRowChunk;
+#pragma unroll
+    for (int b = 0; b < kRowChunk; ++b)
+      if (i1 + b < r1) nxt[b] = A[(i1 + b) * lda + c];
+#pragma unroll
+    for (int b = 0; b < kRowChunk; ++b) {
+      const int i = i0 + b;
+      if (i < r1) {
+        const double2* q2 = reinterpret_cast<const double2*>(Q + (i - qrow0) * qs);
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int jj = 0; jj < NB / 2; ++jj) {
+          const double2 qv = q2[jj];
+          s0 = fma(qv.x, u[2 * jj], s0);
+          s1 = fma(qv.y, u[2 * jj + 1], s1);
+        }
+        A[i * lda + c] = cur[b] - (s0 + s1);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int b = 0; b < kRowChunk; ++b) cur[b] = nxt[b];
+  }
+}
+
+// Forward strip after the panel at kb: per column c right of the panel, apply
+// the row interchanges, U12 = L11^{-1} A12 in registers, then A22 -= L21 U12.
+// P holds the factored panel rows (stride ps).
+template <int NB>
+__device__ __forceinline__ void lu_strip_forward(double* __restrict__ A, int lda, int kb, int np,
+                                                 int cend, const double* __restrict__ P, int ps,
+                                                 const int* __restrict__ piv) {
+  for (int c = kb + NB + (int)threadIdx.x; c < cend; c += kThreads) {
+#pragma unroll 1
+    for (int j = 0; j < NB; ++j) {
+      const int pj = piv[j];
+      if (pj != j) {
+        double* a = A + (kb + j) * lda + c;
+        double* b = A + (kb + pj) * lda + c;
+        const double tmp = *a;
+        *a = *b;
+        *b = tmp;
       }
     }
-    for (int i = r0; i < r1; ++i) {
-      const double* p = P + (i - prow0) * ps;
-      double* a = A + (long long)i * lda + c;
-      double s0 = 0.0, s1 = 0.0;
+    double u[NB];
 #pragma unroll
-      for (int j = 0; j < kNBMax; ++j) {
-        if (j < nb) {
-          const double pj = p[j];
-          s0 = fma(pj, u0[j], s0);
-          s1 = fma(pj, u1[j], s1);
-        }
-      }
-      a[0] -= s0;
-      if (two) a[1] -= s1;
+    for (int j = 0; j < NB; ++j) u[j] = A[(kb + j) * lda + c];
+#pragma unroll
+    for (int j = 0; j < NB - 1; ++j) {
+#pragma unroll
+      for (int r = j + 1; r < NB; ++r) u[r] = fma(-P[r * ps + j], u[j], u[r]);
+      // one column of L11 at a time: hoisting all its LDS reads would spill
+      __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int j = 1; j < NB; ++j) A[(kb + j) * lda + c] = u[j];
+    strip_stream<NB>(A, lda, kb + NB, np, c, P, ps, kb, u);
+  }
+}
+
+// Backward strip for the block at kb: per right-hand-side column, X_b =
+// U11^{-1} Y_b in registers, then Y[0:kb] -= U01 X_b.  P rows 0..kb-1 hold
+// U01, rows kb..kb+NB-1 hold U11 (stride ps).
+template <int NB>
+__device__ __forceinline__ void lu_strip_backward(double* __restrict__ A, int lda, int kb, int np,
+                                                  int cend, const double* __restrict__ P, int ps) {
+  for (int c = np + (int)threadIdx.x; c < cend; c += kThreads) {
+    double u[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) u[j] = A[(kb + j) * lda + c];
+#pragma unroll
+    for (int j = NB - 1; j >= 0; --j) {
+      u[j] = u[j] / P[(kb + j) * ps + j];
+#pragma unroll
+      for (int r = 0; r < j; ++r) u[r] = fma(-P[(kb + r) * ps + j], u[j], u[r]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) A[(kb + j) * lda + c] = u[j];
+    strip_stream<NB>(A, lda, 0, kb, c, P, ps, 0, u);
+  }
+}
+
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+// Orders a wave's global stores before its later loads of the same data by
+// other lanes (the workgroup shares one L1).
+__device__ __forceinline__ void wave_global_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Strip passes on the matrix cores (NB = 16 or 32).  v_mfma_f64_16x16x4f64
+// operand layout, lane l = 16 q + i:  A[i][k=q], B[k=q][j=i], D[4 r + q][i]
+// (register r of the accumulator; note the f32 16x16x4 variant uses D[4 q + r][i]).
+// Each wave owns 16-column tiles; its B operand (NB x 16) stays in registers
+// while the trailing 16-row blocks stream through the accumulators.
+//
+// Forward, panel at kb: U12 = L11^{-1} A12 (Li = L11^{-1} in LDS, stride ls),
+// then A22 -= L21 U12 with L21 = P rows NB.. (stride ps).  Row interchanges
+// must already be applied.
+template <int NB>
+__device__ __forceinline__ void lu_strip_forward_mfma(double* __restrict__ A, int lda, int kb,
+                                                      int np, int cend16,
+                                                      const double* __restrict__ P, int ps,
+                                                      const double* __restrict__ Li, int ls) {
+  constexpr int KS = NB / 4;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int li = lane & 15, lq = lane >> 4;
+  for (int c0 = kb + NB + 16 * wv; c0 < cend16; c0 += 16 * (kThreads / 64)) {
+    const int c = c0 + li;
+    double b[KS];
+#pragma unroll
+    for (int m = 0; m < KS; ++m) b[m] = A[(kb + 4 * m + lq) * lda + c];
+#pragma unroll
+    for (int ob = 0; ob < NB / 16; ++ob) {
+      doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int m = 0; m < KS; ++m)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Li[(16 * ob + li) * ls + 4 * m + lq], b[m], acc,
+                                                   0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) A[(kb + 16 * ob + 4 * r + lq) * lda + c] = acc[r];
+    }
+    wave_global_sync();
+#pragma unroll
+    for (int m = 0; m < KS; ++m) b[m] = A[(kb + 4 * m + lq) * lda + c];
+#pragma unroll 1
+    for (int r0 = kb + NB; r0 < np; r0 += 16) {
+      double* cp = A + (r0 + lq) * lda + c;
+      doublex4 acc;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[r] = cp[4 * r * lda];
+      const double* pa = P + (r0 - kb + li) * ps + lq;
+#pragma unroll
+      for (int m = 0; m < KS; ++m)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-pa[4 * m], b[m], acc, 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) cp[4 * r * lda] = acc[r];
     }
   }
 }
 
-__device__ double dyson_recompute(const Chain& ch, int sigma, double* __restrict__ Gs,
-                                  int nbmax, int* singular) {
+// Backward, block at kb: X_b = U11^{-1} Y_b (Li = U11^{-1}), then
+// Y[0:kb] -= U01 X_b with U01 = P rows 0..kb-1.
+template <int NB>
+__device__ __forceinline__ void lu_strip_backward_mfma(double* __restrict__ A, int lda, int kb,
+                                                       int np, int cend16,
+                                                       const double* __restrict__ P, int ps,
+                                                       const double* __restrict__ Li, int ls) {
+  constexpr int KS = NB / 4;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int li = lane & 15, lq = lane >> 4;
+  for (int c0 = np + 16 * wv; c0 < cend16; c0 += 16 * (kThreads / 64)) {
+    const int c = c0 + li;
+    double b[KS];
+#pragma unroll
+    for (int m = 0; m < KS; ++m) b[m] = A[(kb + 4 * m + lq) * lda + c];
+#pragma unroll
+    for (int ob = 0; ob < NB / 16; ++ob) {
+      doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int m = 0; m < KS; ++m)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Li[(16 * ob + li) * ls + 4 * m + lq], b[m], acc,
+                                                   0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) A[(kb + 16 * ob + 4 * r + lq) * lda + c] = acc[r];
+    }
+    wave_global_sync();
+#pragma unroll
+    for (int m = 0; m < KS; ++m) b[m] = A[(kb + 4 * m + lq) * lda + c];
+#pragma unroll 1
+    for (int r0 = 0; r0 < kb; r0 += 16) {
+      double* cp = A + (r0 + lq) * lda + c;
+      doublex4 acc;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[r] = cp[4 * r * lda];
+      const double* pa = P + (r0 + li) * ps + lq;
+#pragma unroll
+      for (int m = 0; m < KS; ++m)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-pa[4 * m], b[m], acc, 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) cp[4 * r * lda] = acc[r];
+    }
+  }
+}
+
+__device__ __forceinline__ double dyson_recompute(const Chain& ch, int sigma,
+                                                  double* __restrict__ Gs, int NB, Counters& k) {
   const int n = ch.L;
-  const int lda = 2 * n;
+  const int np = (n + NB - 1) / NB * NB;
+  const int lda = 2 * np;
+  const int ps = NB + 2;              // LDS row stride of the panel (16-byte aligned rows)
+  // right-hand-side columns beyond n stay zero and are skipped (up to the
+  // next multiple of 16 on the matrix-core path, which works in 16-column tiles)
+  const int cend = np + n;
+  const int cend16 = np + ((n + 15) & ~15);
   double* __restrict__ A = ch.A;
   const double* __restrict__ G0 = ch.G0;
   const double ep = ch.ep, em = ch.em;
   const int8_t* s = ch.s;
+  const int t = threadIdx.x;
+  const int lane = t & 63, wv = t >> 6;
+  long long tc = wall_clock64();
 
-  // build [M | G0]; M[i][j] = delta_ij + (delta_ij - G0[i][j]) f_j, f_j = e^{V_sigma(j)} - 1
-  for (long long idx = threadIdx.x; idx < (long long)n * n; idx += kThreads) {
-    const int i = (int)(idx / n), j = (int)(idx - (long long)i * n);
-    const double g0 = G0[idx];
-    const double f = (sigma * s[j] > 0) ? ep : em;
-    const double dij = (i == j) ? 1.0 : 0.0;
-    A[(long long)i * lda + j] = axpy_nc(dij, dij - g0, f);
-    A[(long long)i * lda + n + j] = g0;
+  // [M | G0] with M[i][j] = delta_ij + (delta_ij - G0[i][j]) f_j, f_j = e^{V_sigma(j)} - 1
+  for (int idx = t; idx < np * np; idx += kThreads) {
+    const int i = idx / np, j = idx - i * np;
+    double m, r;
+    if (i < n && j < n) {
+      const double g0 = G0[i * n + j];
+      const double f = (sigma * s[j] > 0) ? ep : em;
+      const double dij = (i == j) ? 1.0 : 0.0;
+      m = axpy_nc(dij, dij - g0, f);
+      r = g0;
+    } else {
+      m = (i == j) ? 1.0 : 0.0;
+      r = 0.0;
+    }
+    A[i * lda + j] = m;
+    A[i * lda + np + j] = r;
   }
-  __syncthreads();
 
-  double* P = reinterpret_cast<double*>(ch.scratch);
-  int* piv = reinterpret_cast<int*>(P + (long long)n * (nbmax + 1));
+  double* P = reinterpret_cast<double*>(ch.scratch);     // [np][ps]
+  const int ls = NB + 1;
+  double* Li = P + np * ps;                              // [NB][ls] inverted diagonal triangle
+  double* redv = Li + NB * ls;                           // [kThreads/64]
+  int* redi = reinterpret_cast<int*>(redv + kThreads / 64);
+  int* piv = redi + kThreads / 64;                       // [NB]
   __shared__ int s_sing;
-  if (threadIdx.x == 0) s_sing = 0;
-
-  for (int kb = 0; kb < n; kb += nbmax) {
-    const int nb = min(nbmax, n - kb);
-    const int rows = n - kb;
-    const int ps = nb + 1;
-    // panel -> LDS
-    for (int idx = threadIdx.x; idx < rows * nb; idx += kThreads) {
-      const int r = idx / nb, c = idx - r * nb;
-      P[r * ps + c] = A[(long long)(kb + r) * lda + kb + c];
-    }
-    __syncthreads();
-    // unblocked LU of the panel by wave 0
-    if (threadIdx.x < 64) {
-      const int lane = threadIdx.x;
-      for (int j = 0; j < nb; ++j) {
-        double best = -1.0;
-        int bi = rows;
-        for (int r = j + lane; r < rows; r += 64) {
-          const double v = fabs(P[r * ps + j]);
-          if (v > best) {
-            best = v;
-            bi = r;
-          }
-        }
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-          const double ob = __shfl_xor(best, o, 64);
-          const int oi = __shfl_xor(bi, o, 64);
-          if (ob > best || (ob == best && oi < bi)) {
-            best = ob;
-            bi = oi;
-          }
-        }
-        if (bi >= rows) bi = j;
-        if (lane == 0) piv[j] = bi;
-        if (bi != j) {
-          for (int c = lane; c < nb; c += 64) {
-            const double t = P[j * ps + c];
-            P[j * ps + c] = P[bi * ps + c];
-            P[bi * ps + c] = t;
-          }
-        }
-        wave_sync();
-        const double p = P[j * ps + j];
-        if (lane == 0 && !(fabs(p) > 0.0 && fabs(p) < INFINITY)) s_sing = 1;
-        for (int r = j + 1 + lane; r < rows; r += 64) {
-          const double l = P[r * ps + j] / p;
-          P[r * ps + j] = l;
-          for (int c = j + 1; c < nb; ++c) P[r * ps + c] = fma(-l, P[j * ps + c], P[r * ps + c]);
-        }
-        wave_sync();
-      }
-    }
-    __syncthreads();
-    // row interchanges on the columns right of the panel, U11/L11 rows back to A
-    for (int c = kb + nb + threadIdx.x; c < lda; c += kThreads) {
-      for (int j = 0; j < nb; ++j) {
-        const int pj = piv[j];
-        if (pj != j) {
-          double* a = A + (long long)(kb + j) * lda + c;
-          double* b = A + (long long)(kb + pj) * lda + c;
-          const double t = *a;
-          *a = *b;
-          *b = t;
-        }
-      }
-    }
-    for (int idx = threadIdx.x; idx < nb * nb; idx += kThreads) {
-      const int r = idx / nb, c = idx - r * nb;
-      A[(long long)(kb + r) * lda + kb + c] = P[r * ps + c];
-    }
-    __syncthreads();
-    // U12 = L11^{-1} A12 (unit lower), one column per thread
-    for (int c = kb + nb + threadIdx.x; c < lda; c += kThreads) {
-      double v[kNBMax];
-#pragma unroll
-      for (int r = 0; r < kNBMax; ++r)
-        if (r < nb) v[r] = A[(long long)(kb + r) * lda + c];
-#pragma unroll
-      for (int r = 1; r < kNBMax; ++r) {
-        if (r < nb) {
-          double acc = v[r];
-#pragma unroll
-          for (int j = 0; j < kNBMax; ++j)
-            if (j < r) acc = fma(-P[r * ps + j], v[j], acc);
-          v[r] = acc;
-        }
-      }
-#pragma unroll
-      for (int r = 1; r < kNBMax; ++r)
-        if (r < nb) A[(long long)(kb + r) * lda + c] = v[r];
-    }
-    __syncthreads();
-    // trailing update of M and of the right-hand side
-    if (kb + nb < n)
-      lu_gemm_sub(A, lda, kb + nb, n, kb + nb, lda, P, ps, kb, kb, nb);
-    __syncthreads();
+  if (t == 0) s_sing = 0;
+  __syncthreads();
+  {
+    const long long t1 = wall_clock64();
+    k.t_lu_build += t1 - tc;
+    tc = t1;
   }
 
-  // back substitution U X = Y, block rows from the bottom
-  const int nblk = (n + nbmax - 1) / nbmax;
-  for (int bI = nblk - 1; bI >= 0; --bI) {
-    const int kb = bI * nbmax;
-    const int nb = min(nbmax, n - kb);
-    const int ps = nb + 1;
-    // U11 -> LDS
-    for (int idx = threadIdx.x; idx < nb * nb; idx += kThreads) {
-      const int r = idx / nb, c = idx - r * nb;
-      P[r * ps + c] = A[(long long)(kb + r) * lda + kb + c];
+  for (int kb = 0; kb < np; kb += NB) {
+    const int rows = np - kb;
+    // ---- panel rows kb.., columns kb..kb+NB-1 into LDS, factorized by all waves
+    for (int idx = t; idx < rows * NB; idx += kThreads) {
+      const int r = idx / NB, c = idx - r * NB;
+      P[r * ps + c] = A[(kb + r) * lda + kb + c];
     }
     __syncthreads();
-    for (int c = n + threadIdx.x; c < lda; c += kThreads) {
-      double v[kNBMax];
-#pragma unroll
-      for (int r = 0; r < kNBMax; ++r)
-        if (r < nb) v[r] = A[(long long)(kb + r) * lda + c];
-#pragma unroll
-      for (int r = kNBMax - 1; r >= 0; --r) {
-        if (r < nb) {
-          double acc = v[r];
-#pragma unroll
-          for (int j = 0; j < kNBMax; ++j)
-            if (j > r && j < nb) acc = fma(-P[r * ps + j], v[j], acc);
-          v[r] = acc / P[r * ps + r];
+#pragma unroll 1
+    for (int j = 0; j < NB; ++j) {
+      double best = -1.0;
+      int bi = 1 << 30;
+      for (int r = j + t; r < rows; r += kThreads) {
+        const double v = fabs(P[r * ps + j]);
+        if (v > best) {
+          best = v;
+          bi = r;
         }
       }
 #pragma unroll
-      for (int r = 0; r < kNBMax; ++r)
-        if (r < nb) A[(long long)(kb + r) * lda + c] = v[r];
-    }
-    __syncthreads();
-    if (kb > 0) {
-      // left operand U[0:kb, kb:kb+nb] -> LDS, then rows above -= U X_b
-      for (int idx = threadIdx.x; idx < kb * nb; idx += kThreads) {
-        const int r = idx / nb, c = idx - r * nb;
-        P[r * ps + c] = A[(long long)r * lda + kb + c];
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(best, o, 64);
+        const int oi = __shfl_xor(bi, o, 64);
+        if (ob > best || (ob == best && oi < bi)) {
+          best = ob;
+          bi = oi;
+        }
+      }
+      if (lane == 0) {
+        redv[wv] = best;
+        redi[wv] = bi;
       }
       __syncthreads();
-      lu_gemm_sub(A, lda, 0, kb, n, lda, P, ps, 0, kb, nb);
+      best = redv[0];
+      bi = redi[0];
+#pragma unroll
+      for (int w = 1; w < kThreads / 64; ++w) {
+        const double ob = redv[w];
+        const int oi = redi[w];
+        if (ob > best || (ob == best && oi < bi)) {
+          best = ob;
+          bi = oi;
+        }
+      }
+      if (bi >= rows) bi = j;   // no finite candidate: keep the row, flagged below
+      if (t == 0) piv[j] = bi;
+      if (bi != j && t < NB) {
+        const double tmp = P[j * ps + t];
+        P[j * ps + t] = P[bi * ps + t];
+        P[bi * ps + t] = tmp;
+      }
+      __syncthreads();
+      const double pv = P[j * ps + j];
+      if (t == 0 && !(fabs(pv) > 0.0 && fabs(pv) < INFINITY)) s_sing = 1;
+      for (int r = j + 1 + t; r < rows; r += kThreads) {
+        double* pr = P + r * ps;
+        const double l = pr[j] / pv;
+        pr[j] = l;
+        for (int c = j + 1; c < NB; ++c) pr[c] = fma(-l, P[j * ps + c], pr[c]);
+      }
       __syncthreads();
     }
+    // U11 -> A for the back substitution
+    for (int idx = t; idx < NB * NB; idx += kThreads) {
+      const int r = idx / NB, c = idx - r * NB;
+      if (c >= r) A[(kb + r) * lda + kb + c] = P[r * ps + c];
+    }
+    {
+      const long long t1 = wall_clock64();
+      k.t_lu_panel += t1 - tc;
+      tc = t1;
+    }
+    // ---- strip: interchanges, U12, trailing update (RHS included)
+    if (NB >= 16) {
+      // row interchanges right of the panel, one column per thread
+      for (int c = kb + NB + t; c < cend16; c += kThreads) {
+#pragma unroll 1
+        for (int j = 0; j < NB; ++j) {
+          const int pj = piv[j];
+          if (pj != j) {
+            double* a = A + (kb + j) * lda + c;
+            double* b = A + (kb + pj) * lda + c;
+            const double tmp = *a;
+            *a = *b;
+            *b = tmp;
+          }
+        }
+      }
+      // Li = L11^{-1} (unit lower), one column per lane of wave 0
+      if (t < NB) {
+        const int j = t;
+#pragma unroll 1
+        for (int r = 0; r < NB; ++r) {
+          double x = (r == j) ? 1.0 : 0.0;
+#pragma unroll 1
+          for (int q = j; q < r; ++q) x = fma(-P[r * ps + q], Li[q * ls + j], x);
+          Li[r * ls + j] = x;
+        }
+      }
+      __syncthreads();
+      if (NB == 32)
+        lu_strip_forward_mfma<32>(A, lda, kb, np, cend16, P, ps, Li, ls);
+      else
+        lu_strip_forward_mfma<16>(A, lda, kb, np, cend16, P, ps, Li, ls);
+    } else {
+      switch (NB) {
+        case 8: lu_strip_forward<8>(A, lda, kb, np, cend, P, ps, piv); break;
+        default: lu_strip_forward<4>(A, lda, kb, np, cend, P, ps, piv); break;
+      }
+    }
+    __syncthreads();
+    {
+      const long long t1 = wall_clock64();
+      k.t_lu_strip += t1 - tc;
+      tc = t1;
+    }
+  }
+
+  // ---- back substitution on the right-hand-side columns, block rows from the bottom
+  for (int kb = np - NB; kb >= 0; kb -= NB) {
+    for (int idx = t; idx < (kb + NB) * NB; idx += kThreads) {
+      const int r = idx / NB, c = idx - r * NB;
+      P[r * ps + c] = A[r * lda + kb + c];
+    }
+    __syncthreads();
+    if (NB >= 16) {
+      // Li = U11^{-1} (upper), one column per lane of wave 0
+      if (t < NB) {
+        const int j = t;
+#pragma unroll 1
+        for (int r = NB - 1; r >= 0; --r) {
+          double x = 0.0;
+          if (r <= j) {
+            x = (r == j) ? 1.0 : 0.0;
+#pragma unroll 1
+            for (int q = r + 1; q <= j; ++q) x = fma(-P[(kb + r) * ps + q], Li[q * ls + j], x);
+            x = x / P[(kb + r) * ps + r];
+          }
+          Li[r * ls + j] = x;
+        }
+      }
+      __syncthreads();
+      if (NB == 32)
+        lu_strip_backward_mfma<32>(A, lda, kb, np, cend16, P, ps, Li, ls);
+      else
+        lu_strip_backward_mfma<16>(A, lda, kb, np, cend16, P, ps, Li, ls);
+    } else {
+      switch (NB) {
+        case 8: lu_strip_backward<8>(A, lda, kb, np, cend, P, ps); break;
+        default: lu_strip_backward<4>(A, lda, kb, np, cend, P, ps); break;
+      }
+    }
+    __syncthreads();
   }
 
   // G <- X, drift against the updated G
   double dmax = 0.0;
-  for (long long idx = threadIdx.x; idx < (long long)n * n; idx += kThreads) {
-    const int i = (int)(idx / n), j = (int)(idx - (long long)i * n);
-    const double x = A[(long long)i * lda + n + j];
+  for (int idx = t; idx < n * n; idx += kThreads) {
+    const int i = idx / n, j = idx - i * n;
+    const double x = A[i * lda + np + j];
     dmax = fmax(dmax, fabs(x - Gs[idx]));
     if (!(fabs(x) < INFINITY)) dmax = INFINITY;
     Gs[idx] = x;
   }
   dmax = block_max(dmax, ch.red);
-  if (s_sing) *singular = 1;
+  if (s_sing) k.singular = 1;
   __syncthreads();
+  k.t_lu_back += wall_clock64() - tc;
   return dmax;
 }
 
@@ -391,7 +615,7 @@ __device__ double dyson_recompute(const Chain& ch, int sigma, double* __restrict
 // (sgn = -1 where l + k wraps) and D = (1/L) sum_l (1 - Gu_ll)(1 - Gd_ll)
 // into the chain's bin.  Thread k walks rows i and reads G(i, (i-k) mod L),
 // so every step of a wave reads one contiguous stretch of a row.
-__device__ void measure(const Chain& ch, int bin) {
+__device__ __forceinline__ void measure(const Chain& ch, int bin) {
   const int L = ch.L;
   double* accg = ch.accg;
   for (int k = threadIdx.x; k < L; k += kThreads) {
@@ -426,12 +650,6 @@ __device__ void measure(const Chain& ch, int bin) {
 
 // ---------------------------------------------------------- proposals ----
 
-struct Counters {
-  long long n_prop, n_acc, n_rec, n_bad, n_flips, rep_i;
-  double drift;
-  int acc_since;
-  int singular;
-};
 
 // Metropolis decision for flipping s_l, evaluated identically by every thread
 // of the workgroup (uniform branch).  In replay mode the decision is read from
@@ -475,26 +693,37 @@ __device__ __forceinline__ void log_flip(const ChainIO& io, Counters& k, long lo
   ++k.n_flips;
 }
 
-__device__ void recompute_both(const SweepParams& p, const Chain& ch, Counters& k) {
-  const double d1 = dyson_recompute(ch, +1, ch.Gu, p.lu_nb, &k.singular);
-  const double d2 = dyson_recompute(ch, -1, ch.Gd, p.lu_nb, &k.singular);
-  k.drift = fmax(k.drift, fmax(d1, d2));
-  ++k.n_rec;
+// Dyson recompute of both spins (the kernel's only call site of the LU, so it
+// is inlined once).  The initial recompute of a chain is not counted as one.
+__device__ __forceinline__ void recompute_both(const SweepParams& p, const Chain& ch, Counters& k,
+                                               bool counted) {
+  const long long t0 = wall_clock64();
+  double d = 0.0;
+#pragma unroll 1
+  for (int sp = 0; sp < 2; ++sp)
+    d = fmax(d, dyson_recompute(ch, sp ? -1 : +1, sp ? ch.Gd : ch.Gu, p.lu_nb, k));
+  if (counted) {
+    k.drift = fmax(k.drift, d);
+    ++k.n_rec;
+  }
   k.acc_since = 0;
+  k.t_rec += wall_clock64() - t0;
 }
 
 // ------------------------------------------------- plain rank-1 sweep ----
 // Every accepted flip applies G <- G + (G(:,l) - e_l)(gamma/R_sigma) G(l,:) to
 // both L x L matrices in HBM: 32 L^2 bytes of traffic per accepted flip.
-__device__ void sweep_rank1(const SweepParams& p, const Chain& ch, long long sw, Counters& k,
-                            const ChainIO& io) {
+// Processes slices l_begin.. of sweep sw; returns early (next slice) when a
+// recompute is due, else L.
+__device__ __forceinline__ int sweep_rank1(const SweepParams& p, const Chain& ch, long long sw,
+                                           Counters& k, const ChainIO& io, int l_begin) {
   const int L = ch.L;
   const long long L2 = (long long)L * L;
   double* xu = reinterpret_cast<double*>(ch.scratch);
   double* xd = xu + p.Lmax;
   double* yu = xd + p.Lmax;
   double* yd = yu + p.Lmax;
-  for (int l = 0; l < L; ++l) {
+  for (int l = l_begin; l < L; ++l) {
     const long long dl = (long long)l * L + l;
     const int sl = ch.s[l];
     const Flip f = propose(ch.Gu[dl], ch.Gd[dl], sl, io.gp, io.gm, ch.u[l], io.rlog, io.rlen,
@@ -540,8 +769,9 @@ __device__ void sweep_rank1(const SweepParams& p, const Chain& ch, long long sw,
     }
     if (threadIdx.x == 0) ch.s[l] = (int8_t)(-sl);
     __syncthreads();
-    if (++k.acc_since == p.n_rec) recompute_both(p, ch, k);
+    if (++k.acc_since == p.n_rec) return l + 1;
   }
+  return L;
 }
 
 // -------------------------------------------- windowed delayed update ----
@@ -574,7 +804,7 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 // G += X Y for one spin. X: [L][kMaxK] row-major, Y: [kMaxK][L] row-major, m used columns.
 template <bool MIXED>
-__device__ void flush_gemm(double* __restrict__ G, const double* __restrict__ X,
+__device__ __forceinline__ void flush_gemm(double* __restrict__ G, const double* __restrict__ X,
                            const double* __restrict__ Y, int L, int m, char* lds) {
   const int t = threadIdx.x;
   if constexpr (MIXED) {
@@ -659,7 +889,7 @@ __device__ void flush_gemm(double* __restrict__ G, const double* __restrict__ X,
 }
 
 template <bool MIXED>
-__device__ void flush_window(const Chain& ch, int l0, int m) {
+__device__ __forceinline__ void flush_window(const Chain& ch, int l0, int m) {
   const int L = ch.L;
   const int t = threadIdx.x;
   const int* F = reinterpret_cast<const int*>(ch.scratch);
@@ -715,14 +945,16 @@ __device__ void flush_window(const Chain& ch, int l0, int m) {
     }
   }
   __syncthreads();
-  flush_gemm<MIXED>(ch.Gu, X, Y, L, m, un);
-  flush_gemm<MIXED>(ch.Gd, X + (long long)L * kMaxK, Y + (long long)kMaxK * L, L, m, un);
+#pragma unroll 1
+  for (int sp = 0; sp < 2; ++sp)
+    flush_gemm<MIXED>(sp ? ch.Gd : ch.Gu, X + (long long)sp * L * kMaxK,
+                      Y + (long long)sp * kMaxK * L, L, m, un);
   __syncthreads();
 }
 
 template <bool MIXED>
-__device__ void sweep_window(const SweepParams& p, const Chain& ch, long long sw, Counters& k,
-                             const ChainIO& io) {
+__device__ __forceinline__ int sweep_window(const SweepParams& p, const Chain& ch, long long sw,
+                                            Counters& k, const ChainIO& io, int l_begin) {
   const int L = ch.L;
   const int t = threadIdx.x;
   int* F = reinterpret_cast<int*>(ch.scratch);
@@ -737,7 +969,7 @@ __device__ void sweep_window(const SweepParams& p, const Chain& ch, long long sw
   double* yd = xd + kWin;
   double* Xrec = ch.wbuf;
   double* Yrec = Xrec + 2 * kMaxK * kWin;
-  int l0 = 0;
+  int l0 = l_begin;
   while (l0 < L) {
     const int b = min(kWin, L - l0);
     for (int idx = t; idx < kWin * kWin; idx += kThreads) {
@@ -802,10 +1034,15 @@ __device__ void sweep_window(const SweepParams& p, const Chain& ch, long long sw
       }
       ++pos;
     }
-    if (m > 0) flush_window<MIXED>(ch, l0, m);
-    if (k.acc_since == p.n_rec) recompute_both(p, ch, k);
+    if (m > 0) {
+      const long long t0 = wall_clock64();
+      flush_window<MIXED>(ch, l0, m);
+      k.t_flush += wall_clock64() - t0;
+    }
     l0 += pos;
+    if (k.acc_since == p.n_rec) return l0;
   }
+  return L;
 }
 
 // ----------------------------------------------------------- the chain ----
@@ -824,7 +1061,10 @@ __device__ void run_chain(const SweepParams& p, const GridDev* gd, int chain, do
   ch.Gu = ws;
   ch.Gd = ws + L2;
   ch.A = ws + 2 * L2;
-  ch.wbuf = ws + 4 * L2;
+  {
+    const long long np = (L + p.lu_nb - 1) / p.lu_nb * p.lu_nb;
+    ch.wbuf = ch.A + 2 * np * np;  // after the padded L x 2L LU workspace
+  }
   ch.s = reinterpret_cast<int8_t*>(lds);
   const int s_bytes = (p.Lmax + 15) & ~15;
   ch.u = reinterpret_cast<double*>(lds + s_bytes);
@@ -842,9 +1082,7 @@ __device__ void run_chain(const SweepParams& p, const GridDev* gd, int chain, do
     ch.s[l] = uniform53(ch.key0, (uint64_t)gd->grid_id, (uint64_t)l, 0ull, 1ull) < 0.5 ? 1 : -1;
   __syncthreads();
 
-  Counters k = {0, 0, 0, 0, 0, 0, 0.0, 0, 0};
-  dyson_recompute(ch, +1, ch.Gu, p.lu_nb, &k.singular);
-  dyson_recompute(ch, -1, ch.Gd, p.lu_nb, &k.singular);
+  Counters k = {0, 0, 0, 0, 0, 0, 0.0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
 
   ChainIO io;
   io.flog = gd->flip_log ? gd->flip_log + (long long)chain * p.flip_cap : nullptr;
@@ -854,23 +1092,50 @@ __device__ void run_chain(const SweepParams& p, const GridDev* gd, int chain, do
   io.gp = gd->gp;
   io.gm = gd->gm;
 
+  // One loop drives the whole chain so that every phase has a single call
+  // site: recompute (initial, then whenever n_rec flips have been accepted,
+  // right after the flip that completes the count), sweep segments, and the
+  // measurement after each measured sweep.
   const long long total = p.warmup + p.sweeps;
-  for (long long sw = 0; sw < total; ++sw) {
-    for (int l = threadIdx.x; l < L; l += kThreads)
-      ch.u[l] = uniform53(ch.key0, (uint64_t)gd->grid_id, (uint64_t)l, (uint64_t)sw, 0ull);
-    __syncthreads();
-    if (p.mode == MODE_RANK1)
-      sweep_rank1(p, ch, sw, k, io);
-    else if (p.mode == MODE_MIXED)
-      sweep_window<true>(p, ch, sw, k, io);
-    else
-      sweep_window<false>(p, ch, sw, k, io);
-    if (sw >= p.warmup) {
-      const long long msw = sw - p.warmup;
-      const int bin = (int)((msw * nb) / p.sweeps);
-      measure(ch, bin);
+  long long sw = 0;
+  int l = 0;
+  bool need_rec = true, first = true;
+  for (;;) {
+    if (need_rec) {
+      recompute_both(p, ch, k, !first);
+      first = false;
+      need_rec = false;
     }
-    __syncthreads();
+    if (l >= L) {
+      if (sw >= p.warmup) {
+        const long long t1 = wall_clock64();
+        const long long msw = sw - p.warmup;
+        const int bin = (int)((msw * nb) / p.sweeps);
+        measure(ch, bin);
+        k.t_meas += wall_clock64() - t1;
+      }
+      __syncthreads();
+      ++sw;
+      l = 0;
+    }
+    if (sw >= total) break;
+    if (l == 0) {
+      for (int q = threadIdx.x; q < L; q += kThreads)
+        ch.u[q] = uniform53(ch.key0, (uint64_t)gd->grid_id, (uint64_t)q, (uint64_t)sw, 0ull);
+      __syncthreads();
+    }
+    const long long t0 = wall_clock64();
+    const long long f0 = k.t_flush;
+    int nl;
+    if (p.mode == MODE_RANK1)
+      nl = sweep_rank1(p, ch, sw, k, io, l);
+    else if (p.mode == MODE_MIXED)
+      nl = sweep_window<true>(p, ch, sw, k, io, l);
+    else
+      nl = sweep_window<false>(p, ch, sw, k, io, l);
+    k.t_sweep += (wall_clock64() - t0) - (k.t_flush - f0);
+    need_rec = (k.acc_since == p.n_rec);
+    l = nl;
   }
 
   if (threadIdx.x == 0) {
@@ -882,6 +1147,14 @@ __device__ void run_chain(const SweepParams& p, const GridDev* gd, int chain, do
     st[ST_SINGULAR] = k.singular;
     st[ST_FLIPS] = k.n_flips;
     st[ST_REPLAYED] = k.rep_i;
+    st[ST_T_SWEEP] = k.t_sweep;
+    st[ST_T_FLUSH] = k.t_flush;
+    st[ST_T_REC] = k.t_rec;
+    st[ST_T_MEAS] = k.t_meas;
+    st[ST_T_LU_BUILD] = k.t_lu_build;
+    st[ST_T_LU_PANEL] = k.t_lu_panel;
+    st[ST_T_LU_STRIP] = k.t_lu_strip;
+    st[ST_T_LU_BACK] = k.t_lu_back;
     gd->cdrift[chain] = k.drift;
   }
   if (gd->g_final) {
@@ -953,19 +1226,32 @@ __global__ void k_reduce(const GridDev* grids, int n_bins) {
 
 long long workspace_doubles(int Lmax, int kmax) {
   const long long L2 = (long long)Lmax * Lmax;
-  long long w = 4 * L2 + 256;
+  const long long Lp = Lmax + kNBMax;  // LU padding
+  long long w = 2 * L2 + 2 * Lp * Lp + 256;
   if (kmax > 1) w += 4LL * kMaxK * kWin + 4LL * Lmax * kMaxK;
   return (w + 63) & ~63LL;
+}
+
+// LU panel width: the widest of 32/16/8/4 whose padded LDS panel fits the budget.
+static int lu_panel(int Lmax, long long budget) {
+  const int cand[4] = {32, 16, 8, 4};
+  for (int q = 0; q < 4; ++q) {
+    const int nb = cand[q];
+    const long long np = (Lmax + nb - 1) / nb * nb;
+    if (np * (nb + 2) * 8 + (long long)nb * (nb + 1) * 8 + 1024 <= budget) return nb;
+  }
+  return 4;
 }
 
 int lds_bytes(int Lmax, int mode, int k, int b, int* lu_nb, int* scratch_bytes) {
   (void)k;
   (void)b;
-  int nb = 12288 / (Lmax > 0 ? Lmax : 1);
-  if (nb > kNBMax) nb = kNBMax;
-  if (nb < 4) nb = 4;
+  const long long head = ((Lmax + 15) & ~15) + (long long)Lmax * 8 + 64 * 8;
+  const long long budget = 150 * 1024 - head;
+  const int nb = lu_panel(Lmax, budget);
   *lu_nb = nb;
-  const long long lu = (long long)Lmax * (nb + 1) * 8 + 64 * 4;
+  const long long np = (Lmax + nb - 1) / nb * nb;
+  const long long lu = np * (nb + 2) * 8 + (long long)nb * (nb + 1) * 8 + 1024;
   long long sc = lu;
   if (mode == MODE_RANK1) {
     const long long r1 = 4LL * Lmax * 8;
@@ -982,7 +1268,6 @@ int lds_bytes(int Lmax, int mode, int k, int b, int* lu_nb, int* scratch_bytes) 
   }
   sc = (sc + 15) & ~15LL;
   *scratch_bytes = (int)sc;
-  const long long head = ((Lmax + 15) & ~15) + (long long)Lmax * 8 + 64 * 8;
   return (int)(head + sc);
 }
 
