@@ -15,6 +15,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "hfqmc_internal.h"
 
 namespace hfqmc {
@@ -299,6 +301,50 @@ __device__ __forceinline__ void wave_global_sync() {
 // Each wave owns 16-column tiles; its B operand (NB x 16) stays in registers
 // while the trailing 16-row blocks stream through the accumulators.
 //
+constexpr int kRB = 4;   // 16-row blocks in flight per wave
+
+// Rows [r0, r1) (multiples of 16) of the wave's 16-column tile at column
+// c = c0 + (lane & 15):  C -= Q B, Q = P rows (r - qrow0) (NB wide, stride ps),
+// B = the tile's NB x 16 operand held in registers in B layout.
+template <int NB>
+__device__ __forceinline__ void mfma_rows_update(double* __restrict__ A, int lda, int r0, int r1,
+                                                 int c, const double* __restrict__ P, int ps,
+                                                 int qrow0, const double (&b)[NB / 4]) {
+  const int lane = threadIdx.x & 63;
+  const int li = lane & 15, lq = lane >> 4;
+#pragma unroll 1
+  for (int rb = r0; rb < r1; rb += 16 * kRB) {
+    // blocks past r1 re-read the last block (in bounds) and are not stored
+    doublex4 acc[kRB];
+    double qa[kRB][NB / 4];
+#pragma unroll
+    for (int g = 0; g < kRB; ++g) {
+      const int rr = min(rb + 16 * g, r1 - 16);
+      const double* cp = A + (rr + lq) * lda + c;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[g][r] = cp[4 * r * lda];
+      const double* pa = P + (rr - qrow0 + li) * ps + lq;
+#pragma unroll
+      for (int m = 0; m < NB / 4; ++m) qa[g][m] = -pa[4 * m];
+    }
+#pragma unroll
+    for (int g = 0; g < kRB; ++g) {
+#pragma unroll
+      for (int m = 0; m < NB / 4; ++m)
+        acc[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(qa[g][m], b[m], acc[g], 0, 0, 0);
+    }
+#pragma unroll
+    for (int g = 0; g < kRB; ++g) {
+      const int rr = rb + 16 * g;
+      if (rr < r1) {
+        double* cp = A + (rr + lq) * lda + c;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) cp[4 * r * lda] = acc[g][r];
+      }
+    }
+  }
+}
+
 // Forward, panel at kb: U12 = L11^{-1} A12 (Li = L11^{-1} in LDS, stride ls),
 // then A22 -= L21 U12 with L21 = P rows NB.. (stride ps).  Row interchanges
 // must already be applied.
@@ -328,19 +374,7 @@ __device__ __forceinline__ void lu_strip_forward_mfma(double* __restrict__ A, in
     wave_global_sync();
 #pragma unroll
     for (int m = 0; m < KS; ++m) b[m] = A[(kb + 4 * m + lq) * lda + c];
-#pragma unroll 1
-    for (int r0 = kb + NB; r0 < np; r0 += 16) {
-      double* cp = A + (r0 + lq) * lda + c;
-      doublex4 acc;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) acc[r] = cp[4 * r * lda];
-      const double* pa = P + (r0 - kb + li) * ps + lq;
-#pragma unroll
-      for (int m = 0; m < KS; ++m)
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-pa[4 * m], b[m], acc, 0, 0, 0);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) cp[4 * r * lda] = acc[r];
-    }
+    mfma_rows_update<NB>(A, lda, kb + NB, np, c, P, ps, kb, b);
   }
 }
 
@@ -372,18 +406,137 @@ __device__ __forceinline__ void lu_strip_backward_mfma(double* __restrict__ A, i
     wave_global_sync();
 #pragma unroll
     for (int m = 0; m < KS; ++m) b[m] = A[(kb + 4 * m + lq) * lda + c];
+    mfma_rows_update<NB>(A, lda, 0, kb, c, P, ps, 0, b);
+  }
+}
+
+// Element j (uniform) of a register row, by a 5-level select tree.
+template <int NB>
+__device__ __forceinline__ double reg_pick(const double (&r)[NB], int j) {
+  double t[NB];
+#pragma unroll
+  for (int c = 0; c < NB; ++c) t[c] = r[c];
+#pragma unroll
+  for (int w = 1; w < NB; w <<= 1) {
+#pragma unroll
+    for (int c = 0; c + w < NB; c += 2 * w) t[c] = (j & w) ? t[c + w] : t[c];
+  }
+  return t[0];
+}
+
+// Panel factorization (partial pivoting) with the panel rows in registers:
+// thread t owns the physical rows t + q kThreads and tracks the position each
+// one currently occupies (row interchanges only swap positions).  Per column
+// one barrier: every wave's best candidate row is staged in LDS together with
+// its |pivot|, so after the barrier all threads know the winner and read the
+// pivot row directly (candidate slots are double-buffered across columns).
+// The factored rows go to P in position order (stride ps), U11 also to A;
+// piv[j] = position exchanged with j (relative to kb).
+template <int NB>
+__device__ __forceinline__ void panel_factor_regs(double* __restrict__ A, int lda, int kb, int rows,
+                                                  double* __restrict__ P, int ps,
+                                                  double* __restrict__ cand,
+                                                  double* __restrict__ redv, int* __restrict__ redi,
+                                                  int* __restrict__ piv, int* sing) {
+  constexpr int RPT = 512 / kThreads * (NB == 32 ? 1 : 2);
+  constexpr int NW = kThreads / 64;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  double pr[RPT][NB];
+  int pos[RPT];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int r = t + q * kThreads;
+    pos[q] = r;
+#pragma unroll
+    for (int c = 0; c < NB; ++c) pr[q][c] = (r < rows) ? A[(kb + r) * lda + kb + c] : 0.0;
+  }
 #pragma unroll 1
-    for (int r0 = 0; r0 < kb; r0 += 16) {
-      double* cp = A + (r0 + lq) * lda + c;
-      doublex4 acc;
+  for (int j = 0; j < NB; ++j) {
+    double best = -1.0;
+    int bpos = 1 << 30, bq = -1;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) acc[r] = cp[4 * r * lda];
-      const double* pa = P + (r0 + li) * ps + lq;
+    for (int q = 0; q < RPT; ++q) {
+      const double v = fabs(reg_pick<NB>(pr[q], j));
+      if (pos[q] >= j && pos[q] < rows && (v > best || (v == best && pos[q] < bpos))) {
+        best = v;
+        bpos = pos[q];
+        bq = q;
+      }
+    }
+    double wb = best;
+    int wp = bpos;
 #pragma unroll
-      for (int m = 0; m < KS; ++m)
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-pa[4 * m], b[m], acc, 0, 0, 0);
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ob = __shfl_xor(wb, o, 64);
+      const int op = __shfl_xor(wp, o, 64);
+      if (ob > wb || (ob == wb && op < wp)) {
+        wb = ob;
+        wp = op;
+      }
+    }
+    if (bq >= 0 && bpos == wp) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) cp[4 * r * lda] = acc[r];
+      for (int q = 0; q < RPT; ++q)
+        if (q == bq) {
+#pragma unroll
+          for (int c = 0; c < NB; ++c) cand[wv * NB + c] = pr[q][c];
+        }
+    }
+    if (lane == 0) {
+      redv[wv] = wb;
+      redi[wv] = wp;
+    }
+    __syncthreads();
+    double gb = redv[0];
+    int gp = redi[0], gw = 0;
+#pragma unroll
+    for (int w = 1; w < NW; ++w) {
+      const double ob = redv[w];
+      const int op = redi[w];
+      if (ob > gb || (ob == gb && op < gp)) {
+        gb = ob;
+        gp = op;
+        gw = w;
+      }
+    }
+    const bool found = gp < rows;
+    if (!found) gp = j;   // no finite candidate: keep the position, flagged below
+    if (t == 0) piv[j] = gp;
+    const double* prow = cand + gw * NB;
+    const double pv = found ? prow[j] : 0.0;
+    if (t == 0 && !(fabs(pv) > 0.0 && fabs(pv) < INFINITY)) *sing = 1;
+    const double rinv = 1.0 / pv;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+      if (pos[q] == gp)
+        pos[q] = j;
+      else if (pos[q] == j)
+        pos[q] = gp;
+      if (found && pos[q] > j && pos[q] < rows) {
+        const double l = reg_pick<NB>(pr[q], j) * rinv;
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+          const double e = fma(-l, prow[c], pr[q][c]);
+          pr[q][c] = (c == j) ? l : ((c > j) ? e : pr[q][c]);
+        }
+      }
+    }
+    cand += (j & 1) ? -NW * NB : NW * NB;
+    redv += (j & 1) ? -NW : NW;
+    redi += (j & 1) ? -NW : NW;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int r = pos[q];
+    if (t + q * kThreads < rows) {
+#pragma unroll
+      for (int c = 0; c < NB; ++c) P[r * ps + c] = pr[q][c];
+      if (r < NB) {
+#pragma unroll
+        for (int c = 0; c < NB; ++c)
+          if (c >= r) A[(kb + r) * lda + kb + c] = pr[q][c];
+      }
     }
   }
 }
@@ -430,6 +583,9 @@ __device__ __forceinline__ double dyson_recompute(const Chain& ch, int sigma,
   double* redv = Li + NB * ls;                           // [kThreads/64]
   int* redi = reinterpret_cast<int*>(redv + kThreads / 64);
   int* piv = redi + kThreads / 64;                       // [NB]
+  double* cand = reinterpret_cast<double*>(piv + 32);    // [2][waves][NB] staged candidate rows
+  double* pred_v = cand + 2 * (kThreads / 64) * NB;      // [2][waves] candidate |pivot|
+  int* pred_i = reinterpret_cast<int*>(pred_v + 2 * (kThreads / 64));  // [2][waves] positions
   __shared__ int s_sing;
   if (t == 0) s_sing = 0;
   __syncthreads();
@@ -441,70 +597,78 @@ __device__ __forceinline__ double dyson_recompute(const Chain& ch, int sigma,
 
   for (int kb = 0; kb < np; kb += NB) {
     const int rows = np - kb;
-    // ---- panel rows kb.., columns kb..kb+NB-1 into LDS, factorized by all waves
-    for (int idx = t; idx < rows * NB; idx += kThreads) {
-      const int r = idx / NB, c = idx - r * NB;
-      P[r * ps + c] = A[(kb + r) * lda + kb + c];
+    if (NB == 32) {
+      panel_factor_regs<32>(A, lda, kb, rows, P, ps, cand, pred_v, pred_i, piv, &s_sing);
+    } else if (NB == 16) {
+      panel_factor_regs<16>(A, lda, kb, rows, P, ps, cand, pred_v, pred_i, piv, &s_sing);
+    } else {
+      // ---- panel rows kb.., columns kb..kb+NB-1 into LDS, factorized by all waves
+      for (int idx = t; idx < rows * NB; idx += kThreads) {
+        const int r = idx / NB, c = idx - r * NB;
+        P[r * ps + c] = A[(kb + r) * lda + kb + c];
+      }
+      __syncthreads();
+  #pragma unroll 1
+      for (int j = 0; j < NB; ++j) {
+        double best = -1.0;
+        int bi = 1 << 30;
+        for (int r = j + t; r < rows; r += kThreads) {
+          const double v = fabs(P[r * ps + j]);
+          if (v > best) {
+            best = v;
+            bi = r;
+          }
+        }
+  #pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+          const double ob = __shfl_xor(best, o, 64);
+          const int oi = __shfl_xor(bi, o, 64);
+          if (ob > best || (ob == best && oi < bi)) {
+            best = ob;
+            bi = oi;
+          }
+        }
+        if (lane == 0) {
+          redv[wv] = best;
+          redi[wv] = bi;
+        }
+        __syncthreads();
+        best = redv[0];
+        bi = redi[0];
+  #pragma unroll
+        for (int w = 1; w < kThreads / 64; ++w) {
+          const double ob = redv[w];
+          const int oi = redi[w];
+          if (ob > best || (ob == best && oi < bi)) {
+            best = ob;
+            bi = oi;
+          }
+        }
+        if (bi >= rows) bi = j;   // no finite candidate: keep the row, flagged below
+        if (t == 0) piv[j] = bi;
+        if (bi != j && t < NB) {
+          const double tmp = P[j * ps + t];
+          P[j * ps + t] = P[bi * ps + t];
+          P[bi * ps + t] = tmp;
+        }
+        __syncthreads();
+        const double pv = P[j * ps + j];
+        if (t == 0 && !(fabs(pv) > 0.0 && fabs(pv) < INFINITY)) s_sing = 1;
+        for (int r = j + 1 + t; r < rows; r += kThreads) {
+          double* pr = P + r * ps;
+          const double l = pr[j] / pv;
+          pr[j] = l;
+          for (int c = j + 1; c < NB; ++c) pr[c] = fma(-l, P[j * ps + c], pr[c]);
+        }
+        __syncthreads();
+      }
     }
-    __syncthreads();
-#pragma unroll 1
-    for (int j = 0; j < NB; ++j) {
-      double best = -1.0;
-      int bi = 1 << 30;
-      for (int r = j + t; r < rows; r += kThreads) {
-        const double v = fabs(P[r * ps + j]);
-        if (v > best) {
-          best = v;
-          bi = r;
-        }
+    // U11 -> A for the back substitution (the register panel wrote it already)
+    if (NB < 16) {
+      for (int idx = t; idx < NB * NB; idx += kThreads) {
+        const int r = idx / NB, c = idx - r * NB;
+        if (c >= r) A[(kb + r) * lda + kb + c] = P[r * ps + c];
       }
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        const double ob = __shfl_xor(best, o, 64);
-        const int oi = __shfl_xor(bi, o, 64);
-        if (ob > best || (ob == best && oi < bi)) {
-          best = ob;
-          bi = oi;
-        }
-      }
-      if (lane == 0) {
-        redv[wv] = best;
-        redi[wv] = bi;
-      }
-      __syncthreads();
-      best = redv[0];
-      bi = redi[0];
-#pragma unroll
-      for (int w = 1; w < kThreads / 64; ++w) {
-        const double ob = redv[w];
-        const int oi = redi[w];
-        if (ob > best || (ob == best && oi < bi)) {
-          best = ob;
-          bi = oi;
-        }
-      }
-      if (bi >= rows) bi = j;   // no finite candidate: keep the row, flagged below
-      if (t == 0) piv[j] = bi;
-      if (bi != j && t < NB) {
-        const double tmp = P[j * ps + t];
-        P[j * ps + t] = P[bi * ps + t];
-        P[bi * ps + t] = tmp;
-      }
-      __syncthreads();
-      const double pv = P[j * ps + j];
-      if (t == 0 && !(fabs(pv) > 0.0 && fabs(pv) < INFINITY)) s_sing = 1;
-      for (int r = j + 1 + t; r < rows; r += kThreads) {
-        double* pr = P + r * ps;
-        const double l = pr[j] / pv;
-        pr[j] = l;
-        for (int c = j + 1; c < NB; ++c) pr[c] = fma(-l, P[j * ps + c], pr[c]);
-      }
-      __syncthreads();
-    }
-    // U11 -> A for the back substitution
-    for (int idx = t; idx < NB * NB; idx += kThreads) {
-      const int r = idx / NB, c = idx - r * NB;
-      if (c >= r) A[(kb + r) * lda + kb + c] = P[r * ps + c];
     }
     {
       const long long t1 = wall_clock64();
@@ -802,87 +966,142 @@ constexpr int kYS = kTile + 1;  // FP32 Y tile row stride
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-// G += X Y for one spin. X: [L][kMaxK] row-major, Y: [kMaxK][L] row-major, m used columns.
+// G += X Y for one spin.  X: [L][kMaxK] row-major, Y: [kMaxK][L] row-major,
+// m used columns.  Each wave owns 16-row strips of G: it keeps the strip's X
+// operand in registers and walks the 16 x 16 output blocks of the strip, the
+// next block's G prefetched while the current one runs on the matrix cores.
+// MIXED: FP32 operands and FP32 accumulation (v_mfma_f32_16x16x4f32, output
+// row 4q + r), added into the FP64 G; otherwise FP64 (v_mfma_f64_16x16x4f64,
+// output row 4r + q).
 template <bool MIXED>
 __device__ __forceinline__ void flush_gemm(double* __restrict__ G, const double* __restrict__ X,
-                           const double* __restrict__ Y, int L, int m, char* lds) {
-  const int t = threadIdx.x;
-  if constexpr (MIXED) {
-    float* Xs = reinterpret_cast<float*>(lds);          // [kTile][kXS]
-    float* Ys = Xs + kTile * kXS;                        // [kMaxK][kYS]
-    const int m4 = (m + 3) & ~3;
-    const int w = t >> 6, lane = t & 63;
-    for (int r0 = 0; r0 < L; r0 += kTile) {
-      for (int idx = t; idx < kTile * m4; idx += kThreads) {
-        const int r = idx / m4, kk = idx - r * m4;
-        const int row = r0 + r;
-        Xs[r * kXS + kk] = (row < L && kk < m) ? (float)X[(long long)row * kMaxK + kk] : 0.f;
-      }
-      for (int c0 = 0; c0 < L; c0 += kTile) {
-        for (int idx = t; idx < m4 * kTile; idx += kThreads) {
-          const int kk = idx / kTile, c = idx - kk * kTile;
-          const int col = c0 + c;
-          Ys[kk * kYS + c] = (col < L && kk < m) ? (float)Y[(long long)kk * L + col] : 0.f;
-        }
-        __syncthreads();
+                                           const double* __restrict__ Y, int L, int m) {
+  typedef typename std::conditional<MIXED, float, double>::type T;
+  typedef T Tx4 __attribute__((ext_vector_type(4)));
+  constexpr int KS = kMaxK / 4;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int li = lane & 15, lq = lane >> 4;
+  const int ks = (m + 3) >> 2;
+  const int nb = (L + 15) >> 4;
+  for (int rs = wv; rs < nb; rs += kThreads / 64) {
+    const int row0 = rs * 16;
+    const int arow = min(row0 + li, L - 1);
+    const bool arow_ok = row0 + li < L;
+    // operands are loaded unconditionally from clamped, in-bounds addresses and
+    // zeroed where they fall outside (k >= m, row/col >= L), so no load waits
+    // behind a branch
+    T a[KS];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int blk = 2 * w + h;
-          const int br = blk >> 2, bc = blk & 3;
-          floatx4 acc = {0.f, 0.f, 0.f, 0.f};
-          for (int k0 = 0; k0 < m4; k0 += 4) {
-            const float a = Xs[(br * 16 + (lane & 15)) * kXS + k0 + (lane >> 4)];
-            const float b = Ys[(k0 + (lane >> 4)) * kYS + bc * 16 + (lane & 15)];
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
-          }
-          const int col = c0 + bc * 16 + (lane & 15);
-#pragma unroll
-          for (int rr = 0; rr < 4; ++rr) {
-            const int row = r0 + br * 16 + 4 * (lane >> 4) + rr;
-            if (row < L && col < L) G[(long long)row * L + col] += (double)acc[rr];
-          }
-        }
-        __syncthreads();
-      }
+    for (int q = 0; q < KS; ++q) {
+      const int kk = 4 * q + lq;
+      const double v = X[arow * kMaxK + kk];
+      a[q] = (arow_ok && kk < m) ? (T)v : (T)0;
     }
-  } else {
-    double* Xt = reinterpret_cast<double*>(lds);        // [kMaxK][kTP]  (k-major)
-    double* Yt = Xt + kMaxK * kTP;                      // [kMaxK][kTP]
-    const int tr = t >> 4, tc = t & 15;                 // 32 x 16 threads, 2 x 4 outputs each
-    for (int r0 = 0; r0 < L; r0 += kTile) {
-      for (int idx = t; idx < kTile * m; idx += kThreads) {
-        const int r = idx / m, kk = idx - r * m;
-        const int row = r0 + r;
-        Xt[kk * kTP + r] = row < L ? X[(long long)row * kMaxK + kk] : 0.0;
+    int orow[4];
+    bool rok[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int rr = row0 + (MIXED ? 4 * lq + r : 4 * r + lq);
+      rok[r] = rr < L;
+      orow[r] = min(rr, L - 1);
+    }
+    T ynxt[KS];
+    double gnxt[4];
+    {
+      const int col = min(li, L - 1);
+#pragma unroll
+      for (int q = 0; q < KS; ++q) ynxt[q] = (T)Y[(4 * q + lq) * L + col];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) gnxt[r] = G[orow[r] * L + col];
+    }
+#pragma unroll 1
+    for (int cb = 0; cb < nb; ++cb) {
+      const int col = cb * 16 + li;
+      const bool cok = col < L;
+      T ycur[KS];
+      double gcur[4];
+#pragma unroll
+      for (int q = 0; q < KS; ++q) ycur[q] = ynxt[q];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) gcur[r] = gnxt[r];
+      {
+        const int ncol = min(col + 16, L - 1);
+#pragma unroll
+        for (int q = 0; q < KS; ++q) ynxt[q] = (T)Y[(4 * q + lq) * L + ncol];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) gnxt[r] = G[orow[r] * L + ncol];
       }
-      for (int c0 = 0; c0 < L; c0 += kTile) {
-        for (int idx = t; idx < m * kTile; idx += kThreads) {
-          const int kk = idx / kTile, c = idx - kk * kTile;
-          const int col = c0 + c;
-          Yt[kk * kTP + c] = col < L ? Y[(long long)kk * L + col] : 0.0;
-        }
-        __syncthreads();
-        double acc[2][4] = {{0.0}};
-        for (int kk = 0; kk < m; ++kk) {
-          const double x0 = Xt[kk * kTP + 2 * tr], x1 = Xt[kk * kTP + 2 * tr + 1];
-          const double* yv = Yt + kk * kTP + 4 * tc;
+      Tx4 acc = {(T)0, (T)0, (T)0, (T)0};
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            acc[0][q] = fma(x0, yv[q], acc[0][q]);
-            acc[1][q] = fma(x1, yv[q], acc[1][q]);
-          }
+      for (int q = 0; q < KS; ++q) {
+        const int kk = 4 * q + lq;
+        const T bv = (cok && kk < m) ? ycur[q] : (T)0;
+        if (q < ks) {
+          if constexpr (MIXED)
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q], bv, acc, 0, 0, 0);
+          else
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], bv, acc, 0, 0, 0);
         }
+      }
 #pragma unroll
-        for (int a = 0; a < 2; ++a) {
-          const int row = r0 + 2 * tr + a;
-          if (row >= L) continue;
+      for (int r = 0; r < 4; ++r)
+        if (rok[r] && cok) G[orow[r] * L + col] = gcur[r] + (double)acc[r];
+    }
+  }
+}
+
+// X = C0 T and Y = S R0 of one spin on the matrix cores (FP64), wave-
+// independent 16 x 16 output tiles.  C0[q][i] = G[q][f_i] - delta(q, f_i),
+// R0[i][r] = G[f_i][r] (f_i = l0 + F[i]); T (upper, unit diagonal) and S
+// (lower, diagonal c_j) share the m x m LDS block TS (row stride kKP):
+// T[i][j] = TS[i][j] for i < j, S[j][i] = TS[j][i] for i <= j.
+__device__ __forceinline__ void flush_vectors(const double* __restrict__ G, int L, int l0, int m,
+                                              const int* __restrict__ F,
+                                              const double* __restrict__ TS,
+                                              double* __restrict__ X, double* __restrict__ Y) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int li = lane & 15, lq = lane >> 4;
+  const int ks = (m + 3) >> 2;
+  const int mb = (m + 15) >> 4;
+  const int nb = (L + 15) >> 4;
+  // X tiles: row block rb (of L), column block jb (of m); Y tiles: row block jb (of m), column block cb
+  const int nx = nb * mb;
+  for (int tile = wv; tile < 2 * nx; tile += kThreads / 64) {
+    doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+    if (tile < nx) {
+      const int rb = tile / mb, jb = tile - rb * mb;
+      const int q = min(rb * 16 + li, L - 1);
+      const int j = jb * 16 + li;
+#pragma unroll 4
+      for (int s4 = 0; s4 < ks; ++s4) {
+        const int i = 4 * s4 + lq;
+        const int fi = (i < m) ? l0 + F[i] : 0;
+        const double c0 = (i < m) ? G[q * L + fi] - (q == fi ? 1.0 : 0.0) : 0.0;
+        const double tv = (i < m && j < m) ? (i < j ? TS[i * kKP + j] : (i == j ? 1.0 : 0.0)) : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(c0, tv, acc, 0, 0, 0);
+      }
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const int col = c0 + 4 * tc + q;
-            if (col < L) G[(long long)row * L + col] += acc[a][q];
-          }
-        }
-        __syncthreads();
+      for (int r = 0; r < 4; ++r) {
+        const int qq = rb * 16 + 4 * r + lq;
+        if (qq < L && j < m) X[qq * kMaxK + j] = acc[r];
+      }
+    } else {
+      const int t2 = tile - nx;
+      const int jb = t2 / nb, cb = t2 - jb * nb;
+      const int jr = jb * 16 + li;
+      const int col = min(cb * 16 + li, L - 1);
+#pragma unroll 4
+      for (int s4 = 0; s4 < ks; ++s4) {
+        const int i = 4 * s4 + lq;
+        const double sv = (jr < m && i < m && i <= jr) ? TS[jr * kKP + i] : 0.0;
+        const int fi = (i < m) ? l0 + F[i] : 0;
+        const double r0 = (i < m) ? G[fi * L + col] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(sv, r0, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int jj = jb * 16 + 4 * r + lq;
+        if (jj < m && cb * 16 + li < L) Y[jj * L + cb * 16 + li] = acc[r];
       }
     }
   }
@@ -892,6 +1111,7 @@ template <bool MIXED>
 __device__ __forceinline__ void flush_window(const Chain& ch, int l0, int m) {
   const int L = ch.L;
   const int t = threadIdx.x;
+  const int lane = t & 63, wv = t >> 6;
   const int* F = reinterpret_cast<const int*>(ch.scratch);
   const double* cU = reinterpret_cast<const double*>(ch.scratch + 256);
   const double* cD = cU + kMaxK;
@@ -917,38 +1137,54 @@ __device__ __forceinline__ void flush_window(const Chain& ch, int l0, int m) {
     ULd[i * kKP + j] = vd;
   }
   __syncthreads();
-  // full update vectors: one row of X or one column of Y per item
-  for (int item = t; item < 4 * L; item += kThreads) {
-    const int sp = item / (2 * L);
-    const int rem = item - sp * 2 * L;
-    const double* G = sp ? ch.Gd : ch.Gu;
-    const double* UL = sp ? ULd : ULu;
-    if (rem < L) {
-      const int q = rem;
-      double* xs = X + (long long)sp * L * kMaxK + (long long)q * kMaxK;
-      for (int j = 0; j < m; ++j) {
-        const int fj = l0 + F[j];
-        double acc = G[(long long)q * L + fj] - (q == fj ? 1.0 : 0.0);
-        for (int i = 0; i < j; ++i) acc = fma(xs[i], UL[i * kKP + j], acc);
-        xs[j] = acc;
+  // In place, one wave per triangle:
+  //   T = (I - U)^{-1}: lane r builds row r, T[r][j] = sum_{r <= i < j} T[r][i] U[i][j] (T[r][r] = 1);
+  //   S = (I - Dc Lw)^{-1} Dc: lane c builds column c, S[c][c] = c_c,
+  //   S[j][c] = c_j sum_{c <= i < j} Lw[j][i] S[i][c].
+  // Each step j reads only entries the wave has not yet overwritten at that step.
+  if (wv < 4 && lane < m) {
+    double* UL = (wv & 1) ? ULd : ULu;
+    const double* cc = (wv & 1) ? cD : cU;
+    // all lanes step through j together, so every read of column / row j
+    // happens before any lane overwrites it at the end of the same step
+    if (wv < 2) {
+      const int r = lane;
+#pragma unroll 1
+      for (int j = 1; j < m; ++j) {
+        if (r < j) {
+          double acc = UL[r * kKP + j];
+#pragma unroll 1
+          for (int i = r + 1; i < j; ++i) acc = fma(UL[r * kKP + i], UL[i * kKP + j], acc);
+          UL[r * kKP + j] = acc;
+        }
+        wave_sync();
       }
     } else {
-      const int r = rem - L;
-      double* ys = Y + (long long)sp * kMaxK * L;
-      const double* c = sp ? cD : cU;
-      for (int j = 0; j < m; ++j) {
-        const int fj = l0 + F[j];
-        double acc = G[(long long)fj * L + r];
-        for (int i = 0; i < j; ++i) acc = fma(UL[j * kKP + i], ys[(long long)i * L + r], acc);
-        ys[(long long)j * L + r] = c[j] * acc;
+      const int c = lane;
+      UL[c * kKP + c] = cc[c];
+      wave_sync();
+#pragma unroll 1
+      for (int j = 1; j < m; ++j) {
+        if (c < j) {
+          double acc = 0.0;
+#pragma unroll 1
+          for (int i = c; i < j; ++i) acc = fma(UL[j * kKP + i], UL[i * kKP + c], acc);
+          UL[j * kKP + c] = cc[j] * acc;
+        }
+        wave_sync();
       }
     }
   }
   __syncthreads();
 #pragma unroll 1
   for (int sp = 0; sp < 2; ++sp)
+    flush_vectors(sp ? ch.Gd : ch.Gu, L, l0, m, F, sp ? ULd : ULu, X + (long long)sp * L * kMaxK,
+                  Y + (long long)sp * kMaxK * L);
+  __syncthreads();
+#pragma unroll 1
+  for (int sp = 0; sp < 2; ++sp)
     flush_gemm<MIXED>(sp ? ch.Gd : ch.Gu, X + (long long)sp * L * kMaxK,
-                      Y + (long long)sp * kMaxK * L, L, m, un);
+                      Y + (long long)sp * kMaxK * L, L, m);
   __syncthreads();
 }
 
@@ -1047,7 +1283,7 @@ __device__ __forceinline__ int sweep_window(const SweepParams& p, const Chain& c
 
 // ----------------------------------------------------------- the chain ----
 
-__device__ void run_chain(const SweepParams& p, const GridDev* gd, int chain, double* ws,
+__device__ __forceinline__ void run_chain(const SweepParams& p, const GridDev* gd, int chain, double* ws,
                           char* lds) {
   Chain ch;
   ch.G0 = gd->G0;
@@ -1232,13 +1468,18 @@ long long workspace_doubles(int Lmax, int kmax) {
   return (w + 63) & ~63LL;
 }
 
+// LDS bytes of the LU besides the panel and the inverted triangle: reduction
+// slots, pivots and the double-buffered staged candidate rows.
+constexpr long long kLuExtra = 1024 + 2LL * (kThreads / 64) * kNBMax * 8 + 256;
+
 // LU panel width: the widest of 32/16/8/4 whose padded LDS panel fits the budget.
 static int lu_panel(int Lmax, long long budget) {
   const int cand[4] = {32, 16, 8, 4};
   for (int q = 0; q < 4; ++q) {
     const int nb = cand[q];
     const long long np = (Lmax + nb - 1) / nb * nb;
-    if (np * (nb + 2) * 8 + (long long)nb * (nb + 1) * 8 + 1024 <= budget) return nb;
+    if (nb >= 16 && np > (long long)kThreads * (nb == 32 ? 1 : 2)) continue;  // register panel
+    if (np * (nb + 2) * 8 + (long long)nb * (nb + 1) * 8 + kLuExtra <= budget) return nb;
   }
   return 4;
 }
@@ -1251,7 +1492,7 @@ int lds_bytes(int Lmax, int mode, int k, int b, int* lu_nb, int* scratch_bytes) 
   const int nb = lu_panel(Lmax, budget);
   *lu_nb = nb;
   const long long np = (Lmax + nb - 1) / nb * nb;
-  const long long lu = np * (nb + 2) * 8 + (long long)nb * (nb + 1) * 8 + 1024;
+  const long long lu = np * (nb + 2) * 8 + (long long)nb * (nb + 1) * 8 + kLuExtra;
   long long sc = lu;
   if (mode == MODE_RANK1) {
     const long long r1 = 4LL * Lmax * 8;
