@@ -4,13 +4,20 @@ Workload (the headline configuration): half-filled single-band Hubbard
 impurity, Bethe-lattice semicircular DOS (t = 1), beta = 40, U = 4.5,
 dtau = 0.1 (L = 400), 256 independent chains (seeds 0..255), 200 warm-up +
 2000 measured sweeps per chain.  One step = one full solve of that workload
-(all chains, all sweeps, chain init, recomputes, measurement and reduction).
+(all chains, all sweeps: chain init, Metropolis sweeps, delayed updates,
+Dyson recomputes, measurement and chain reduction) in one persistent launch.
 
-Prints ONE JSON line: metric sweeps/s over all chains for the production
-path, the plain FP64 rank-1 path timed beside it, the roofline of the
-persistent sweep kernel and the CPU oracle timed on a bounded sample.
+Prints ONE JSON line on stdout with the production path's sweeps/s over all
+chains, the plain FP64 rank-1 path timed beside it on the same chains, the
+roofline of the persistent sweep kernel (k_sweeps) from HIP events, and the
+CPU oracle timed on a bounded sample of the workload.  Progress goes to stderr.
+
+  python bench.py                      # mixed precision, k = 64 (default)
+  python bench.py --mode delayed       # delayed rank-k, FP64 flush
+  python bench.py --calib-copy         # copy kernel used to scale PMC counters
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -23,31 +30,90 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3
+KERNEL_SRC = os.path.join(ROOT, "paper_0801_1222_amd", "csrc", "hfqmc_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweeps_traffic.json")
 
 WORKLOAD = dict(beta=40.0, U=4.5, dtau=0.1, L=400, n_chains=256, warmup=200, sweeps=2000,
                 t=1.0, seed=0)
 
+_T0 = time.perf_counter()
 
-def algorithmic_work(L, st, n_chains, measured_sweeps, mode, k):
-    """Algorithmic HBM bytes and FP64 flops of one solve (Measurement)."""
+
+def progress(msg):
+    print("[bench %7.1fs] %s" % (time.perf_counter() - _T0, msg), file=sys.stderr, flush=True)
+
+
+def algorithmic_work(L, st, n_chains, measured_sweeps, mode):
+    """Algorithmic HBM bytes and FP64/FP32 flops of one solve.
+
+    Per unit (both spins, L x L FP64 Green matrices):
+      rank-1 accepted flip     32 L^2 bytes (read + write G), 4 L^2 FP64 flops
+      delayed flush of rank m  32 L^2 bytes; its flips cost 4 L^2 flops each
+                               (FP32 in the mixed path, FP64 otherwise)
+      Dyson recompute          24 L^2 bytes (read G0 twice, write G), 2 (8/3) L^3 FP64 flops
+      measurement              16 L^2 bytes
+    The accepted-flip, flush and recompute counts come from the kernel's stats.
+    """
     L2 = float(L) * L
     n_acc = st["n_accepted"]
-    n_rec = st["n_recomputes"] + 2 * n_chains  # plus the initial G of each chain (both spins counted below)
+    n_rec = st["n_recomputes"] + n_chains            # plus the initial recompute of each chain
+    n_flush = st.get("n_flushes", 0)
     meas = float(n_chains) * measured_sweeps
     if mode == "rank1":
         upd_bytes = 32.0 * L2 * n_acc
+        f64, f32 = 4.0 * L2 * n_acc, 0.0
     else:
-        # one read+write of both G per flush of up to k pending flips
-        upd_bytes = 32.0 * L2 * n_acc / k
+        upd_bytes = 32.0 * L2 * n_flush
+        f64, f32 = (0.0, 4.0 * L2 * n_acc) if mode == "mixed" else (4.0 * L2 * n_acc, 0.0)
     bytes_ = upd_bytes + 16.0 * L2 * meas + 24.0 * L2 * n_rec
-    flops = 4.0 * L2 * n_acc + n_rec * (8.0 / 3.0) * L2 * L
-    return bytes_, flops
+    f64 += n_rec * 2.0 * (8.0 / 3.0) * L2 * L
+    return bytes_, f64, f32
+
+
+def roofline(L, st, n_chains, measured_sweeps, mode, t_kernel):
+    """Roofline entry of the sweep kernel: the resource whose lower-bound time is largest."""
+    by, f64, f32 = algorithmic_work(L, st, n_chains, measured_sweeps, mode)
+    t_hbm = by / (HBM_PEAK_GBS * 1e9)
+    t_mfma = f64 / (FP64_PEAK_TFLOPS * 1e12) + f32 / (FP32_PEAK_TFLOPS * 1e12)
+    hbm = {"bound": "hbm", "achieved": by / t_kernel / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    hbm["frac"] = hbm["achieved"] / hbm["peak"]
+    # matrix-core work expressed at the FP64 rate (FP32 flops count half)
+    f64e = f64 + f32 * FP64_PEAK_TFLOPS / FP32_PEAK_TFLOPS
+    mf = {"bound": "mfma", "achieved": f64e / t_kernel / 1e12, "peak": FP64_PEAK_TFLOPS,
+          "unit": "TFLOP/s"}
+    mf["frac"] = mf["achieved"] / mf["peak"]
+    main, other = (hbm, mf) if t_hbm >= t_mfma else (mf, hbm)
+    main = dict(main)
+    main["secondary"] = other
+    main["lower_bound_s"] = {"hbm": t_hbm, "mfma_fp64_equiv": t_mfma}
+    main["algorithmic"] = {"bytes": by, "fp64_flops": f64, "fp32_flops": f32}
+    return main
+
+
+def kernel_source_hash():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(mode, chain_sweeps):
+    """HBM bytes per launch from committed PMC counters, if taken on this kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        tr = json.load(f)
+    if tr.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    ent = tr.get("modes", {}).get(mode)
+    if not ent:
+        return None
+    # counters were taken on a shorter run of the same chains: scale per chain-sweep
+    return ent["bytes_per_chain_sweep"] * chain_sweeps
 
 
 def cpu_baseline(sample_chains, warmup, sweeps, procs):
     """Oracle (as it stands) on the host cores over a bounded sample of the workload."""
     import multiprocessing as mp
-    w = WORKLOAD
     ctx = mp.get_context("fork")
     t0 = time.perf_counter()
     with ctx.Pool(procs) as pool:
@@ -55,42 +121,65 @@ def cpu_baseline(sample_chains, warmup, sweeps, procs):
     dt = time.perf_counter() - t0
     return dict(value=sample_chains * (warmup + sweeps) / dt, unit="sweeps/s", cores=procs,
                 kind="oracle",
-                sample="%d chains x (%d+%d) sweeps of the beta=40 U=4.5 L=400 workload, "
-                       "one chain per process, %d processes, %.1f s" % (sample_chains, warmup,
-                                                                           sweeps, procs, dt))
+                sample="chains 0..%d of the beta=40 U=4.5 L=400 workload, %d+%d sweeps each, "
+                       "FP64 rank-1 with recompute every 100, one chain per process, "
+                       "%d processes x 1 BLAS thread, %.1f s wall"
+                       % (sample_chains - 1, warmup, sweeps, procs, dt))
 
 
 def _oracle_chain(args):
-    os.environ.setdefault("OMP_NUM_THREADS", "1")
     c, warmup, sweeps = args
+    from threadpoolctl import threadpool_limits
+
     from oracle import bath as OB
     from oracle import hfqmc as OH
     w = WORKLOAD
-    g0 = OB.bath_to_tau(OB.semicircle_iw(w["beta"], w["t"], 20000), w["t"] ** 2, w["beta"], w["L"])
-    OH.run_chain(g0, w["U"], w["beta"], w["seed"], chain=c, warmup=warmup, sweeps=sweeps, n_rec=100)
+    with threadpool_limits(1):
+        g0 = OB.bath_to_tau(OB.semicircle_iw(w["beta"], w["t"], 20000), w["t"] ** 2, w["beta"],
+                            w["L"])
+        OH.run_chain(g0, w["U"], w["beta"], w["seed"], chain=c, warmup=warmup, sweeps=sweeps,
+                     n_rec=100)
     return c
+
+
+def calib_copy():
+    """A plain device copy of known size, profiled to scale FETCH_SIZE / WRITE_SIZE."""
+    import torch
+    n = 1 << 28                                   # 2 GiB of FP64 read, 2 GiB written
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calib_copy_bytes_read": 8 * n, "calib_copy_bytes_written": 8 * n}))
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--mode", default="rank1", choices=["rank1", "delayed", "mixed"])
-    ap.add_argument("--delay-k", type=int, default=0)
+    ap.add_argument("--mode", default="mixed", choices=["rank1", "delayed", "mixed"])
+    ap.add_argument("--delay-k", type=int, default=64)
     ap.add_argument("--chain-sweeps", type=int, default=None,
                     help="measured sweeps per chain (default: the workload's 2000)")
-    ap.add_argument("--chain-warmup", type=int, default=None)
+    ap.add_argument("--chain-warmup", type=int, default=None,
+                    help="warm-up sweeps per chain (default: the workload's 200)")
     ap.add_argument("--rank1-sweeps", type=int, default=40,
-                    help="measured sweeps of the plain FP64 comparison solve (0 = skip)")
+                    help="sweeps per chain of the plain FP64 rank-1 comparison solve (0 = skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-chains", type=int, default=0)
+    ap.add_argument("--cpu-sweeps", type=int, default=12)
+    ap.add_argument("--calib-copy", action="store_true")
     args = ap.parse_args()
 
     if args.gpus != 1:
         print("bench.py: this build measures one GPU; --gpus %d is not supported "
-              "(independent chains shard across GPUs, see DESIGN.md)" % args.gpus, file=sys.stderr)
+              "(independent chains shard across GPUs; see the design notes)" % args.gpus,
+              file=sys.stderr)
         sys.exit(2)
+    if args.calib_copy:
+        calib_copy()
+        return
 
     import torch
 
@@ -107,51 +196,68 @@ def main():
     ctx = P.Context(0)
     stream = torch.cuda.current_stream()
     ctx.set_stream(stream)
+    progress("context ready; mode %s, %d chains x (%d+%d) sweeps per step"
+             % (args.mode, w["n_chains"], w["warmup"], w["sweeps"]))
 
     def solve(mode, warmup, sweeps):
         return P.hfqmc_solve(ctx, g0, w["U"], w["beta"], w["dtau"], w["seed"],
                              n_chains=w["n_chains"], warmup=warmup, sweeps=sweeps, mode=mode,
-                             delay_k=args.delay_k)
+                             delay_k=args.delay_k if mode != "rank1" else 0)
 
-    for _ in range(args.warmup):
-        solve(args.mode, w["warmup"], w["sweeps"])
+    for i in range(args.warmup):
+        r = solve(args.mode, w["warmup"], w["sweeps"])
+        progress("warmup step %d done, kernel %.2f s" % (i, r["stats"]["seconds_kernel"]))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     outs = []
-    for _ in range(args.steps):
+    for i in range(args.steps):
         outs.append(solve(args.mode, w["warmup"], w["sweeps"]))
+        progress("timed step %d done, kernel %.2f s" % (i, outs[-1]["stats"]["seconds_kernel"]))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     chain_sweeps = w["n_chains"] * (w["warmup"] + w["sweeps"])
     value = chain_sweeps * args.steps / elapsed
     kern = [o["stats"]["seconds_kernel"] for o in outs]
     st = outs[-1]["stats"]
-    k_used = st["delay_k"]
-    by, fl = algorithmic_work(L, st, w["n_chains"], w["sweeps"], args.mode, max(k_used, 1))
     t_k = float(np.mean(kern))
-    achieved = by / t_k / 1e9
+    rf = roofline(L, st, w["n_chains"], w["sweeps"], args.mode, t_k)
+    rf["traffic"] = measured_traffic(args.mode, chain_sweeps)
+    rf["kernel"] = "k_sweeps"
+    rf["kernel_ms"] = t_k * 1e3
     g = outs[-1]["g"]
     checks = dict(
         ph_symmetry_max=float(np.abs(g[1:L] - g[1:L][::-1]).max()),
         g0_minus_half=float(abs(g[0] - 0.5)),
-        max_drift=float(st["max_drift"]),
+        max_elementwise_drift=float(st["max_drift"]),
         acc_rate=float(st["acc_rate"]),
         bad_ratios=int(st["n_bad_ratio"]),
+        singular=int(st["n_singular"]),
         docc=float(outs[-1]["D"]),
         docc_err=float(outs[-1]["D_err"]),
+        g_beta_half=float(g[L // 2]),
+        g_beta_half_err=float(outs[-1]["g_err"][L // 2]),
     )
     rank1 = None
     if args.rank1_sweeps > 0 and args.mode != "rank1":
         r = solve("rank1", 0, args.rank1_sweeps)
-        rank1 = dict(sweeps_per_s=w["n_chains"] * args.rank1_sweeps / r["stats"]["seconds_kernel"],
+        rs = r["stats"]
+        rr = roofline(L, rs, w["n_chains"], args.rank1_sweeps, "rank1", rs["seconds_kernel"])
+        rank1 = dict(sweeps_per_s=w["n_chains"] * args.rank1_sweeps / rs["seconds_kernel"],
                      chain_sweeps=w["n_chains"] * args.rank1_sweeps,
-                     kernel_s=r["stats"]["seconds_kernel"])
+                     kernel_s=rs["seconds_kernel"], recompute_every=rs["recompute_every"],
+                     roofline={k: rr[k] for k in ("bound", "achieved", "peak", "unit", "frac")},
+                     note="same 256 chains, 0+%d sweeps, FP64 Sherman-Morrison per accepted "
+                          "flip, recompute every 100" % args.rank1_sweeps)
+        progress("plain rank-1 comparison done: %.0f sweeps/s" % rank1["sweeps_per_s"])
     cpu = None
     if not args.no_cpu_baseline:
         procs = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
         procs = max(1, min(procs, 16))
-        n_ch = args.cpu_chains or procs
-        cpu = cpu_baseline(n_ch, 0, 2, procs)
+        cpu = cpu_baseline(procs, 0, args.cpu_sweeps, procs)
+        progress("cpu baseline done: %.2f sweeps/s on %d cores" % (cpu["value"], procs))
+    ph = {k: st[k] for k in ("chain_s_sweep", "chain_s_flush", "chain_s_recompute",
+                             "chain_s_measure", "chain_s_lu_build", "chain_s_lu_panel",
+                             "chain_s_lu_strip", "chain_s_lu_back")}
     line = {
         "metric": "HF-QMC sweeps/s (all chains, L=400)",
         "value": value,
@@ -163,23 +269,21 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.mode != "mixed" else "f64+f32",
+        "dtype": {"mixed": "f64+f32", "delayed": "f64", "rank1": "f64"}[args.mode],
         "data": "synthetic",
-        "config": {"workload": "half-filled Bethe-lattice impurity beta=40 U=4.5 dtau=0.1 L=400, "
-                               "256 chains x (%d+%d) sweeps" % (w["warmup"], w["sweeps"]),
-                   "mode": args.mode, "delay_k": k_used, "recompute_every": st["recompute_every"],
-                   "n_chains": w["n_chains"], "L": L, "parallelism": "chains"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_sweeps", "kernel_ms": t_k * 1e3,
-                     "fp64_tflops": fl / t_k / 1e12},
-        "rank1_fp64": rank1,
+        "config": {"workload": "half-filled Bethe-lattice impurity (t=1) beta=40 U=4.5 "
+                               "dtau=0.1 L=400, 256 chains x (%d+%d) sweeps"
+                               % (w["warmup"], w["sweeps"]),
+                   "mode": args.mode, "delay_k": st["delay_k"],
+                   "recompute_every": st["recompute_every"], "n_chains": w["n_chains"], "L": L,
+                   "workgroups": st["n_workgroups"]},
+        "roofline": rf,
+        "plain_fp64_rank1": rank1,
+        "speedup_vs_rank1": (chain_sweeps / t_k) / rank1["sweeps_per_s"] if rank1 else None,
         "cpu_baseline": cpu,
         "checks": checks,
-        "phases_chain_s": {k: st[k] for k in ("chain_s_sweep", "chain_s_flush",
-                                              "chain_s_recompute", "chain_s_measure",
-                                              "chain_s_lu_build", "chain_s_lu_panel",
-                                              "chain_s_lu_strip", "chain_s_lu_back")},
+        "phases_chain_s": ph,
+        "kernel_sweeps_per_s": chain_sweeps / t_k,
     }
     print(json.dumps(line), flush=True)
 

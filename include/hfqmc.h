@@ -96,6 +96,7 @@ typedef struct {
   double seconds_total;     /* wall time of the call */
   double seconds_kernel;    /* HIP-event time of the persistent sweep kernel */
   int64_t n_proposed, n_accepted, n_recomputes, n_bad_ratio, n_singular;
+  int64_t n_flushes;        /* delayed modes: rank-m products applied to G */
   /* per-phase time inside the sweep kernel, summed over chains (chain-seconds,
      from the device wall clock): sweeping excluding flushes and recomputes,
      delayed-update flushes, Dyson recomputes (initial ones included), measurement */

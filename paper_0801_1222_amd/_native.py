@@ -42,7 +42,7 @@ class Stats(C.Structure):
     _fields_ = [
         ("acc_rate", _f64), ("max_drift", _f64), ("seconds_total", _f64), ("seconds_kernel", _f64),
         ("n_proposed", _i64), ("n_accepted", _i64), ("n_recomputes", _i64),
-        ("n_bad_ratio", _i64), ("n_singular", _i64),
+        ("n_bad_ratio", _i64), ("n_singular", _i64), ("n_flushes", _i64),
         ("chain_s_sweep", _f64), ("chain_s_flush", _f64), ("chain_s_recompute", _f64),
         ("chain_s_measure", _f64),
         ("chain_s_lu_build", _f64), ("chain_s_lu_panel", _f64), ("chain_s_lu_strip", _f64),

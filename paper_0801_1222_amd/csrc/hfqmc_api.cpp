@@ -374,6 +374,7 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
       gs.n_recomputes += s[ST_RECOMPUTES];
       gs.n_bad_ratio += s[ST_BAD];
       gs.n_singular += s[ST_SINGULAR];
+      gs.n_flushes += s[ST_FLUSHES];
       const double f = 1.0 / c->wall_hz;
       gs.chain_s_sweep += s[ST_T_SWEEP] * f;
       gs.chain_s_flush += s[ST_T_FLUSH] * f;
@@ -399,6 +400,7 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
     tot.n_recomputes += gs.n_recomputes;
     tot.n_bad_ratio += gs.n_bad_ratio;
     tot.n_singular += gs.n_singular;
+    tot.n_flushes += gs.n_flushes;
     tot.chain_s_sweep += gs.chain_s_sweep;
     tot.chain_s_flush += gs.chain_s_flush;
     tot.chain_s_recompute += gs.chain_s_recompute;

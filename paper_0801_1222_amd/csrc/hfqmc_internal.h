@@ -14,6 +14,7 @@ enum {
   ST_SINGULAR = 4,  // zero or non-finite pivots met in a Dyson recompute
   ST_FLIPS = 5,     // entries written to the flip log (may exceed its capacity)
   ST_REPLAYED = 6,  // replay entries consumed
+  ST_FLUSHES = 7,   // delayed-update flushes (rank-m products applied to G)
   ST_T_SWEEP = 8,   // wall-clock ticks spent in sweeps, flushes and recomputes excluded
   ST_T_FLUSH = 9,   // ... in delayed-update flushes
   ST_T_REC = 10,    // ... in Dyson recomputes (initial ones included)

@@ -168,6 +168,7 @@ struct Counters {
   int singular;
   long long t_sweep, t_flush, t_rec, t_meas;        // constant-rate wall-clock ticks
   long long t_lu_build, t_lu_panel, t_lu_strip, t_lu_back;
+  long long n_flush;
 };
 
 // ------------------------------------------------ Dyson recompute (LU) ----
@@ -1274,6 +1275,7 @@ __device__ __forceinline__ int sweep_window(const SweepParams& p, const Chain& c
       const long long t0 = wall_clock64();
       flush_window<MIXED>(ch, l0, m);
       k.t_flush += wall_clock64() - t0;
+      ++k.n_flush;
     }
     l0 += pos;
     if (k.acc_since == p.n_rec) return l0;
@@ -1318,7 +1320,7 @@ __device__ __forceinline__ void run_chain(const SweepParams& p, const GridDev* g
     ch.s[l] = uniform53(ch.key0, (uint64_t)gd->grid_id, (uint64_t)l, 0ull, 1ull) < 0.5 ? 1 : -1;
   __syncthreads();
 
-  Counters k = {0, 0, 0, 0, 0, 0, 0.0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  Counters k = {0, 0, 0, 0, 0, 0, 0.0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
 
   ChainIO io;
   io.flog = gd->flip_log ? gd->flip_log + (long long)chain * p.flip_cap : nullptr;
@@ -1383,6 +1385,7 @@ __device__ __forceinline__ void run_chain(const SweepParams& p, const GridDev* g
     st[ST_SINGULAR] = k.singular;
     st[ST_FLIPS] = k.n_flips;
     st[ST_REPLAYED] = k.rep_i;
+    st[ST_FLUSHES] = k.n_flush;
     st[ST_T_SWEEP] = k.t_sweep;
     st[ST_T_FLUSH] = k.t_flush;
     st[ST_T_REC] = k.t_rec;
