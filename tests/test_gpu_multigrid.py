@@ -1,0 +1,133 @@
+"""GPU parity of the batched multigrid solve, the large-L recompute paths and
+the DMFT cycle.
+
+* multigrid_solve runs all grids and chains in one launch; grid i uses Philox
+  grid key i exactly like the oracle, so every grid estimate must match the
+  oracle's to 1e-10 and the extrapolated G(tau_j) to 1e-9 (host spline and
+  least squares are independent implementations).
+* U = 0 and the Hubbard atom are exact end to end.
+* L = 1000 and L = 2000 exercise the narrow-panel LU (panel widths 8 and 4).
+"""
+import numpy as np
+import pytest
+
+from oracle import bath as OB
+from oracle import hfqmc as OH
+from oracle import multigrid as OMG
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_0801_1222_amd as P
+    c = P.Context(0)
+    yield c
+    c.close()
+
+
+def test_multigrid_matches_oracle_grid_by_grid(ctx):
+    """beta=20, U=4.8, grids dtau 0.4..0.125 (L = 50..160) as in the batched multigrid
+    workload, shortened to 3 chains x (2+6) sweeps."""
+    import paper_0801_1222_amd as P
+    beta, U, t = 20.0, 4.8, 1.0
+    dtaus = [0.4, 0.333, 0.286, 0.25, 0.2, 0.167, 0.125]
+    n_iw = 4000
+    bath = OB.semicircle_iw(beta, t, n_iw)
+    out = P.multigrid_solve(ctx, bath, t * t, U, beta, dtaus, seed=3, n_fine=200, n_chains=3,
+                            warmup=2, sweeps=6)
+    ref = OMG.multigrid_solve(bath, t * t, U, beta, dtaus, seed=3, n_chains=3, warmup=2,
+                              sweeps=6, n_rec=100, n_fine=200)
+    assert out["Ls"] == [50, 60, 70, 80, 100, 120, 160]
+    for i in range(len(dtaus)):
+        assert np.abs(out["g_grids"][i] - ref["grids"][i]["g"]).max() < 1e-10
+    assert np.abs(out["g"] - ref["g"]).max() < 1e-9
+    assert np.abs(out["g_err"] - ref["g_err"]).max() < 1e-9
+
+
+def test_multigrid_u0_is_exact(ctx):
+    import paper_0801_1222_amd as P
+    beta, t = 10.0, 1.0
+    bath = OB.semicircle_iw(beta, t, 4000)
+    out = P.multigrid_solve(ctx, bath, 1.0, 0.0, beta, [0.5, 0.4, 0.25], seed=0, n_fine=60,
+                            n_chains=2, warmup=1, sweeps=2)
+    exact = OB.iw_to_tau(bath, 1.0, beta, out["tau"])
+    exact[-1] = 1.0 - exact[0]
+    assert np.abs(out["g"] - exact).max() < 1e-11
+
+
+def test_multigrid_atomic_limit(ctx):
+    import paper_0801_1222_amd as P
+    beta, U = 4.0, 4.0
+    bath = 1.0 / (1j * OB.matsubara(beta, 4000))
+    out = P.multigrid_solve(ctx, bath, 0.0, U, beta, [0.5, 0.4, 0.25], seed=5, n_fine=41,
+                            n_chains=64, warmup=20, sweeps=400, mode="mixed", delay_k=16)
+    exact = OH.atomic_limit_g(U, beta, out["tau"])
+    z = np.abs(out["g"] - exact)[1:-1] / out["g_err"][1:-1]
+    assert z.max() < 4.5
+
+
+def test_bethe_cycle_at_u0_is_a_fixed_point(ctx):
+    import paper_0801_1222_amd as P
+    beta, t = 10.0, 1.0
+    bath = P.bethe_semicircle_bath(beta, t, 3000)
+    for _ in range(2):
+        out = P.multigrid_solve(ctx, bath, t * t, 0.0, beta, [0.5, 0.4, 0.25], seed=1,
+                                n_fine=200, n_chains=2, warmup=1, sweeps=1)
+        new = P.dmft_bethe_step(out["g"], bath, t * t, 0.0, beta, t)
+        assert np.abs(new - bath).max() < 1e-10
+        bath = new
+
+
+@pytest.mark.parametrize("mode", ["rank1", "delayed"])
+def test_large_L_1000_matches_oracle(ctx, mode):
+    """L = 1000 (beta=100, dtau=0.1) takes the 8-wide LU panel; one sweep, two recomputes."""
+    import paper_0801_1222_amd as P
+    beta, U, L, seed = 100.0, 4.6, 1000, 2
+    g0 = OB.bath_to_tau(OB.semicircle_iw(beta, 1.0, 40000), 1.0, beta, L)
+    out = P.hfqmc_solve(ctx, g0, U, beta, beta / L, seed, n_chains=1, warmup=0, sweeps=1,
+                        mode=mode, delay_k=32, recompute_every=200, n_bins=1,
+                        flip_cap=4000, want_chain=True)
+    ref = OH.run_chain(g0, U, beta, seed, chain=0, warmup=0, sweeps=1, n_rec=200)
+    assert list(out["flips"][0]) == [sw * L + l for sw, l in ref["flips"]]
+    got = out["chain_g"][0][0] / out["chain_n"][0][0]
+    assert np.abs(got - ref["bins_g"][0]).max() < 1e-10
+    assert out["stats"]["n_recomputes"] == ref["n_recomputes"]
+    assert out["stats"]["max_drift"] < 1e-9
+
+
+def test_large_L_2000_final_green_is_exact(ctx):
+    """L = 2000 (beta=100, dtau=0.05) takes the 4-wide LU panel: after a sweep with
+    recomputes, G must equal the exact Dyson solution for the final field."""
+    import paper_0801_1222_amd as P
+    beta, U, L, seed = 100.0, 5.0, 2000, 1
+    g0 = OB.bath_to_tau(OB.semicircle_iw(beta, 1.0, 40000), 1.0, beta, L)
+    out = P.hfqmc_solve(ctx, g0, U, beta, beta / L, seed, n_chains=1, warmup=0, sweeps=1,
+                        mode="delayed", delay_k=64, recompute_every=300, n_bins=1,
+                        flip_cap=8000, want_green=True)
+    flips = out["flips"][0]
+    s = OB  # noqa: F841  (field reconstructed below)
+    from oracle import philox
+    field = philox.initial_field(seed, 0, 0, L).astype(np.int64)
+    for code in flips:
+        field[code % L] *= -1
+    lam = OH.hs_lambda(U, beta / L)
+    Gu, Gd = OH.green_from_field(OH.g0_matrix(g0), field, lam)
+    assert np.abs(out["green"][0, 0] - Gu).max() < 1e-9
+    assert np.abs(out["green"][0, 1] - Gd).max() < 1e-9
+    assert out["stats"]["n_recomputes"] >= 2
+    assert out["stats"]["max_drift"] < 1e-9
+
+
+def test_degenerate_sizes(ctx):
+    """L = 2, one chain, one sweep; and a single measured sweep with many chains."""
+    import paper_0801_1222_amd as P
+    g0 = np.array([0.5, 0.3])
+    out = P.hfqmc_solve(ctx, g0, 2.0, 1.0, 0.5, 0, n_chains=1, warmup=0, sweeps=1, n_bins=1,
+                        flip_cap=10, want_chain=True)
+    ref = OH.run_chain(g0, 2.0, 1.0, 0, warmup=0, sweeps=1)
+    assert list(out["flips"][0]) == [sw * 2 + l for sw, l in ref["flips"]]
+    assert np.abs(out["chain_g"][0][0] - ref["bins_g"][0]).max() < 1e-12
+    out = P.hfqmc_solve(ctx, g0, 2.0, 1.0, 0.5, 0, n_chains=300, warmup=0, sweeps=1,
+                        mode="mixed", delay_k=2)
+    assert np.all(np.isfinite(out["g"]))
