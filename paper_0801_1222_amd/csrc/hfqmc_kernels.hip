@@ -906,29 +906,45 @@ __device__ __forceinline__ int sweep_rank1(const SweepParams& p, const Chain& ch
       yd[i] = mul_nc(cd, ch.Gd[(long long)l * L + i]);
     }
     __syncthreads();
-    // G += x y^T, both spins, two consecutive elements per thread
+    // G += x y^T, both spins: thread -> (column pair, row group); the pair's
+    // y values stay in registers, x is an LDS broadcast per row
     {
-      long long idx = 2 * (long long)threadIdx.x;
-      int i = (int)(idx / L), j = (int)(idx - (long long)i * L);
-      const long long step = 2 * (long long)kThreads;
-      const int di = (int)(step / L), dj = (int)(step - (long long)di * L);
-      for (; idx < L2; idx += step) {
-        int i1 = i, j1 = j + 1;
-        if (j1 == L) {
-          j1 = 0;
-          ++i1;
-        }
-        ch.Gu[idx] = axpy_nc(ch.Gu[idx], xu[i], yu[j]);
-        ch.Gd[idx] = axpy_nc(ch.Gd[idx], xd[i], yd[j]);
-        if (idx + 1 < L2) {
-          ch.Gu[idx + 1] = axpy_nc(ch.Gu[idx + 1], xu[i1], yu[j1]);
-          ch.Gd[idx + 1] = axpy_nc(ch.Gd[idx + 1], xd[i1], yd[j1]);
-        }
-        i += di;
-        j += dj;
-        if (j >= L) {
-          j -= L;
-          ++i;
+      const int ncp = (L + 1) >> 1;
+      const int rg = max(1, kThreads / ncp);
+      const int t = threadIdx.x;
+      if (t < ncp * rg) {
+        const int cp = t % ncp, r0 = t / ncp;
+        const int j = 2 * cp;
+        const bool two = j + 1 < L;
+        const double yu0 = yu[j], yd0 = yd[j];
+        const double yu1 = two ? yu[j + 1] : 0.0, yd1 = two ? yd[j + 1] : 0.0;
+        if ((L & 1) == 0) {
+#pragma unroll 4
+          for (int i = r0; i < L; i += rg) {
+            const double xui = xu[i], xdi = xd[i];
+            double2* gu = reinterpret_cast<double2*>(ch.Gu + (long long)i * L + j);
+            double2* gd = reinterpret_cast<double2*>(ch.Gd + (long long)i * L + j);
+            double2 a = *gu, b = *gd;
+            a.x = axpy_nc(a.x, xui, yu0);
+            a.y = axpy_nc(a.y, xui, yu1);
+            b.x = axpy_nc(b.x, xdi, yd0);
+            b.y = axpy_nc(b.y, xdi, yd1);
+            *gu = a;
+            *gd = b;
+          }
+        } else {
+#pragma unroll 4
+          for (int i = r0; i < L; i += rg) {
+            const double xui = xu[i], xdi = xd[i];
+            double* gu = ch.Gu + (long long)i * L + j;
+            double* gd = ch.Gd + (long long)i * L + j;
+            gu[0] = axpy_nc(gu[0], xui, yu0);
+            gd[0] = axpy_nc(gd[0], xdi, yd0);
+            if (two) {
+              gu[1] = axpy_nc(gu[1], xui, yu1);
+              gd[1] = axpy_nc(gd[1], xdi, yd1);
+            }
+          }
         }
       }
     }
@@ -1060,27 +1076,40 @@ __device__ __forceinline__ void flush_vectors(const double* __restrict__ G, int 
                                               const int* __restrict__ F,
                                               const double* __restrict__ TS,
                                               double* __restrict__ X, double* __restrict__ Y) {
+  constexpr int KS = kMaxK / 4;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int li = lane & 15, lq = lane >> 4;
   const int ks = (m + 3) >> 2;
   const int mb = (m + 15) >> 4;
   const int nb = (L + 15) >> 4;
-  // X tiles: row block rb (of L), column block jb (of m); Y tiles: row block jb (of m), column block cb
+  // flipped slice of each k-step of this lane (clamped for k >= m; those operands are zeroed)
+  int fk[KS];
+#pragma unroll
+  for (int q = 0; q < KS; ++q) {
+    const int i = 4 * q + lq;
+    fk[q] = l0 + F[min(i, m - 1)];
+  }
+  // X tiles: row block rb (of L), column block jb (of m); Y tiles: row block jb (of m),
+  // column block cb.  All operands of a tile are loaded before its MFMA chain.
   const int nx = nb * mb;
   for (int tile = wv; tile < 2 * nx; tile += kThreads / 64) {
     doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+    double av[KS], bv[KS];
     if (tile < nx) {
       const int rb = tile / mb, jb = tile - rb * mb;
       const int q = min(rb * 16 + li, L - 1);
       const int j = jb * 16 + li;
-#pragma unroll 4
-      for (int s4 = 0; s4 < ks; ++s4) {
+#pragma unroll
+      for (int s4 = 0; s4 < KS; ++s4) {
         const int i = 4 * s4 + lq;
-        const int fi = (i < m) ? l0 + F[i] : 0;
-        const double c0 = (i < m) ? G[q * L + fi] - (q == fi ? 1.0 : 0.0) : 0.0;
-        const double tv = (i < m && j < m) ? (i < j ? TS[i * kKP + j] : (i == j ? 1.0 : 0.0)) : 0.0;
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(c0, tv, acc, 0, 0, 0);
+        const double g = G[q * L + fk[s4]];
+        av[s4] = (i < m) ? g - (q == fk[s4] ? 1.0 : 0.0) : 0.0;
+        const double tsv = TS[min(i, kMaxK - 1) * kKP + min(j, kMaxK - 1)];
+        bv[s4] = (i < m && j < m) ? (i < j ? tsv : (i == j ? 1.0 : 0.0)) : 0.0;
       }
+#pragma unroll
+      for (int s4 = 0; s4 < KS; ++s4)
+        if (s4 < ks) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s4], bv[s4], acc, 0, 0, 0);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int qq = rb * 16 + 4 * r + lq;
@@ -1091,14 +1120,17 @@ __device__ __forceinline__ void flush_vectors(const double* __restrict__ G, int 
       const int jb = t2 / nb, cb = t2 - jb * nb;
       const int jr = jb * 16 + li;
       const int col = min(cb * 16 + li, L - 1);
-#pragma unroll 4
-      for (int s4 = 0; s4 < ks; ++s4) {
+#pragma unroll
+      for (int s4 = 0; s4 < KS; ++s4) {
         const int i = 4 * s4 + lq;
-        const double sv = (jr < m && i < m && i <= jr) ? TS[jr * kKP + i] : 0.0;
-        const int fi = (i < m) ? l0 + F[i] : 0;
-        const double r0 = (i < m) ? G[fi * L + col] : 0.0;
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(sv, r0, acc, 0, 0, 0);
+        const double tsv = TS[min(jr, kMaxK - 1) * kKP + min(i, kMaxK - 1)];
+        av[s4] = (jr < m && i < m && i <= jr) ? tsv : 0.0;
+        const double g = G[fk[s4] * L + col];
+        bv[s4] = (i < m) ? g : 0.0;
       }
+#pragma unroll
+      for (int s4 = 0; s4 < KS; ++s4)
+        if (s4 < ks) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s4], bv[s4], acc, 0, 0, 0);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int jj = jb * 16 + 4 * r + lq;
