@@ -12,8 +12,9 @@ chains, the plain FP64 rank-1 path timed beside it on the same chains, the
 roofline of the persistent sweep kernel (k_sweeps) from HIP events, and the
 CPU oracle timed on a bounded sample of the workload.  Progress goes to stderr.
 
-  python bench.py                      # mixed precision, k = 64 (default)
+  python bench.py                      # mixed precision, autotuned k (default)
   python bench.py --mode delayed       # delayed rank-k, FP64 flush
+  python bench.py --delay-k 64         # fixed k instead of the autotuner
   python bench.py --calib-copy         # copy kernel used to scale PMC counters
 """
 import argparse
@@ -71,6 +72,22 @@ def algorithmic_work(L, st, n_chains, measured_sweeps, mode):
     return bytes_, f64, f32
 
 
+def composite_bound_s(L, st, n_chains, measured_sweeps, mode):
+    """Sum over phases of max(bytes / HBM peak, flops / matrix-core peak) (phases not overlapped)."""
+    L2 = float(L) * L
+    n_acc = st["n_accepted"]
+    n_rec = st["n_recomputes"] + n_chains
+    n_flush = st.get("n_flushes", 0)
+    bw, f64p, f32p = HBM_PEAK_GBS * 1e9, FP64_PEAK_TFLOPS * 1e12, FP32_PEAK_TFLOPS * 1e12
+    if mode == "rank1":
+        upd = max(32.0 * L2 * n_acc / bw, 4.0 * L2 * n_acc / f64p)
+    else:
+        upd = max(32.0 * L2 * n_flush / bw, 4.0 * L2 * n_acc / (f32p if mode == "mixed" else f64p))
+    rec = max(24.0 * L2 * n_rec / bw, n_rec * 2.0 * (8.0 / 3.0) * L2 * L / f64p)
+    meas = 16.0 * L2 * n_chains * measured_sweeps / bw
+    return upd + rec + meas
+
+
 def roofline(L, st, n_chains, measured_sweeps, mode, t_kernel):
     """Roofline entry of the sweep kernel: the resource whose lower-bound time is largest."""
     by, f64, f32 = algorithmic_work(L, st, n_chains, measured_sweeps, mode)
@@ -88,6 +105,7 @@ def roofline(L, st, n_chains, measured_sweeps, mode, t_kernel):
     main["secondary"] = other
     main["lower_bound_s"] = {"hbm": t_hbm, "mfma_fp64_equiv": t_mfma}
     main["algorithmic"] = {"bytes": by, "fp64_flops": f64, "fp32_flops": f32}
+    main["composite_frac"] = composite_bound_s(L, st, n_chains, measured_sweeps, mode) / t_kernel
     return main
 
 
@@ -160,7 +178,8 @@ def main():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--mode", default="mixed", choices=["rank1", "delayed", "mixed"])
-    ap.add_argument("--delay-k", type=int, default=64)
+    ap.add_argument("--delay-k", type=int, default=0,
+                    help="delayed rank k (0 = autotuned over 16/32/64 and the LU panel width)")
     ap.add_argument("--chain-sweeps", type=int, default=None,
                     help="measured sweeps per chain (default: the workload's 2000)")
     ap.add_argument("--chain-warmup", type=int, default=None,
@@ -200,31 +219,55 @@ def main():
              % (args.mode, w["n_chains"], w["warmup"], w["sweeps"]))
 
     def solve(mode, warmup, sweeps):
+        # host-pointer entry (bath and results cross PCIe; used for the warm-up step)
         return P.hfqmc_solve(ctx, g0, w["U"], w["beta"], w["dtau"], w["seed"],
                              n_chains=w["n_chains"], warmup=warmup, sweeps=sweeps, mode=mode,
                              delay_k=args.delay_k if mode != "rank1" else 0)
 
+    # device-resident input and outputs for the timed steps
+    g0_d = torch.tensor(g0, dtype=torch.float64, device="cuda")
+    g_d = torch.zeros(L + 1, dtype=torch.float64, device="cuda")
+    e_d = torch.zeros(L + 1, dtype=torch.float64, device="cuda")
+    d_d = torch.zeros(2, dtype=torch.float64, device="cuda")
+
+    def solve_dev():
+        return P.hfqmc_solve_dev(ctx, g0_d.data_ptr(), L, w["U"], w["beta"], w["dtau"], w["seed"],
+                                 g_d.data_ptr(), e_d.data_ptr(), d_d.data_ptr(),
+                                 n_chains=w["n_chains"], warmup=w["warmup"], sweeps=w["sweeps"],
+                                 mode=args.mode,
+                                 delay_k=args.delay_k if args.mode != "rank1" else 0)
+
+    chain_sweeps = w["n_chains"] * (w["warmup"] + w["sweeps"])
+    host_rate = None
+    tune = None
     for i in range(args.warmup):
         r = solve(args.mode, w["warmup"], w["sweeps"])
-        progress("warmup step %d done, kernel %.2f s" % (i, r["stats"]["seconds_kernel"]))
+        rs = r["stats"]
+        host_rate = chain_sweeps / (rs["seconds_total"] - rs["seconds_autotune"])
+        if rs["autotuned"] and rs["seconds_autotune"] > 0:
+            tune = dict(delay_k=rs["delay_k"], lu_panel=rs["lu_panel"],
+                        seconds=rs["seconds_autotune"])
+        progress("warmup step %d done, kernel %.2f s (autotune %.2f s)"
+                 % (i, rs["seconds_kernel"], rs["seconds_autotune"]))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    outs = []
+    stats = []
     for i in range(args.steps):
-        outs.append(solve(args.mode, w["warmup"], w["sweeps"]))
-        progress("timed step %d done, kernel %.2f s" % (i, outs[-1]["stats"]["seconds_kernel"]))
+        stats.append(solve_dev())
+        progress("timed step %d done, kernel %.2f s" % (i, stats[-1]["seconds_kernel"]))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    chain_sweeps = w["n_chains"] * (w["warmup"] + w["sweeps"])
     value = chain_sweeps * args.steps / elapsed
-    kern = [o["stats"]["seconds_kernel"] for o in outs]
-    st = outs[-1]["stats"]
+    kern = [s_["seconds_kernel"] for s_ in stats]
+    st = stats[-1]
     t_k = float(np.mean(kern))
     rf = roofline(L, st, w["n_chains"], w["sweeps"], args.mode, t_k)
     rf["traffic"] = measured_traffic(args.mode, chain_sweeps)
     rf["kernel"] = "k_sweeps"
     rf["kernel_ms"] = t_k * 1e3
-    g = outs[-1]["g"]
+    g = g_d.cpu().numpy()
+    ge = e_d.cpu().numpy()
+    dd = d_d.cpu().numpy()
     checks = dict(
         ph_symmetry_max=float(np.abs(g[1:L] - g[1:L][::-1]).max()),
         g0_minus_half=float(abs(g[0] - 0.5)),
@@ -232,10 +275,10 @@ def main():
         acc_rate=float(st["acc_rate"]),
         bad_ratios=int(st["n_bad_ratio"]),
         singular=int(st["n_singular"]),
-        docc=float(outs[-1]["D"]),
-        docc_err=float(outs[-1]["D_err"]),
+        docc=float(dd[0]),
+        docc_err=float(dd[1]),
         g_beta_half=float(g[L // 2]),
-        g_beta_half_err=float(outs[-1]["g_err"][L // 2]),
+        g_beta_half_err=float(ge[L // 2]),
     )
     rank1 = None
     if args.rank1_sweeps > 0 and args.mode != "rank1":
@@ -276,7 +319,10 @@ def main():
                                % (w["warmup"], w["sweeps"]),
                    "mode": args.mode, "delay_k": st["delay_k"],
                    "recompute_every": st["recompute_every"], "n_chains": w["n_chains"], "L": L,
-                   "workgroups": st["n_workgroups"]},
+                   "workgroups": st["n_workgroups"], "lu_panel": st["lu_panel"],
+                   "graph": bool(st["graph"]), "autotuned": bool(st["autotuned"])},
+        "autotune": tune,
+        "host_entry_sweeps_per_s": host_rate,
         "roofline": rf,
         "plain_fp64_rank1": rank1,
         "speedup_vs_rank1": (chain_sweeps / t_k) / rank1["sweeps_per_s"] if rank1 else None,

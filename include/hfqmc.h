@@ -50,8 +50,10 @@ typedef struct hfqmc_ctx hfqmc_ctx;
  * or is not gfx950. */
 int hfqmc_create(hfqmc_ctx **out, int device);
 void hfqmc_destroy(hfqmc_ctx *ctx);
-/* Launch all device work on `stream` (a hipStream_t; NULL = the null
- * stream).  The stream must outlive its use by the context. */
+/* Launch all device work on `stream` (a hipStream_t of the HIP runtime this
+ * library is linked with; NULL = the null stream).  The stream must outlive
+ * its use by the context.  Streams of another HIP runtime in the process
+ * (PyTorch ships its own) are not valid here; the null stream is common. */
 int hfqmc_set_stream(hfqmc_ctx *ctx, void *stream);
 /* Message for the last nonzero return on the calling thread. */
 const char *hfqmc_last_error(void);
@@ -65,6 +67,13 @@ enum {
                                   recompute stay FP64 */
 };
 
+/* Option bits (hfqmc_opts.flags). */
+enum {
+  HFQMC_FLAG_EAGER = 1,      /* launch the kernels one by one instead of replaying a captured
+                                HIP graph of the launch sequence (results are identical) */
+  HFQMC_FLAG_HEAT_BATH = 2   /* heat-bath acceptance u < R/(1+R) instead of Metropolis u < R */
+};
+
 typedef struct {
   int32_t n_chains;         /* independent chains per grid; chain c uses Philox key (seed + c, grid) */
   int32_t mode;             /* HFQMC_MODE_* */
@@ -72,9 +81,12 @@ typedef struct {
   int64_t sweeps;           /* measured sweeps per chain (>= 1) */
   int32_t recompute_every;  /* accepted flips between FP64 Dyson recomputes;
                                0 -> 100 (rank-1) or 4*k (delayed) */
-  int32_t delay_k;          /* delayed modes: max pending flips k (2..64); 0 -> autotune */
+  int32_t delay_k;          /* delayed modes: max pending flips k (2..64); 0 -> autotune:
+                               k in {16, 32, 64} and the LU panel width are chosen by timing
+                               short trial launches of the same grids and chain count, and
+                               the choice is cached in the context */
   int32_t n_bins;           /* measurement bins per chain; 0 -> 20 if n_chains == 1 else 1 */
-  int32_t reserved;
+  int32_t flags;            /* HFQMC_FLAG_* bits */
   double drift_limit;       /* 0: report only; > 0: HFQMC_EDRIFT if any recompute drift exceeds it */
   /* Optional test hooks (NULL to disable).  Flip codes are sweep * L + l. */
   int64_t *flip_log;        /* [n_grids][n_chains][flip_cap] accepted flips, in order */
@@ -107,7 +119,10 @@ typedef struct {
   int32_t delay_k;          /* k actually used (delayed modes) */
   int32_t recompute_every;  /* recompute interval actually used */
   int32_t n_workgroups;     /* persistent workgroups launched */
-  int32_t reserved;
+  int32_t lu_panel;         /* LU panel width of the recompute */
+  int32_t graph;            /* 1 if the launch sequence ran as a captured HIP graph */
+  int32_t autotuned;        /* 1 if k and the panel width came from the autotuner */
+  double seconds_autotune;  /* time spent in trial launches during this call (0 on a cache hit) */
 } hfqmc_stats;
 
 /* Fixed-dtau solve: hfqmc_solve(G0(tau), U, beta, dtau, sweeps, seed) -> G(tau).
@@ -120,6 +135,18 @@ typedef struct {
 int hfqmc_solve(hfqmc_ctx *ctx, const double *g0_tau, int32_t L, double U, double beta,
                 double dtau, uint64_t seed, const hfqmc_opts *opts,
                 double *g_tau, double *g_err, double *docc, hfqmc_stats *stats);
+
+/* hfqmc_solve with device memory: g0_tau, g_tau, g_err and docc are device
+ * pointers (hipMalloc'd or torch tensors on the context's device; g_err and
+ * docc may be NULL) and are read and written on the context's stream.  The
+ * statistics and the opts test hooks stay host pointers.  The buffers are
+ * read and written by kernels, so they may also come from another HIP runtime
+ * loaded in the same process (PyTorch's).  Same semantics and errors as
+ * hfqmc_solve, except that g0_tau is not checked for finiteness on the host
+ * (a non-finite bath surfaces as HFQMC_ENUMERIC). */
+int hfqmc_solve_dev(hfqmc_ctx *ctx, const double *g0_tau, int32_t L, double U, double beta,
+                    double dtau, uint64_t seed, const hfqmc_opts *opts,
+                    double *g_tau, double *g_err, double *docc, hfqmc_stats *stats);
 
 /* Batched solve of several grids in ONE persistent launch (the data-parallel
  * core of a multigrid step): grid i has L[i] slices, bath g0_tau (concatenated,

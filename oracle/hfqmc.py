@@ -116,11 +116,13 @@ def measure(Gu, Gd):
 
 def run_chain(g_tau, U, beta, seed, chain=0, grid_id=0, warmup=0, sweeps=1,
               n_rec=100, n_bins=1, replay=None, delay_k=0, flush_fp32=False,
-              keep_trace=False):
+              keep_trace=False, heat_bath=False):
     """One Markov chain of fixed-dtau HF-QMC.
 
-    Sweep order l = 0..L-1; Metropolis acceptance u < R with u from stream 0 of
-    the Philox layout; R <= 0 or NaN counts as a reject and is tallied.
+    Sweep order l = 0..L-1; Metropolis acceptance u < R (or, with
+    ``heat_bath``, u < R / (1 + R): both satisfy detailed balance for weights
+    proportional to det M_up det M_dn) with u from stream 0 of the Philox
+    layout; R <= 0 or NaN counts as a reject and is tallied.
     Every ``n_rec`` accepted flips (counted across warm-up) G is recomputed
     from the field and the largest elementwise change is kept as the drift.
     Measurements are taken after every sweep >= warmup.
@@ -196,7 +198,7 @@ def run_chain(g_tau, U, beta, seed, chain=0, grid_id=0, warmup=0, sweeps=1,
             if replay is not None:
                 accept = (sw, l) in replay
             else:
-                accept = (not bad) and (u[l] < R)
+                accept = (not bad) and (u[l] < (R / (1.0 + R) if heat_bath else R))
             if not accept:
                 continue
             n_acc += 1

@@ -29,7 +29,7 @@ class Opts(C.Structure):
     _fields_ = [
         ("n_chains", _i32), ("mode", _i32),
         ("warmup", _i64), ("sweeps", _i64),
-        ("recompute_every", _i32), ("delay_k", _i32), ("n_bins", _i32), ("reserved", _i32),
+        ("recompute_every", _i32), ("delay_k", _i32), ("n_bins", _i32), ("flags", _i32),
         ("drift_limit", _f64),
         ("flip_log", _pi64), ("flip_count", _pi64), ("flip_cap", _i64),
         ("replay_log", _pi64), ("replay_count", _pi64), ("replay_cap", _i64),
@@ -47,11 +47,12 @@ class Stats(C.Structure):
         ("chain_s_measure", _f64),
         ("chain_s_lu_build", _f64), ("chain_s_lu_panel", _f64), ("chain_s_lu_strip", _f64),
         ("chain_s_lu_back", _f64),
-        ("delay_k", _i32), ("recompute_every", _i32), ("n_workgroups", _i32), ("reserved", _i32),
+        ("delay_k", _i32), ("recompute_every", _i32), ("n_workgroups", _i32), ("lu_panel", _i32),
+        ("graph", _i32), ("autotuned", _i32), ("seconds_autotune", _f64),
     ]
 
     def as_dict(self):
-        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 _ctx_p = C.c_void_p
@@ -67,6 +68,9 @@ lib.hfqmc_last_error.restype = C.c_char_p
 lib.hfqmc_solve.argtypes = [_ctx_p, _pd, _i32, _f64, _f64, _f64, _u64, C.POINTER(Opts),
                             _pd, _pd, _pd, C.POINTER(Stats)]
 lib.hfqmc_solve.restype = C.c_int
+lib.hfqmc_solve_dev.argtypes = [_ctx_p, C.c_void_p, _i32, _f64, _f64, _f64, _u64, C.POINTER(Opts),
+                                C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(Stats)]
+lib.hfqmc_solve_dev.restype = C.c_int
 lib.hfqmc_solve_grids.argtypes = [_ctx_p, _i32, _pi32, _pd, _f64, _f64, _u64, C.POINTER(Opts),
                                   _pd, _pd, _pd, C.POINTER(Stats)]
 lib.hfqmc_solve_grids.restype = C.c_int
@@ -80,8 +84,11 @@ lib.bethe_semicircle_bath.restype = C.c_int
 lib.bath_to_tau.argtypes = [_pd, _i32, _f64, _f64, _i32, _pd]
 lib.bath_to_tau.restype = C.c_int
 
+FLAG_EAGER = 1       # launch kernels one by one (no captured graph)
+FLAG_HEAT_BATH = 2   # heat-bath acceptance u < R/(1+R)
+
 EXPORTED = ["hfqmc_create", "hfqmc_destroy", "hfqmc_set_stream", "hfqmc_last_error",
-            "hfqmc_solve", "hfqmc_solve_grids", "multigrid_solve", "dmft_bethe_step",
+            "hfqmc_solve", "hfqmc_solve_dev", "hfqmc_solve_grids", "multigrid_solve", "dmft_bethe_step",
             "bethe_semicircle_bath", "bath_to_tau"]
 
 

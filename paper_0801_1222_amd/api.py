@@ -2,11 +2,13 @@
 
   ctx = Context(0)
   out = hfqmc_solve(ctx, g0_tau, U, beta, dtau, seed, n_chains=..., ...)
+  hfqmc_solve_dev(ctx, g0_dev, L, U, beta, dtau, seed, g_dev, ...)   # device pointers
   out = hfqmc_solve_grids(ctx, Ls, [g0_tau_i], U, beta, seed, ...)
   out = multigrid_solve(ctx, bath_iw, m3, U, beta, dtaus, seed, n_fine, ...)
   new_bath = dmft_bethe_step(g_fine, bath_iw, m3, U, beta, t)
 """
 import ctypes as C
+import sys
 
 import numpy as np
 
@@ -17,15 +19,28 @@ MODES = {"rank1": 0, "delayed": 1, "mixed": 2}
 
 
 class Context:
-    """Owns one hfqmc_ctx (device buffers, stream binding)."""
+    """Owns one hfqmc_ctx (device buffers, stream binding).
+
+    PyTorch-ROCm ships its own HIP runtime next to the one this library links;
+    both drive the same device through one HSA runtime, so device addresses are
+    shared, but PyTorch's runtime must come up first: when torch is imported,
+    its device is initialised before the context is created.
+    """
 
     def __init__(self, device=0):
+        torch = sys.modules.get("torch")
+        if torch is not None and torch.cuda.is_available():
+            torch.cuda.init()
         self._p = C.c_void_p()
         N.check(N.lib.hfqmc_create(C.byref(self._p), int(device)), "hfqmc_create")
 
     def set_stream(self, stream):
-        """Bind a HIP stream: a torch.cuda.Stream, a raw handle (int) or None."""
+        """Bind a HIP stream: a raw handle of this library's runtime, None, or a
+        torch.cuda.Stream that is the null stream (PyTorch's other streams belong
+        to its own runtime and cannot be shared)."""
         handle = getattr(stream, "cuda_stream", stream)
+        if hasattr(stream, "cuda_stream") and handle:
+            raise ValueError("only PyTorch's null stream can be shared with libhfqmc")
         N.check(N.lib.hfqmc_set_stream(self._p, C.c_void_p(handle or 0)), "hfqmc_set_stream")
 
     @property
@@ -44,8 +59,13 @@ class Context:
             pass
 
 
-def _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drift_limit):
+def _flags(eager=False, heat_bath=False):
+    return (N.FLAG_EAGER if eager else 0) | (N.FLAG_HEAT_BATH if heat_bath else 0)
+
+
+def _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drift_limit, flags=0):
     o = N.Opts()
+    o.flags = int(flags)
     o.n_chains = int(n_chains)
     o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
     o.warmup = int(warmup)
@@ -126,11 +146,13 @@ class _Hooks:
 
 def hfqmc_solve(ctx, g0_tau, U, beta, dtau, seed, n_chains=1, warmup=0, sweeps=1,
                 mode="rank1", recompute_every=0, delay_k=0, n_bins=0, drift_limit=0.0,
-                flip_cap=0, replay=None, want_chain=False, want_green=False):
+                flip_cap=0, replay=None, want_chain=False, want_green=False, eager=False,
+                heat_bath=False):
     """Fixed-dtau solve; returns dict(g, g_err, D, D_err, stats, [hooks])."""
     g0 = np.ascontiguousarray(g0_tau, dtype=np.float64)
     L = g0.shape[0]
-    o = _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drift_limit)
+    o = _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drift_limit,
+              _flags(eager, heat_bath))
     hk = _Hooks(o, 1, n_chains, [L], n_bins, flip_cap,
                 [replay] if replay is not None else None, want_chain, want_green)
     g = np.zeros(L + 1)
@@ -152,16 +174,33 @@ def hfqmc_solve(ctx, g0_tau, U, beta, dtau, seed, n_chains=1, warmup=0, sweeps=1
     return out
 
 
+def hfqmc_solve_dev(ctx, g0_tau, L, U, beta, dtau, seed, g_tau, g_err=None, docc=None,
+                    n_chains=1, warmup=0, sweeps=1, mode="rank1", recompute_every=0, delay_k=0,
+                    n_bins=0, drift_limit=0.0, eager=False, heat_bath=False):
+    """hfqmc_solve on device buffers (raw device addresses as ints, e.g. a torch
+    tensor's data_ptr(), on the context's device and stream); returns the stats."""
+    o = _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drift_limit,
+              _flags(eager, heat_bath))
+    st = N.Stats()
+    rc = N.lib.hfqmc_solve_dev(ctx.handle, C.c_void_p(int(g0_tau)), int(L), float(U), float(beta),
+                               float(dtau), int(seed), C.byref(o), C.c_void_p(int(g_tau)),
+                               C.c_void_p(int(g_err) if g_err else None),
+                               C.c_void_p(int(docc) if docc else None), C.byref(st))
+    N.check(rc, "hfqmc_solve_dev")
+    return st.as_dict()
+
+
 def hfqmc_solve_grids(ctx, Ls, g0_taus, U, beta, seed, n_chains=1, warmup=0, sweeps=1,
                       mode="rank1", recompute_every=0, delay_k=0, n_bins=0, drift_limit=0.0,
-                      flip_cap=0, replay=None, want_chain=False):
+                      flip_cap=0, replay=None, want_chain=False, eager=False, heat_bath=False):
     """Several grids in one persistent launch; per-grid lists in the result."""
     Ls = [int(L) for L in Ls]
     n = len(Ls)
     Larr = np.array(Ls, dtype=np.int32)
     g0 = np.ascontiguousarray(np.concatenate([np.asarray(x, dtype=np.float64) for x in g0_taus]))
     assert g0.shape[0] == sum(Ls)
-    o = _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drift_limit)
+    o = _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drift_limit,
+              _flags(eager, heat_bath))
     hk = _Hooks(o, n, n_chains, Ls, n_bins, flip_cap, replay, want_chain, False)
     P = sum(L + 1 for L in Ls)
     g = np.zeros(P)
@@ -185,12 +224,13 @@ def hfqmc_solve_grids(ctx, Ls, g0_taus, U, beta, seed, n_chains=1, warmup=0, swe
 
 def multigrid_solve(ctx, bath_iw, bath_m3, U, beta, dtaus, seed, n_fine=200, n_chains=1,
                     warmup=0, sweeps=1, mode="rank1", recompute_every=0, delay_k=0, n_bins=0,
-                    drift_limit=0.0):
+                    drift_limit=0.0, eager=False, heat_bath=False):
     """dtau -> 0 extrapolated G(tau_j), tau_j = j beta/(n_fine-1)."""
     b = np.ascontiguousarray(np.asarray(bath_iw, dtype=np.complex128)).view(np.float64)
     n_iw = b.shape[0] // 2
     dt = np.ascontiguousarray(dtaus, dtype=np.float64)
-    o = _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drift_limit)
+    o = _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drift_limit,
+              _flags(eager, heat_bath))
     Ls = [int(round(beta / x)) for x in dt]
     gf = np.zeros(n_fine)
     ef = np.zeros(n_fine)

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -76,16 +77,41 @@ struct Bump {
 
 }  // namespace
 
+// Autotuner choice for one (mode, chains, grids) shape.
+struct TuneChoice {
+  int delay_k;
+  int lu_nb;
+};
+
+// A captured launch sequence and the key of everything its kernels depend on.
+struct GraphEntry {
+  std::vector<unsigned long long> key;
+  hipGraphExec_t exec = nullptr;
+};
+
 struct hfqmc_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;  // private stream the launch sequence is captured on
   int n_cu = 0;
   int lds_max = 0;  // bytes of LDS a workgroup may allocate
   double wall_hz = 1e8;  // device wall-clock rate
   DevBuf work;
   DevBuf arena;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  std::map<std::vector<int>, TuneChoice> tune;  // key: mode, chains, L_0, L_1, ...
+  std::vector<GraphEntry> graphs;                // most recent first, at most kGraphCache
 };
+
+namespace {
+constexpr size_t kGraphCache = 4;
+
+void drop_graphs(hfqmc_ctx* c) {
+  for (auto& g : c->graphs)
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  c->graphs.clear();
+}
+}  // namespace
 
 extern "C" const char* hfqmc_last_error(void) { return g_err.c_str(); }
 
@@ -111,9 +137,10 @@ extern "C" int hfqmc_create(hfqmc_ctx** out, int device) {
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && khz > 0)
       c->wall_hz = khz * 1e3;
   }
-  if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+  if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
+      hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
     delete c;
-    return fail(HFQMC_EDEVICE, "hfqmc_create: hipEventCreate failed");
+    return fail(HFQMC_EDEVICE, "hfqmc_create: event or stream creation failed");
   }
   *out = c;
   return HFQMC_OK;
@@ -123,6 +150,9 @@ extern "C" void hfqmc_destroy(hfqmc_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
+  (void)hipDeviceSynchronize();
+  drop_graphs(c);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   c->work.release();
   c->arena.release();
   if (c->ev0) (void)hipEventDestroy(c->ev0);
@@ -158,12 +188,13 @@ int resolve_opts(const hfqmc_opts* o, Resolved* r) {
   r->mode = o->mode;
   r->warmup = o->warmup;
   r->sweeps = o->sweeps;
+  if (o->flags & ~(HFQMC_FLAG_EAGER | HFQMC_FLAG_HEAT_BATH)) return fail(HFQMC_EINVAL, "flags=0x%x", o->flags);
   if (o->mode == MODE_RANK1) {
     r->delay_k = 1;
     r->window_b = 1;
   } else {
-    int k = o->delay_k == 0 ? 32 : o->delay_k;
-    if (k < 2 || k > kMaxK) return fail(HFQMC_EINVAL, "delay_k=%d (2..%d)", k, kMaxK);
+    const int k = o->delay_k;   // 0: chosen by the autotuner before the launch
+    if (k != 0 && (k < 2 || k > kMaxK)) return fail(HFQMC_EINVAL, "delay_k=%d (2..%d)", k, kMaxK);
     r->delay_k = k;
     r->window_b = 64;  // slices per window; the kernel's diagonal block edge
   }
@@ -179,10 +210,91 @@ struct GridHost {
   double lam;
 };
 
-// Shared implementation of hfqmc_solve / hfqmc_solve_grids / multigrid_solve.
+// How a solve is called: host or device buffers, a cap on the LU panel width
+// (autotuner trials), and whether it is a trial launch of the autotuner.
+struct Call {
+  bool dev_io = false;
+  int nb_max = 0;
+  bool trial = false;
+};
+
 int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double* g0_tau, double U,
                      double beta, uint64_t seed, const hfqmc_opts* opts, double* g_tau,
-                     double* g_err, double* docc, hfqmc_stats* stats) {
+                     double* g_err, double* docc, hfqmc_stats* stats, const Call& call);
+
+// Autotuner: k in {16, 32, 64} (recompute interval 4k unless given) and the
+// LU panel width (the widest that fits, and 16 where 32 fits), each timed on a
+// short trial launch of the caller's grids and chain count (no warm-up, two
+// sweeps, eager launches); the fastest kernel time wins and is cached.
+int autotune(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double* g0_tau, bool dev_io,
+             double U, double beta, uint64_t seed, const hfqmc_opts* opts, int Lmax,
+             TuneChoice* out, double* seconds) {
+  std::vector<int> key = {opts->mode, opts->n_chains};
+  long long Lsum = 0;
+  for (int i = 0; i < n_grids; ++i) {
+    key.push_back(Ls[i]);
+    Lsum += Ls[i];
+  }
+  *seconds = 0.0;
+  auto it = c->tune.find(key);
+  if (it != c->tune.end()) {
+    *out = it->second;
+    return HFQMC_OK;
+  }
+  const auto t0 = std::chrono::steady_clock::now();
+  std::vector<double> g0h;
+  const double* g0 = g0_tau;
+  if (dev_io) {
+    g0h.resize(Lsum);
+    HIPCHK(hipMemcpyAsync(g0h.data(), g0_tau, sizeof(double) * Lsum, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    g0 = g0h.data();
+  }
+  int nb_widest = 0, scratch = 0;
+  (void)lds_bytes(Lmax, opts->mode, 0, &nb_widest, &scratch);
+  std::vector<int> nbs = {nb_widest};
+  if (nb_widest == 32) nbs.push_back(16);
+  hfqmc_opts to;
+  std::memset(&to, 0, sizeof to);
+  to.n_chains = opts->n_chains;
+  to.mode = opts->mode;
+  to.warmup = 0;
+  to.sweeps = 2;
+  to.recompute_every = opts->recompute_every;
+  to.n_bins = 1;
+  to.flags = (opts->flags & HFQMC_FLAG_HEAT_BATH) | HFQMC_FLAG_EAGER;
+  long long P = 0;
+  for (int i = 0; i < n_grids; ++i) P += Ls[i] + 1;
+  std::vector<double> gs(P), es(P), ds(2 * n_grids);
+  std::vector<hfqmc_stats> st(n_grids);
+  double best = INFINITY;
+  TuneChoice choice = {32, nb_widest};
+  for (int k : {16, 32, 64}) {
+    for (int nb : nbs) {
+      to.delay_k = k;
+      Call tc;
+      tc.nb_max = nb;
+      tc.trial = true;
+      const int rc = solve_grids_impl(c, n_grids, Ls, g0, U, beta, seed, &to, gs.data(), es.data(),
+                                      ds.data(), st.data(), tc);
+      if (rc != HFQMC_OK) return rc;
+      const double tk = st[0].seconds_kernel;
+      if (tk < best) {
+        best = tk;
+        choice = {k, nb};
+      }
+    }
+  }
+  c->tune[key] = choice;
+  *out = choice;
+  *seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return HFQMC_OK;
+}
+
+// Shared implementation of every solve entry point.
+int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double* g0_tau, double U,
+                     double beta, uint64_t seed, const hfqmc_opts* opts, double* g_tau,
+                     double* g_err, double* docc, hfqmc_stats* stats, const Call& call) {
   const auto t_start = std::chrono::steady_clock::now();
   if (!c) return fail(HFQMC_EINVAL, "ctx is NULL");
   if (!Ls || !g0_tau || !g_tau) return fail(HFQMC_EINVAL, "null input/output pointer");
@@ -200,12 +312,27 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
     Lsum += Ls[i];
   }
   if (opts->final_green && n_grids != 1) return fail(HFQMC_EINVAL, "final_green needs a single grid");
-  for (long long q = 0; q < Lsum; ++q)
-    if (!std::isfinite(g0_tau[q])) return fail(HFQMC_EINVAL, "g0_tau[%lld] not finite", q);
+  if (!call.dev_io)
+    for (long long q = 0; q < Lsum; ++q)
+      if (!std::isfinite(g0_tau[q])) return fail(HFQMC_EINVAL, "g0_tau[%lld] not finite", q);
 
   HIPCHK(hipSetDevice(c->device));
   hipStream_t st = c->stream;
   const int nch = r.n_chains, nbin = r.n_bins;
+
+  // ---- k and the LU panel width: given, or from the autotuner
+  int nb_max = call.nb_max;
+  bool tuned = false;
+  double t_tune = 0.0;
+  if (r.mode != MODE_RANK1 && r.delay_k == 0) {
+    TuneChoice tc;
+    rc = autotune(c, n_grids, Ls, g0_tau, call.dev_io, U, beta, seed, opts, Lmax, &tc, &t_tune);
+    if (rc) return rc;
+    r.delay_k = tc.delay_k;
+    if (opts->recompute_every <= 0) r.n_rec = 4 * r.delay_k;
+    nb_max = tc.lu_nb;
+    tuned = true;
+  }
 
   // ---- device memory layout (two passes: size, then assign)
   std::vector<GridDev> gd(n_grids);
@@ -245,6 +372,7 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
 
   // ---- per-grid constants (transcendentals on the host)
   std::vector<GridHost> gh(n_grids);
+  std::vector<long long> goff0(n_grids);
   long long off = 0;
   for (int i = 0; i < n_grids; ++i) {
     const int L = Ls[i];
@@ -260,20 +388,22 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
     g.gm = std::expm1(-2.0 * lam);
     g.ep = std::expm1(lam);
     g.em = std::expm1(-lam);
-    HIPCHK(hipMemcpyAsync(d_gtau + off, g0_tau + off, sizeof(double) * L, hipMemcpyHostToDevice, st));
-    HIPCHK(launch_build_g0(d_gtau + off, L, const_cast<double*>(g.G0), st));
-    HIPCHK(launch_zero(g.acc_g, (long long)nch * nbin * (L + 1), st));
-    HIPCHK(launch_zero(g.acc_d, (long long)nch * nbin, st));
-    HIPCHK(launch_zero_i64(g.acc_n, (long long)nch * nbin, st));
-    HIPCHK(launch_zero_i64(g.cstats, (long long)nch * NSTAT, st));
-    HIPCHK(launch_zero(g.cdrift, nch, st));
-    if (g.replay) {
-      HIPCHK(hipMemcpyAsync((void*)g.replay, opts->replay_log + (size_t)i * nch * opts->replay_cap,
+    goff0[i] = off;
+    off += L;
+  }
+  // device input is copied by a kernel: the caller's buffer may come from another
+  // HIP runtime of the process (PyTorch's), whose allocations this one does not track
+  if (call.dev_io)
+    HIPCHK(launch_copy(g0_tau, d_gtau, Lsum, st));
+  else
+    HIPCHK(hipMemcpyAsync(d_gtau, g0_tau, sizeof(double) * Lsum, hipMemcpyHostToDevice, st));
+  if (opts->replay_log) {
+    for (int i = 0; i < n_grids; ++i) {
+      HIPCHK(hipMemcpyAsync((void*)gd[i].replay, opts->replay_log + (size_t)i * nch * opts->replay_cap,
                             sizeof(long long) * nch * opts->replay_cap, hipMemcpyHostToDevice, st));
-      HIPCHK(hipMemcpyAsync((void*)g.replay_n, opts->replay_count + (size_t)i * nch,
+      HIPCHK(hipMemcpyAsync((void*)gd[i].replay_n, opts->replay_count + (size_t)i * nch,
                             sizeof(long long) * nch, hipMemcpyHostToDevice, st));
     }
-    off += L;
   }
   // ---- dispatch order: longest chains first (cost per sweep ~ L^3), then grid, chain
   std::vector<int> units;
@@ -285,11 +415,10 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
     for (int ch = 0; ch < nch; ++ch) units.push_back((i << 20) | ch);
   HIPCHK(hipMemcpyAsync(d_units, units.data(), sizeof(int) * units.size(), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(d_grids, gd.data(), sizeof(GridDev) * n_grids, hipMemcpyHostToDevice, st));
-  HIPCHK(launch_zero_i32(d_queue, 64, st));
 
   // ---- launch shape
   int lu_nb = 0, scratch = 0;
-  const int lds = lds_bytes(Lmax, r.mode, r.delay_k, r.window_b, &lu_nb, &scratch);
+  const int lds = lds_bytes(Lmax, r.mode, nb_max, &lu_nb, &scratch);
   if (lds + 1024 > c->lds_max)
     return fail(HFQMC_EUNSUPPORTED, "L=%d needs %d bytes of LDS, device allows %d", Lmax, lds, c->lds_max);
   // workgroups per CU: limited by LDS (160 KiB per CU) and by 2048 threads per CU
@@ -322,20 +451,99 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
   p.work_stride = wstride;
   p.Lmax = Lmax;
   p.lds_scratch_bytes = scratch;
+  p.heat_bath = (opts->flags & HFQMC_FLAG_HEAT_BATH) ? 1 : 0;
 
-  HIPCHK(hipEventRecord(c->ev0, st));
-  {
-    hipError_t e = launch_sweeps(p, n_wg, lds, st);
-    if (e != hipSuccess)
-      return fail(HFQMC_EDEVICE, "sweep kernel launch (%d workgroups, %d B LDS, device LDS %d B): %s",
-                  n_wg, lds, c->lds_max, hipGetErrorString(e));
+  // ---- the device launch sequence: bath matrices, zeroed accumulators and
+  // counters (fill kernels), the persistent sweep kernel, the chain reduction
+  HIPCHK(prepare_sweeps(lds));
+  auto enqueue = [&](hipStream_t s) -> hipError_t {
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < n_grids && e == hipSuccess; ++i) {
+      const int L = Ls[i];
+      const GridDev& g = gd[i];
+      if ((e = launch_build_g0(d_gtau + goff0[i], L, const_cast<double*>(g.G0), s)) != hipSuccess) break;
+      if ((e = launch_zero(g.acc_g, (long long)nch * nbin * (L + 1), s)) != hipSuccess) break;
+      if ((e = launch_zero(g.acc_d, (long long)nch * nbin, s)) != hipSuccess) break;
+      if ((e = launch_zero_i64(g.acc_n, (long long)nch * nbin, s)) != hipSuccess) break;
+      if ((e = launch_zero_i64(g.cstats, (long long)nch * NSTAT, s)) != hipSuccess) break;
+      e = launch_zero(g.cdrift, nch, s);
+    }
+    if (e == hipSuccess) e = launch_zero_i32(d_queue, 64, s);
+    if (e == hipSuccess) e = launch_sweeps(p, n_wg, lds, s);
+    if (e == hipSuccess) e = launch_reduce(d_grids, n_grids, nbin, s);
+    return e;
+  };
+  const bool use_graph = !(opts->flags & HFQMC_FLAG_EAGER);
+  if (use_graph) {
+    // key: everything the captured kernels' arguments depend on
+    std::vector<unsigned long long> key;
+    key.push_back((unsigned long long)(uintptr_t)c->arena.p);
+    key.push_back((unsigned long long)(uintptr_t)c->work.p);
+    key.push_back((unsigned long long)n_wg);
+    key.push_back((unsigned long long)lds);
+    for (int i = 0; i < n_grids; ++i) key.push_back((unsigned long long)Ls[i]);
+    {
+      unsigned long long w[(sizeof(SweepParams) + 7) / 8] = {0};
+      std::memcpy(w, &p, sizeof p);
+      key.insert(key.end(), w, w + (sizeof(SweepParams) + 7) / 8);
+    }
+    hipGraphExec_t exec = nullptr;
+    for (size_t q = 0; q < c->graphs.size(); ++q) {
+      if (c->graphs[q].key == key) {
+        exec = c->graphs[q].exec;
+        std::rotate(c->graphs.begin(), c->graphs.begin() + q, c->graphs.begin() + q + 1);
+        break;
+      }
+    }
+    if (!exec) {
+      hipGraph_t graph = nullptr;
+      HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+      const hipError_t e = enqueue(c->cap_stream);
+      const hipError_t e2 = hipStreamEndCapture(c->cap_stream, &graph);
+      if (e != hipSuccess || e2 != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return fail(HFQMC_EDEVICE, "capturing the launch sequence: %s",
+                    hipGetErrorString(e != hipSuccess ? e : e2));
+      }
+      const hipError_t e3 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      if (e3 != hipSuccess) return fail(HFQMC_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e3));
+      if (c->graphs.size() >= kGraphCache) {
+        (void)hipGraphExecDestroy(c->graphs.back().exec);
+        c->graphs.pop_back();
+      }
+      GraphEntry ge;
+      ge.key = key;
+      ge.exec = exec;
+      c->graphs.insert(c->graphs.begin(), ge);
+    }
+    HIPCHK(hipEventRecord(c->ev0, st));
+    {
+      const hipError_t e = hipGraphLaunch(exec, st);
+      if (e != hipSuccess)
+        return fail(HFQMC_EDEVICE, "graph launch (%d workgroups, %d B LDS): %s", n_wg, lds,
+                    hipGetErrorString(e));
+    }
+    HIPCHK(hipEventRecord(c->ev1, st));
+  } else {
+    HIPCHK(hipEventRecord(c->ev0, st));
+    {
+      const hipError_t e = enqueue(st);
+      if (e != hipSuccess)
+        return fail(HFQMC_EDEVICE, "launch sequence (%d workgroups, %d B LDS, device LDS %d B): %s",
+                    n_wg, lds, c->lds_max, hipGetErrorString(e));
+    }
+    HIPCHK(hipEventRecord(c->ev1, st));
   }
-  HIPCHK(hipEventRecord(c->ev1, st));
-  HIPCHK(launch_reduce(d_grids, n_grids, nbin, st));
 
   // ---- results back
+  auto out_copy = [&](double* dst, const double* src, long long n) -> hipError_t {
+    return call.dev_io ? launch_copy(src, dst, n, st)
+                       : hipMemcpyAsync(dst, src, sizeof(double) * n, hipMemcpyDeviceToHost, st);
+  };
   std::vector<long long> cst((size_t)nch * NSTAT);
   std::vector<double> cdr(nch);
+  std::vector<double> gcheck;
   long long goff = 0;
   double max_drift = 0.0;
   bool numeric_bad = false;
@@ -344,9 +552,13 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
   for (int i = 0; i < n_grids; ++i) {
     const int L = Ls[i];
     const GridDev& g = gd[i];
-    HIPCHK(hipMemcpyAsync(g_tau + goff, g.g_out, sizeof(double) * (L + 1), hipMemcpyDeviceToHost, st));
-    if (g_err) HIPCHK(hipMemcpyAsync(g_err + goff, g.g_err, sizeof(double) * (L + 1), hipMemcpyDeviceToHost, st));
-    if (docc) HIPCHK(hipMemcpyAsync(docc + 2 * i, g.d_out, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
+    HIPCHK(out_copy(g_tau + goff, g.g_out, L + 1));
+    if (g_err) HIPCHK(out_copy(g_err + goff, g.g_err, L + 1));
+    if (docc) HIPCHK(out_copy(docc + 2 * i, g.d_out, 2));
+    if (call.dev_io) {
+      gcheck.resize(L + 1);
+      HIPCHK(hipMemcpyAsync(gcheck.data(), g.g_out, sizeof(double) * (L + 1), hipMemcpyDeviceToHost, st));
+    }
     HIPCHK(hipMemcpyAsync(cst.data(), g.cstats, sizeof(long long) * cst.size(), hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(cdr.data(), g.cdrift, sizeof(double) * nch, hipMemcpyDeviceToHost, st));
     const size_t cb = (size_t)i * nch;
@@ -394,6 +606,10 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
     gs.delay_k = r.delay_k;
     gs.recompute_every = r.n_rec;
     gs.n_workgroups = n_wg;
+    gs.lu_panel = lu_nb;
+    gs.graph = use_graph ? 1 : 0;
+    gs.autotuned = tuned ? 1 : 0;
+    gs.seconds_autotune = t_tune;
     if (stats && n_grids > 1) stats[i] = gs;
     tot.n_proposed += gs.n_proposed;
     tot.n_accepted += gs.n_accepted;
@@ -410,8 +626,9 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
     tot.chain_s_lu_strip += gs.chain_s_lu_strip;
     tot.chain_s_lu_back += gs.chain_s_lu_back;
     max_drift = std::max(max_drift, gdrift);
+    const double* gv = call.dev_io ? gcheck.data() : g_tau + goff;
     for (int k = 0; k <= L; ++k)
-      if (!std::isfinite(g_tau[goff + k])) numeric_bad = true;
+      if (!std::isfinite(gv[k])) numeric_bad = true;
     goff += L + 1;
   }
   float ms = 0.f;
@@ -425,6 +642,10 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
   tot.delay_k = r.delay_k;
   tot.recompute_every = r.n_rec;
   tot.n_workgroups = n_wg;
+  tot.lu_panel = lu_nb;
+  tot.graph = use_graph ? 1 : 0;
+  tot.autotuned = tuned ? 1 : 0;
+  tot.seconds_autotune = t_tune;
   if (stats) {
     if (n_grids == 1) {
       stats[0] = tot;
@@ -450,14 +671,25 @@ extern "C" int hfqmc_solve(hfqmc_ctx* c, const double* g0_tau, int32_t L, double
   if (!(dtau > 0.0) || !(beta > 0.0)) return fail(HFQMC_EINVAL, "dtau=%g beta=%g", dtau, beta);
   if (std::fabs(beta / dtau - L) > 1e-9 * L) return fail(HFQMC_EINVAL, "beta/dtau=%.12g != L=%d", beta / dtau, L);
   const int32_t Ls[1] = {L};
-  return solve_grids_impl(c, 1, Ls, g0_tau, U, beta, seed, opts, g_tau, g_err, docc, stats);
+  return solve_grids_impl(c, 1, Ls, g0_tau, U, beta, seed, opts, g_tau, g_err, docc, stats, Call());
+}
+
+extern "C" int hfqmc_solve_dev(hfqmc_ctx* c, const double* g0_tau, int32_t L, double U, double beta,
+                               double dtau, uint64_t seed, const hfqmc_opts* opts, double* g_tau,
+                               double* g_err, double* docc, hfqmc_stats* stats) {
+  if (!(dtau > 0.0) || !(beta > 0.0)) return fail(HFQMC_EINVAL, "dtau=%g beta=%g", dtau, beta);
+  if (std::fabs(beta / dtau - L) > 1e-9 * L) return fail(HFQMC_EINVAL, "beta/dtau=%.12g != L=%d", beta / dtau, L);
+  const int32_t Ls[1] = {L};
+  Call call;
+  call.dev_io = true;
+  return solve_grids_impl(c, 1, Ls, g0_tau, U, beta, seed, opts, g_tau, g_err, docc, stats, call);
 }
 
 extern "C" int hfqmc_solve_grids(hfqmc_ctx* c, int32_t n_grids, const int32_t* L,
                                  const double* g0_tau, double U, double beta, uint64_t seed,
                                  const hfqmc_opts* opts, double* g_tau, double* g_err,
                                  double* docc, hfqmc_stats* stats) {
-  return solve_grids_impl(c, n_grids, L, g0_tau, U, beta, seed, opts, g_tau, g_err, docc, stats);
+  return solve_grids_impl(c, n_grids, L, g0_tau, U, beta, seed, opts, g_tau, g_err, docc, stats, Call());
 }
 
 extern "C" int bethe_semicircle_bath(double beta, double t, int32_t n_iw, double* bath_iw) {
@@ -503,7 +735,7 @@ extern "C" int multigrid_solve(hfqmc_ctx* c, const double* bath_iw, int32_t n_iw
     off += Ls[i];
   }
   int rc = solve_grids_impl(c, n_grids, Ls.data(), g0.data(), U, beta, seed, opts, gg.data(),
-                            ge.data(), nullptr, per_grid);
+                            ge.data(), nullptr, per_grid, Call());
   if (rc) return rc;
   // (i) interpolation onto the fine grid with the reference model
   std::vector<double> tf(n_fine), gref_f(n_fine);

@@ -70,6 +70,7 @@ struct SweepParams {
   long long work_stride;  // doubles per workgroup
   int Lmax;
   int lds_scratch_bytes;  // bytes of the phase-shared LDS region
+  int heat_bath;          // 1: accept iff u < R/(1+R); 0: Metropolis, u < R
 };
 
 constexpr int kThreads = 512;   // threads per persistent workgroup (8 wave64)
@@ -78,10 +79,15 @@ constexpr int kMaxK = 64;       // largest delayed rank
 
 // Workspace (doubles) needed per workgroup for chains of length up to Lmax.
 long long workspace_doubles(int Lmax, int kmax);
-// Dynamic LDS bytes of the persistent kernel and the LU panel width for Lmax.
-int lds_bytes(int Lmax, int mode, int k, int b, int* lu_nb, int* scratch_bytes);
+// Dynamic LDS bytes of the persistent kernel and the LU panel width for Lmax
+// (the widest that fits the LDS budget, at most nb_max).
+int lds_bytes(int Lmax, int mode, int nb_max, int* lu_nb, int* scratch_bytes);
+// Sets the kernel's dynamic-LDS limit (needed above 64 KiB); call before a
+// launch or a stream capture.
+hipError_t prepare_sweeps(int lds);
 
 hipError_t launch_build_g0(const double* g_tau, int L, double* G0, hipStream_t s);
+hipError_t launch_copy(const double* src, double* dst, long long n, hipStream_t s);
 hipError_t launch_zero(double* p, long long n, hipStream_t s);
 hipError_t launch_zero_i64(long long* p, long long n, hipStream_t s);
 hipError_t launch_zero_i32(int* p, long long n, hipStream_t s);

@@ -133,6 +133,14 @@ __global__ void k_build_g0(const double* __restrict__ g, int L, double* __restri
   }
 }
 
+// Device-to-device copy by a kernel: works on any device address of the
+// process (also memory another HIP runtime in the process allocated).
+__global__ void k_copy(const double* __restrict__ src, double* __restrict__ dst, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
 template <typename T>
 __global__ void k_zero(T* p, long long n) {
   for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < n;
@@ -141,6 +149,8 @@ __global__ void k_zero(T* p, long long n) {
 }
 
 // ----------------------------------------------------- chain context ----
+
+constexpr int kStatBytes = 256;   // LDS statistics block: NSTAT counters + drift
 
 struct Chain {
   const double* G0;
@@ -158,18 +168,22 @@ struct Chain {
   int8_t* s;       // field, LDS
   double* u;       // uniforms, LDS
   char* scratch;   // phase-shared LDS
+  int scratch_bytes;
   double* red;     // reduction scratch, LDS
+  long long* st;   // per-chain statistics [NSTAT] (ST_*), LDS, written by thread 0 only
+  double* drift;   // largest recompute drift so far, LDS, thread 0 only
 };
 
+// Control state every thread keeps (uniform); the statistics live in LDS.
 struct Counters {
-  long long n_prop, n_acc, n_rec, n_bad, n_flips, rep_i;
-  double drift;
-  int acc_since;
-  int singular;
-  long long t_sweep, t_flush, t_rec, t_meas;        // constant-rate wall-clock ticks
-  long long t_lu_build, t_lu_panel, t_lu_strip, t_lu_back;
-  long long n_flush;
+  long long rep_i;   // next entry of the replay list
+  int acc_since;     // accepted flips since the last recompute
 };
+
+// Adds v to statistic `which` (thread 0 keeps the LDS copy).
+__device__ __forceinline__ void stat_add(long long* st, int which, long long v) {
+  if (threadIdx.x == 0) st[which] += v;
+}
 
 // ------------------------------------------------ Dyson recompute (LU) ----
 //
@@ -411,139 +425,172 @@ __device__ __forceinline__ void lu_strip_backward_mfma(double* __restrict__ A, i
   }
 }
 
-// Element j (uniform) of a register row, by a 5-level select tree.
-template <int NB>
-__device__ __forceinline__ double reg_pick(const double (&r)[NB], int j) {
-  double t[NB];
-#pragma unroll
-  for (int c = 0; c < NB; ++c) t[c] = r[c];
-#pragma unroll
-  for (int w = 1; w < NB; w <<= 1) {
-#pragma unroll
-    for (int c = 0; c + w < NB; c += 2 * w) t[c] = (j & w) ? t[c + w] : t[c];
-  }
-  return t[0];
+// Max of a 64-bit key over the 16 lanes of each row of the wave (xor
+// butterfly on DPP: quad permutations, then half-row and row mirrors).
+template <int CTRL>
+__device__ __forceinline__ unsigned long long dpp_u64(unsigned long long v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)v, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(v >> 32), CTRL, 0xF, 0xF, false);
+  return ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo;
 }
 
-// Panel factorization (partial pivoting) with the panel rows in registers:
-// thread t owns the physical rows t + q kThreads and tracks the position each
-// one currently occupies (row interchanges only swap positions).  Per column
-// one barrier: every wave's best candidate row is staged in LDS together with
-// its |pivot|, so after the barrier all threads know the winner and read the
-// pivot row directly (candidate slots are double-buffered across columns).
-// The factored rows go to P in position order (stride ps), U11 also to A;
-// piv[j] = position exchanged with j (relative to kb).
+__device__ __forceinline__ unsigned long long wave_max_key(unsigned long long k) {
+  unsigned long long o;
+  o = dpp_u64<0xB1>(k);   // quad_perm [1,0,3,2]
+  k = o > k ? o : k;
+  o = dpp_u64<0x4E>(k);   // quad_perm [2,3,0,1]
+  k = o > k ? o : k;
+  o = dpp_u64<0x141>(k);  // row_half_mirror
+  k = o > k ? o : k;
+  o = dpp_u64<0x140>(k);  // row_mirror
+  k = o > k ? o : k;
+  unsigned long long m = 0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)k, 16 * r);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(k >> 32), 16 * r);
+    const unsigned long long v = ((unsigned long long)hi << 32) | lo;
+    m = v > m ? v : m;
+  }
+  return m;
+}
+
+// Panel factorization (partial pivoting) with the panel rows in registers.
+// Thread t owns the physical rows t + q kThreads and tracks the position each
+// one currently occupies (row interchanges only swap positions).  A row's
+// registers hold a window that shifts left by one slot per eliminated column
+// (slots 0..NB-1-j are its columns j..NB-1 before step j; the slots beyond
+// hold values nothing reads), so the pivot column is always slot 0.  The
+// multiplier of each step goes to LDS, indexed by physical row, in the P
+// buffer that receives the factored rows in position order at the end.
+// Pivot search: key = |a| with its 10 low mantissa bits replaced by
+// 1023 - physical row (largest magnitude; ties and near-ties resolved by the
+// row), reduced over the wave on DPP; each wave stages its best row with its
+// position and reciprocal in LDS (double-buffered), so one barrier per
+// column suffices.  U11 also goes to A; piv[j] = position exchanged with j.
 template <int NB>
 __device__ __forceinline__ void panel_factor_regs(double* __restrict__ A, int lda, int kb, int rows,
                                                   double* __restrict__ P, int ps,
                                                   double* __restrict__ cand,
-                                                  double* __restrict__ redv, int* __restrict__ redi,
+                                                  unsigned long long* __restrict__ keys,
                                                   int* __restrict__ piv, int* sing) {
   constexpr int RPT = 512 / kThreads * (NB == 32 ? 1 : 2);
   constexpr int NW = kThreads / 64;
-  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+  constexpr int CS = NB + 2;   // staged candidate: window, reciprocal, position
+  const int t = threadIdx.x, wv = t >> 6;
   double pr[RPT][NB];
-  int pos[RPT];
+  int pos[RPT], fz[RPT];
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
     const int r = t + q * kThreads;
     pos[q] = r;
+    fz[q] = NB;
 #pragma unroll
     for (int c = 0; c < NB; ++c) pr[q][c] = (r < rows) ? A[(kb + r) * lda + kb + c] : 0.0;
   }
+  // the old contents of P (previous panel) must have been consumed
+  __syncthreads();
 #pragma unroll 1
   for (int j = 0; j < NB; ++j) {
-    double best = -1.0;
-    int bpos = 1 << 30, bq = -1;
+    unsigned long long best = 0;
+    int bq = 0;
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
-      const double v = fabs(reg_pick<NB>(pr[q], j));
-      if (pos[q] >= j && pos[q] < rows && (v > best || (v == best && pos[q] < bpos))) {
-        best = v;
-        bpos = pos[q];
+      const bool act = pos[q] >= j && pos[q] < rows;
+      const unsigned long long bits =
+          (unsigned long long)__double_as_longlong(fabs(pr[q][0])) & ~0x3FFull;
+      const unsigned long long key =
+          act ? (bits | (unsigned long long)(1023 - (t + q * kThreads))) : 0ull;
+      if (key > best) {
+        best = key;
         bq = q;
       }
     }
-    double wb = best;
-    int wp = bpos;
+    const double head = (RPT == 2 && bq) ? pr[RPT - 1][0] : pr[0][0];
+    const double hinv = 1.0 / head;   // used only if this row wins
+    const unsigned long long wbest = wave_max_key(best);
+    if (best == wbest && wbest != 0ull) {
+      double* cw = cand + wv * CS;
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      const double ob = __shfl_xor(wb, o, 64);
-      const int op = __shfl_xor(wp, o, 64);
-      if (ob > wb || (ob == wb && op < wp)) {
-        wb = ob;
-        wp = op;
-      }
-    }
-    if (bq >= 0 && bpos == wp) {
-#pragma unroll
-      for (int q = 0; q < RPT; ++q)
-        if (q == bq) {
-#pragma unroll
-          for (int c = 0; c < NB; ++c) cand[wv * NB + c] = pr[q][c];
-        }
-    }
-    if (lane == 0) {
-      redv[wv] = wb;
-      redi[wv] = wp;
+      for (int c = 0; c < NB; ++c) cw[c] = (RPT == 2 && bq) ? pr[RPT - 1][c] : pr[0][c];
+      cw[NB] = hinv;
+      cw[NB + 1] = (double)((RPT == 2 && bq) ? pos[RPT - 1] : pos[0]);
+      keys[wv] = wbest;
+    } else if (wbest == 0ull && (t & 63) == 0) {
+      keys[wv] = 0ull;
     }
     __syncthreads();
-    double gb = redv[0];
-    int gp = redi[0], gw = 0;
+    unsigned long long gk = keys[0];
 #pragma unroll
     for (int w = 1; w < NW; ++w) {
-      const double ob = redv[w];
-      const int op = redi[w];
-      if (ob > gb || (ob == gb && op < gp)) {
-        gb = ob;
-        gp = op;
-        gw = w;
+      const unsigned long long o = keys[w];
+      gk = o > gk ? o : gk;
+    }
+    const int gw = ((1023 - (int)(gk & 0x3FFull)) & (kThreads - 1)) >> 6;
+    double prow[CS];
+    {
+      const double2* c2 = reinterpret_cast<const double2*>(cand + gw * CS);
+#pragma unroll
+      for (int c = 0; c < CS / 2; ++c) {
+        const double2 v = c2[c];
+        prow[2 * c] = v.x;
+        prow[2 * c + 1] = v.y;
       }
     }
-    const bool found = gp < rows;
-    if (!found) gp = j;   // no finite candidate: keep the position, flagged below
-    if (t == 0) piv[j] = gp;
-    const double* prow = cand + gw * NB;
-    const double pv = found ? prow[j] : 0.0;
-    if (t == 0 && !(fabs(pv) > 0.0 && fabs(pv) < INFINITY)) *sing = 1;
-    const double rinv = 1.0 / pv;
+    const double pv = prow[0];
+    const double rinv = prow[NB];
+    const int gp = (int)prow[NB + 1];
+    if (t == 0) {
+      piv[j] = gp;
+      if (!(fabs(pv) > 0.0 && fabs(pv) < INFINITY)) *sing = 1;
+    }
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
       if (pos[q] == gp)
         pos[q] = j;
       else if (pos[q] == j)
         pos[q] = gp;
-      if (found && pos[q] > j && pos[q] < rows) {
-        const double l = reg_pick<NB>(pr[q], j) * rinv;
+      if (pos[q] == j) {
+        fz[q] = j;
+      } else if (pos[q] > j && pos[q] < rows) {
+        const double l = pr[q][0] * rinv;
+        P[(t + q * kThreads) * ps + j] = l;
 #pragma unroll
-        for (int c = 0; c < NB; ++c) {
-          const double e = fma(-l, prow[c], pr[q][c]);
-          pr[q][c] = (c == j) ? l : ((c > j) ? e : pr[q][c]);
-        }
+        for (int c = 0; c + 1 < NB; ++c) pr[q][c] = fma(-l, prow[c + 1], pr[q][c + 1]);
       }
     }
-    cand += (j & 1) ? -NW * NB : NW * NB;
-    redv += (j & 1) ? -NW : NW;
-    redi += (j & 1) ? -NW : NW;
+    cand += (j & 1) ? -NW * CS : NW * CS;
+    keys += (j & 1) ? -NW : NW;
+  }
+  __syncthreads();
+  // multipliers (by physical row) -> registers, then every row to its position
+  double lm[RPT][NB];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q) {
+    const int r = t + q * kThreads;
+#pragma unroll
+    for (int c = 0; c < NB; ++c) lm[q][c] = (r < rows) ? P[r * ps + c] : 0.0;
   }
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
     const int r = pos[q];
     if (t + q * kThreads < rows) {
+      const int f = fz[q];
 #pragma unroll
-      for (int c = 0; c < NB; ++c) P[r * ps + c] = pr[q][c];
-      if (r < NB) {
-#pragma unroll
-        for (int c = 0; c < NB; ++c)
-          if (c >= r) A[(kb + r) * lda + kb + c] = pr[q][c];
+      for (int c = 0; c < NB; ++c) {
+        if (c < f) P[r * ps + c] = lm[q][c];
+        if (c < NB - f) {
+          P[r * ps + f + c] = pr[q][c];
+          A[(kb + r) * lda + kb + f + c] = pr[q][c];
+        }
       }
     }
   }
 }
 
 __device__ __forceinline__ double dyson_recompute(const Chain& ch, int sigma,
-                                                  double* __restrict__ Gs, int NB, Counters& k) {
+                                                  double* __restrict__ Gs, int NB) {
   const int n = ch.L;
   const int np = (n + NB - 1) / NB * NB;
   const int lda = 2 * np;
@@ -585,23 +632,23 @@ __device__ __forceinline__ double dyson_recompute(const Chain& ch, int sigma,
   int* redi = reinterpret_cast<int*>(redv + kThreads / 64);
   int* piv = redi + kThreads / 64;                       // [NB]
   double* cand = reinterpret_cast<double*>(piv + 32);    // [2][waves][NB] staged candidate rows
-  double* pred_v = cand + 2 * (kThreads / 64) * NB;      // [2][waves] candidate |pivot|
-  int* pred_i = reinterpret_cast<int*>(pred_v + 2 * (kThreads / 64));  // [2][waves] positions
+  unsigned long long* pkeys =                            // [2][waves] candidate pivot keys
+      reinterpret_cast<unsigned long long*>(cand + 2 * (kThreads / 64) * (NB + 2));
   __shared__ int s_sing;
   if (t == 0) s_sing = 0;
   __syncthreads();
   {
     const long long t1 = wall_clock64();
-    k.t_lu_build += t1 - tc;
+    stat_add(ch.st, ST_T_LU_BUILD, t1 - tc);
     tc = t1;
   }
 
   for (int kb = 0; kb < np; kb += NB) {
     const int rows = np - kb;
     if (NB == 32) {
-      panel_factor_regs<32>(A, lda, kb, rows, P, ps, cand, pred_v, pred_i, piv, &s_sing);
+      panel_factor_regs<32>(A, lda, kb, rows, P, ps, cand, pkeys, piv, &s_sing);
     } else if (NB == 16) {
-      panel_factor_regs<16>(A, lda, kb, rows, P, ps, cand, pred_v, pred_i, piv, &s_sing);
+      panel_factor_regs<16>(A, lda, kb, rows, P, ps, cand, pkeys, piv, &s_sing);
     } else {
       // ---- panel rows kb.., columns kb..kb+NB-1 into LDS, factorized by all waves
       for (int idx = t; idx < rows * NB; idx += kThreads) {
@@ -673,7 +720,7 @@ __device__ __forceinline__ double dyson_recompute(const Chain& ch, int sigma,
     }
     {
       const long long t1 = wall_clock64();
-      k.t_lu_panel += t1 - tc;
+      stat_add(ch.st, ST_T_LU_PANEL, t1 - tc);
       tc = t1;
     }
     // ---- strip: interchanges, U12, trailing update (RHS included)
@@ -717,7 +764,7 @@ __device__ __forceinline__ double dyson_recompute(const Chain& ch, int sigma,
     __syncthreads();
     {
       const long long t1 = wall_clock64();
-      k.t_lu_strip += t1 - tc;
+      stat_add(ch.st, ST_T_LU_STRIP, t1 - tc);
       tc = t1;
     }
   }
@@ -769,9 +816,9 @@ __device__ __forceinline__ double dyson_recompute(const Chain& ch, int sigma,
     Gs[idx] = x;
   }
   dmax = block_max(dmax, ch.red);
-  if (s_sing) k.singular = 1;
+  if (s_sing && t == 0) ch.st[ST_SINGULAR] = 1;
   __syncthreads();
-  k.t_lu_back += wall_clock64() - tc;
+  stat_add(ch.st, ST_T_LU_BACK, wall_clock64() - tc);
   return dmax;
 }
 
@@ -816,9 +863,10 @@ __device__ __forceinline__ void measure(const Chain& ch, int bin) {
 // ---------------------------------------------------------- proposals ----
 
 
-// Metropolis decision for flipping s_l, evaluated identically by every thread
-// of the workgroup (uniform branch).  In replay mode the decision is read from
-// the given flip list instead of u < R.
+// Acceptance decision for flipping s_l (Metropolis u < R, or heat bath
+// u < R/(1+R)), evaluated identically by every thread of the workgroup
+// (uniform branch).  In replay mode the decision is read from the given flip
+// list instead.
 struct Flip {
   double g_up, g_dn, r_up, r_dn;
   bool accept;
@@ -826,21 +874,24 @@ struct Flip {
 
 __device__ __forceinline__ Flip propose(double gul, double gdl, int sl, double gp, double gm,
                                        double u, const long long* rlog, long long rlen,
-                                       long long code, Counters& k) {
+                                       long long code, Counters& k, long long* st, bool hb) {
   Flip f;
   f.g_up = sl > 0 ? gm : gp;
   f.g_dn = sl > 0 ? gp : gm;
   f.r_up = ratio_factor(f.g_up, gul);
   f.r_dn = ratio_factor(f.g_dn, gdl);
   const double R = mul_nc(f.r_up, f.r_dn);
-  ++k.n_prop;
   const bool bad = !(R > 0.0);
-  k.n_bad += bad ? 1 : 0;
+  if (threadIdx.x == 0) {
+    st[ST_PROPOSED] += 1;
+    st[ST_BAD] += bad ? 1 : 0;
+  }
   if (rlog) {
     f.accept = k.rep_i < rlen && rlog[k.rep_i] == code;
     k.rep_i += f.accept ? 1 : 0;
   } else {
-    f.accept = !bad && u < R;
+    // Metropolis min(1, R), or heat bath R / (1 + R)
+    f.accept = !bad && (hb ? u < R / (1.0 + R) : u < R);
   }
   return f;
 }
@@ -851,11 +902,16 @@ struct ChainIO {
   long long rlen;
   long long flip_cap;
   double gp, gm;
+  bool hb;   // heat-bath acceptance
 };
 
-__device__ __forceinline__ void log_flip(const ChainIO& io, Counters& k, long long code) {
-  if (io.flog && threadIdx.x == 0 && k.n_flips < io.flip_cap) io.flog[k.n_flips] = code;
-  ++k.n_flips;
+__device__ __forceinline__ void log_flip(const ChainIO& io, long long* st, long long code) {
+  if (threadIdx.x == 0) {
+    const long long n = st[ST_FLIPS];
+    if (io.flog && n < io.flip_cap) io.flog[n] = code;
+    st[ST_FLIPS] = n + 1;
+    st[ST_ACCEPTED] += 1;
+  }
 }
 
 // Dyson recompute of both spins (the kernel's only call site of the LU, so it
@@ -866,13 +922,13 @@ __device__ __forceinline__ void recompute_both(const SweepParams& p, const Chain
   double d = 0.0;
 #pragma unroll 1
   for (int sp = 0; sp < 2; ++sp)
-    d = fmax(d, dyson_recompute(ch, sp ? -1 : +1, sp ? ch.Gd : ch.Gu, p.lu_nb, k));
-  if (counted) {
-    k.drift = fmax(k.drift, d);
-    ++k.n_rec;
+    d = fmax(d, dyson_recompute(ch, sp ? -1 : +1, sp ? ch.Gd : ch.Gu, p.lu_nb));
+  if (counted && threadIdx.x == 0) {
+    *ch.drift = fmax(*ch.drift, d);
+    ch.st[ST_RECOMPUTES] += 1;
   }
   k.acc_since = 0;
-  k.t_rec += wall_clock64() - t0;
+  stat_add(ch.st, ST_T_REC, wall_clock64() - t0);
 }
 
 // ------------------------------------------------- plain rank-1 sweep ----
@@ -892,10 +948,9 @@ __device__ __forceinline__ int sweep_rank1(const SweepParams& p, const Chain& ch
     const long long dl = (long long)l * L + l;
     const int sl = ch.s[l];
     const Flip f = propose(ch.Gu[dl], ch.Gd[dl], sl, io.gp, io.gm, ch.u[l], io.rlog, io.rlen,
-                           sw * L + l, k);
+                           sw * L + l, k, ch.st, io.hb);
     if (!f.accept) continue;
-    ++k.n_acc;
-    log_flip(io, k, sw * L + l);
+    log_flip(io, ch.st, sw * L + l);
     // update vectors x = G(:,l) - e_l and y = (gamma/R_sigma) G(l,:)
     const double cu = f.g_up / f.r_up, cd = f.g_dn / f.r_dn;
     for (int i = threadIdx.x; i < L; i += kThreads) {
@@ -976,93 +1031,121 @@ constexpr int kWin = 64;        // slices per window (diagonal block edge)
 constexpr int kWP = kWin + 1;   // LDS row stride of the window blocks
 constexpr int kKP = kMaxK + 1;  // LDS row stride of the m x m coefficient blocks
 constexpr int kSmall = 1536;    // bytes for flip positions and coefficients
-constexpr int kTile = 64;       // flush output tile edge
-constexpr int kTP = kTile + 4;  // FP64 tile row stride
-constexpr int kXS = kMaxK + 1;  // FP32 X tile row stride
-constexpr int kYS = kTile + 1;  // FP32 Y tile row stride
-
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 // G += X Y for one spin.  X: [L][kMaxK] row-major, Y: [kMaxK][L] row-major,
-// m used columns.  Each wave owns 16-row strips of G: it keeps the strip's X
-// operand in registers and walks the 16 x 16 output blocks of the strip, the
-// next block's G prefetched while the current one runs on the matrix cores.
+// m used columns.  Y is staged once per column panel in LDS, transposed
+// ([column][k], row stride kYK, as the MFMA input type), so every element of Y
+// leaves memory once per flush; X rows stay in registers per 16-row strip.
+// The output is walked in work items of one 16-row strip by kCW columns,
+// split into contiguous ranges per wave; the next item's G is loaded while the
+// current one runs on the matrix cores.
 // MIXED: FP32 operands and FP32 accumulation (v_mfma_f32_16x16x4f32, output
 // row 4q + r), added into the FP64 G; otherwise FP64 (v_mfma_f64_16x16x4f64,
 // output row 4r + q).
+constexpr int kCW = 64;          // columns per work item (4 output tiles)
+constexpr int kCT = kCW / 16;
+constexpr int kYK = kMaxK + 4;   // LDS stride of a staged Y column
+
 template <bool MIXED>
 __device__ __forceinline__ void flush_gemm(double* __restrict__ G, const double* __restrict__ X,
-                                           const double* __restrict__ Y, int L, int m) {
+                                           const double* __restrict__ Y, int L, int m,
+                                           char* __restrict__ ybuf, int ybytes) {
   typedef typename std::conditional<MIXED, float, double>::type T;
   typedef T Tx4 __attribute__((ext_vector_type(4)));
   constexpr int KS = kMaxK / 4;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   const int li = lane & 15, lq = lane >> 4;
   const int ks = (m + 3) >> 2;
-  const int nb = (L + 15) >> 4;
-  for (int rs = wv; rs < nb; rs += kThreads / 64) {
-    const int row0 = rs * 16;
-    const int arow = min(row0 + li, L - 1);
-    const bool arow_ok = row0 + li < L;
-    // operands are loaded unconditionally from clamped, in-bounds addresses and
-    // zeroed where they fall outside (k >= m, row/col >= L), so no load waits
-    // behind a branch
-    T a[KS];
+  const int rows = 4 * ks;
+  const int nstrip = (L + 15) >> 4;
+  // panel width: a multiple of kCW whose staged columns fit the buffer
+  int pw = ybytes / (kYK * (int)sizeof(T)) / kCW * kCW;
+  if (pw > ((L + kCW - 1) / kCW) * kCW) pw = ((L + kCW - 1) / kCW) * kCW;
+  T* __restrict__ Yl = reinterpret_cast<T*>(ybuf);
+  int orow_off[4];
 #pragma unroll
-    for (int q = 0; q < KS; ++q) {
-      const int kk = 4 * q + lq;
-      const double v = X[arow * kMaxK + kk];
-      a[q] = (arow_ok && kk < m) ? (T)v : (T)0;
-    }
-    int orow[4];
-    bool rok[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int rr = row0 + (MIXED ? 4 * lq + r : 4 * r + lq);
-      rok[r] = rr < L;
-      orow[r] = min(rr, L - 1);
-    }
-    T ynxt[KS];
-    double gnxt[4];
-    {
-      const int col = min(li, L - 1);
-#pragma unroll
-      for (int q = 0; q < KS; ++q) ynxt[q] = (T)Y[(4 * q + lq) * L + col];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) gnxt[r] = G[orow[r] * L + col];
-    }
+  for (int r = 0; r < 4; ++r) orow_off[r] = MIXED ? 4 * lq + r : 4 * r + lq;
+  // (32-bit byte offsets from the uniform base keep each address in one register)
+  const char* __restrict__ Gc = reinterpret_cast<const char*>(G);
 #pragma unroll 1
-    for (int cb = 0; cb < nb; ++cb) {
-      const int col = cb * 16 + li;
-      const bool cok = col < L;
-      T ycur[KS];
-      double gcur[4];
+  for (int c0 = 0; c0 < L; c0 += pw) {
+    const int w = min(pw, L - c0);
+    __syncthreads();
+    for (int idx = t; idx < rows * pw; idx += kThreads) {
+      const int kk = idx / pw, c = idx - kk * pw;
+      Yl[c * kYK + kk] = (kk < m && c < w) ? (T)Y[kk * L + c0 + c] : (T)0;
+    }
+    __syncthreads();
+    const int nchunk = (w + kCW - 1) / kCW;
+    const int items = nstrip * nchunk;
+    const int lo = (int)((long long)items * wv / (kThreads / 64));
+    const int hi = (int)((long long)items * (wv + 1) / (kThreads / 64));
+    if (lo >= hi) continue;
+    // G of item `it` for this lane: 4 rows x kCT tiles (clamped, in bounds)
+    auto load_g = [&](int it, double (&g)[kCT][4]) {
+      const int st = it / nchunk, chk = it - st * nchunk;
 #pragma unroll
-      for (int q = 0; q < KS; ++q) ycur[q] = ynxt[q];
+      for (int ct = 0; ct < kCT; ++ct) {
+        const int col = min(c0 + chk * kCW + 16 * ct + li, L - 1);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) gcur[r] = gnxt[r];
-      {
-        const int ncol = min(col + 16, L - 1);
-#pragma unroll
-        for (int q = 0; q < KS; ++q) ynxt[q] = (T)Y[(4 * q + lq) * L + ncol];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) gnxt[r] = G[orow[r] * L + ncol];
+        for (int r = 0; r < 4; ++r) {
+          const unsigned o = (unsigned)(min(16 * st + orow_off[r], L - 1) * L + col) << 3;
+          g[ct][r] = *reinterpret_cast<const double*>(Gc + o);
+        }
       }
-      Tx4 acc = {(T)0, (T)0, (T)0, (T)0};
+    };
+    double gnxt[kCT][4];
+    load_g(lo, gnxt);
+    T a[KS];
+    int cur_strip = -1;
+#pragma unroll 1
+    for (int it = lo; it < hi; ++it) {
+      const int st = it / nchunk, chk = it - st * nchunk;
+      double gcur[kCT][4];
+#pragma unroll
+      for (int ct = 0; ct < kCT; ++ct)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) gcur[ct][r] = gnxt[ct][r];
+      if (it + 1 < hi) load_g(it + 1, gnxt);
+      if (st != cur_strip) {
+        cur_strip = st;
+        const int arow = min(16 * st + li, L - 1);
+        const bool arow_ok = 16 * st + li < L;
+#pragma unroll
+        for (int q = 0; q < KS; ++q) {
+          const int kk = 4 * q + lq;
+          const double v = X[arow * kMaxK + kk];
+          a[q] = (arow_ok && kk < m) ? (T)v : (T)0;
+        }
+      }
+      Tx4 acc[kCT];
+#pragma unroll
+      for (int ct = 0; ct < kCT; ++ct) acc[ct] = Tx4{(T)0, (T)0, (T)0, (T)0};
+      const T* yb = Yl + (chk * kCW + li) * kYK + lq;
 #pragma unroll
       for (int q = 0; q < KS; ++q) {
-        const int kk = 4 * q + lq;
-        const T bv = (cok && kk < m) ? ycur[q] : (T)0;
         if (q < ks) {
-          if constexpr (MIXED)
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q], bv, acc, 0, 0, 0);
-          else
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], bv, acc, 0, 0, 0);
+#pragma unroll
+          for (int ct = 0; ct < kCT; ++ct) {
+            const T bv = yb[16 * ct * kYK + 4 * q];
+            if constexpr (MIXED)
+              acc[ct] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q], bv, acc[ct], 0, 0, 0);
+            else
+              acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], bv, acc[ct], 0, 0, 0);
+          }
         }
       }
 #pragma unroll
-      for (int r = 0; r < 4; ++r)
-        if (rok[r] && cok) G[orow[r] * L + col] = gcur[r] + (double)acc[r];
+      for (int ct = 0; ct < kCT; ++ct) {
+        const int col = c0 + chk * kCW + 16 * ct + li;
+        const bool cok = (chk * kCW + 16 * ct + li < w);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * st + orow_off[r];
+          if (cok && row < L) G[row * L + col] = gcur[ct][r] + (double)acc[ct][r];
+        }
+      }
     }
   }
 }
@@ -1217,7 +1300,7 @@ __device__ __forceinline__ void flush_window(const Chain& ch, int l0, int m) {
 #pragma unroll 1
   for (int sp = 0; sp < 2; ++sp)
     flush_gemm<MIXED>(sp ? ch.Gd : ch.Gu, X + (long long)sp * L * kMaxK,
-                      Y + (long long)sp * kMaxK * L, L, m);
+                      Y + (long long)sp * kMaxK * L, L, m, un, ch.scratch_bytes - kSmall);
   __syncthreads();
 }
 
@@ -1256,10 +1339,9 @@ __device__ __forceinline__ int sweep_window(const SweepParams& p, const Chain& c
       const int l = l0 + pos;
       const int sl = ch.s[l];
       const Flip f = propose(Wu[pos * kWP + pos], Wd[pos * kWP + pos], sl, io.gp, io.gm, ch.u[l],
-                             io.rlog, io.rlen, sw * L + l, k);
+                             io.rlog, io.rlen, sw * L + l, k, ch.st, io.hb);
       if (f.accept) {
-        ++k.n_acc;
-        log_flip(io, k, sw * L + l);
+        log_flip(io, ch.st, sw * L + l);
         const double cu = f.g_up / f.r_up, cd = f.g_dn / f.r_dn;
         // in-window parts of x = G(:,l) - e_l and y = c G(l,:), kept for the flush
         if (t < b) {
@@ -1306,8 +1388,10 @@ __device__ __forceinline__ int sweep_window(const SweepParams& p, const Chain& c
     if (m > 0) {
       const long long t0 = wall_clock64();
       flush_window<MIXED>(ch, l0, m);
-      k.t_flush += wall_clock64() - t0;
-      ++k.n_flush;
+      if (threadIdx.x == 0) {
+        ch.st[ST_T_FLUSH] += wall_clock64() - t0;
+        ch.st[ST_FLUSHES] += 1;
+      }
     }
     l0 += pos;
     if (k.acc_since == p.n_rec) return l0;
@@ -1339,7 +1423,10 @@ __device__ __forceinline__ void run_chain(const SweepParams& p, const GridDev* g
   const int s_bytes = (p.Lmax + 15) & ~15;
   ch.u = reinterpret_cast<double*>(lds + s_bytes);
   ch.red = ch.u + p.Lmax;
-  ch.scratch = reinterpret_cast<char*>(ch.red + 64);
+  ch.st = reinterpret_cast<long long*>(ch.red + 64);
+  ch.drift = reinterpret_cast<double*>(ch.st + NSTAT);
+  ch.scratch = reinterpret_cast<char*>(ch.red + 64) + kStatBytes;
+  ch.scratch_bytes = p.lds_scratch_bytes;
 
   // this chain's accumulators
   const int nb = p.n_bins;
@@ -1352,7 +1439,10 @@ __device__ __forceinline__ void run_chain(const SweepParams& p, const GridDev* g
     ch.s[l] = uniform53(ch.key0, (uint64_t)gd->grid_id, (uint64_t)l, 0ull, 1ull) < 0.5 ? 1 : -1;
   __syncthreads();
 
-  Counters k = {0, 0, 0, 0, 0, 0, 0.0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  if (threadIdx.x < NSTAT) ch.st[threadIdx.x] = 0;
+  if (threadIdx.x == 0) *ch.drift = 0.0;
+  __syncthreads();
+  Counters k = {0, 0};
 
   ChainIO io;
   io.flog = gd->flip_log ? gd->flip_log + (long long)chain * p.flip_cap : nullptr;
@@ -1361,6 +1451,7 @@ __device__ __forceinline__ void run_chain(const SweepParams& p, const GridDev* g
   io.flip_cap = p.flip_cap;
   io.gp = gd->gp;
   io.gm = gd->gm;
+  io.hb = p.heat_bath != 0;
 
   // One loop drives the whole chain so that every phase has a single call
   // site: recompute (initial, then whenever n_rec flips have been accepted,
@@ -1382,7 +1473,7 @@ __device__ __forceinline__ void run_chain(const SweepParams& p, const GridDev* g
         const long long msw = sw - p.warmup;
         const int bin = (int)((msw * nb) / p.sweeps);
         measure(ch, bin);
-        k.t_meas += wall_clock64() - t1;
+        stat_add(ch.st, ST_T_MEAS, wall_clock64() - t1);
       }
       __syncthreads();
       ++sw;
@@ -1395,7 +1486,7 @@ __device__ __forceinline__ void run_chain(const SweepParams& p, const GridDev* g
       __syncthreads();
     }
     const long long t0 = wall_clock64();
-    const long long f0 = k.t_flush;
+    const long long f0 = threadIdx.x == 0 ? ch.st[ST_T_FLUSH] : 0;
     int nl;
     if (p.mode == MODE_RANK1)
       nl = sweep_rank1(p, ch, sw, k, io, l);
@@ -1403,30 +1494,16 @@ __device__ __forceinline__ void run_chain(const SweepParams& p, const GridDev* g
       nl = sweep_window<true>(p, ch, sw, k, io, l);
     else
       nl = sweep_window<false>(p, ch, sw, k, io, l);
-    k.t_sweep += (wall_clock64() - t0) - (k.t_flush - f0);
+    if (threadIdx.x == 0) ch.st[ST_T_SWEEP] += (wall_clock64() - t0) - (ch.st[ST_T_FLUSH] - f0);
     need_rec = (k.acc_since == p.n_rec);
     l = nl;
   }
 
   if (threadIdx.x == 0) {
     long long* st = gd->cstats + (long long)chain * NSTAT;
-    st[ST_PROPOSED] = k.n_prop;
-    st[ST_ACCEPTED] = k.n_acc;
-    st[ST_RECOMPUTES] = k.n_rec;
-    st[ST_BAD] = k.n_bad;
-    st[ST_SINGULAR] = k.singular;
-    st[ST_FLIPS] = k.n_flips;
-    st[ST_REPLAYED] = k.rep_i;
-    st[ST_FLUSHES] = k.n_flush;
-    st[ST_T_SWEEP] = k.t_sweep;
-    st[ST_T_FLUSH] = k.t_flush;
-    st[ST_T_REC] = k.t_rec;
-    st[ST_T_MEAS] = k.t_meas;
-    st[ST_T_LU_BUILD] = k.t_lu_build;
-    st[ST_T_LU_PANEL] = k.t_lu_panel;
-    st[ST_T_LU_STRIP] = k.t_lu_strip;
-    st[ST_T_LU_BACK] = k.t_lu_back;
-    gd->cdrift[chain] = k.drift;
+    ch.st[ST_REPLAYED] = k.rep_i;
+    for (int q = 0; q < NSTAT; ++q) st[q] = ch.st[q];
+    gd->cdrift[chain] = *ch.drift;
   }
   if (gd->g_final) {
     double* out = gd->g_final + (long long)chain * 2 * L2;
@@ -1505,13 +1582,15 @@ long long workspace_doubles(int Lmax, int kmax) {
 
 // LDS bytes of the LU besides the panel and the inverted triangle: reduction
 // slots, pivots and the double-buffered staged candidate rows.
-constexpr long long kLuExtra = 1024 + 2LL * (kThreads / 64) * kNBMax * 8 + 256;
+constexpr long long kLuExtra = 1024 + 2LL * (kThreads / 64) * (kNBMax + 2) * 8 + 256;
 
-// LU panel width: the widest of 32/16/8/4 whose padded LDS panel fits the budget.
-static int lu_panel(int Lmax, long long budget) {
+// LU panel width: the widest of 32/16/8/4 (at most nb_max) whose padded LDS
+// panel fits the budget.
+static int lu_panel(int Lmax, long long budget, int nb_max) {
   const int cand[4] = {32, 16, 8, 4};
   for (int q = 0; q < 4; ++q) {
     const int nb = cand[q];
+    if (nb > nb_max) continue;
     const long long np = (Lmax + nb - 1) / nb * nb;
     if (nb >= 16 && np > (long long)kThreads * (nb == 32 ? 1 : 2)) continue;  // register panel
     if (np * (nb + 2) * 8 + (long long)nb * (nb + 1) * 8 + kLuExtra <= budget) return nb;
@@ -1519,12 +1598,10 @@ static int lu_panel(int Lmax, long long budget) {
   return 4;
 }
 
-int lds_bytes(int Lmax, int mode, int k, int b, int* lu_nb, int* scratch_bytes) {
-  (void)k;
-  (void)b;
-  const long long head = ((Lmax + 15) & ~15) + (long long)Lmax * 8 + 64 * 8;
+int lds_bytes(int Lmax, int mode, int nb_max, int* lu_nb, int* scratch_bytes) {
+  const long long head = ((Lmax + 15) & ~15) + (long long)Lmax * 8 + 64 * 8 + kStatBytes;
   const long long budget = 150 * 1024 - head;
-  const int nb = lu_panel(Lmax, budget);
+  const int nb = lu_panel(Lmax, budget, nb_max > 0 ? nb_max : kNBMax);
   *lu_nb = nb;
   const long long np = (Lmax + nb - 1) / nb * nb;
   const long long lu = np * (nb + 2) * 8 + (long long)nb * (nb + 1) * 8 + kLuExtra;
@@ -1535,11 +1612,10 @@ int lds_bytes(int Lmax, int mode, int k, int b, int* lu_nb, int* scratch_bytes) 
   } else {
     const long long win = kSmall + (2LL * kWin * kWP + 4LL * kWin) * 8;
     const long long ul = kSmall + 2LL * kMaxK * kKP * 8;
-    const long long t64 = kSmall + 2LL * kMaxK * kTP * 8;
-    const long long t32 = kSmall + (1LL * kTile * kXS + 1LL * kMaxK * kYS) * 4;
+    // flush GEMM: at least one kCW-wide FP64 panel of Y
+    const long long yp = kSmall + 1LL * kCW * kYK * 8;
     long long w = win > ul ? win : ul;
-    w = w > t64 ? w : t64;
-    w = w > t32 ? w : t32;
+    w = w > yp ? w : yp;
     sc = sc > w ? sc : w;
   }
   sc = (sc + 15) & ~15LL;
@@ -1552,6 +1628,14 @@ hipError_t launch_build_g0(const double* g_tau, int L, double* G0, hipStream_t s
   int blocks = (int)((n + 255) / 256);
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(k_build_g0, dim3(blocks), dim3(256), 0, s, g_tau, L, G0);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const double* src, double* dst, long long n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int blocks = (int)((n + 255) / 256);
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(256), 0, s, src, dst, n);
   return hipGetLastError();
 }
 
@@ -1579,12 +1663,12 @@ hipError_t launch_zero_i32(int* p, long long n, hipStream_t s) {
   return hipGetLastError();
 }
 
+hipError_t prepare_sweeps(int lds) {
+  if (lds <= 64 * 1024) return hipSuccess;
+  return hipFuncSetAttribute((const void*)k_sweeps, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+}
+
 hipError_t launch_sweeps(const SweepParams& p, int n_wg, int lds, hipStream_t s) {
-  if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_sweeps,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    if (e != hipSuccess) return e;
-  }
   hipLaunchKernelGGL(k_sweeps, dim3(n_wg), dim3(kThreads), lds, s, p);
   return hipGetLastError();
 }

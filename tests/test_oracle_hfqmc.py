@@ -150,6 +150,21 @@ def test_monte_carlo_matches_enumeration_L12():
     assert c["n_recomputes"] == c["n_accepted"] // 100
 
 
+def test_heat_bath_matches_enumeration_L12():
+    # heat-bath acceptance samples the same distribution: same exact answer,
+    # a lower acceptance rate than Metropolis on the same stream
+    beta, U, L = 10.0, 4.0, 12
+    g = _semicircle_tau(beta, L)
+    gb, Db, _ = H.brute_force(g, U, beta)
+    res = H.solve(g, U, beta, seed=0, n_chains=1, warmup=100, sweeps=4000, heat_bath=True)
+    z = np.abs(res["g"][1:L] - gb[1:L]) / res["g_err"][1:L]
+    assert z.max() < 3.5
+    assert abs(res["D"] - Db) < 3.5 * res["D_err"]
+    met = H.run_chain(g, U, beta, seed=0, warmup=0, sweeps=200)
+    hb = H.run_chain(g, U, beta, seed=0, warmup=0, sweeps=200, heat_bath=True)
+    assert hb["n_accepted"] < met["n_accepted"]
+
+
 def test_delayed_updates_reproduce_rank1():
     beta, U, L = 10.0, 4.0, 20
     g = _semicircle_tau(beta, L)
