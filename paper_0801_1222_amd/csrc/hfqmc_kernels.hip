@@ -164,6 +164,7 @@ struct Chain {
   double* Gu;
   double* Gd;
   double* A;       // L x 2L LU workspace
+  double* Ui;      // U11^{-1} blocks of the LU
   double* wbuf;    // delayed-update buffers
   int8_t* s;       // field, LDS
   double* u;       // uniforms, LDS
@@ -320,11 +321,13 @@ constexpr int kRB = 4;   // 16-row blocks in flight per wave
 
 // Rows [r0, r1) (multiples of 16) of the wave's 16-column tile at column
 // c = c0 + (lane & 15):  C -= Q B, Q = P rows (r - qrow0) (NB wide, stride ps),
-// B = the tile's NB x 16 operand held in registers in B layout.
+// B = the tile's NB x 16 operand held in registers in B layout.  Row r of
+// the factorization lives in physical row perm[r] of A.
 template <int NB>
 __device__ __forceinline__ void mfma_rows_update(double* __restrict__ A, int lda, int r0, int r1,
                                                  int c, const double* __restrict__ P, int ps,
-                                                 int qrow0, const double (&b)[NB / 4]) {
+                                                 int qrow0, const double (&b)[NB / 4],
+                                                 const int* __restrict__ perm) {
   const int lane = threadIdx.x & 63;
   const int li = lane & 15, lq = lane >> 4;
 #pragma unroll 1
@@ -332,12 +335,15 @@ __device__ __forceinline__ void mfma_rows_update(double* __restrict__ A, int lda
     // blocks past r1 re-read the last block (in bounds) and are not stored
     doublex4 acc[kRB];
     double qa[kRB][NB / 4];
+    int prow[kRB][4];
 #pragma unroll
     for (int g = 0; g < kRB; ++g) {
       const int rr = min(rb + 16 * g, r1 - 16);
-      const double* cp = A + (rr + lq) * lda + c;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) acc[g][r] = cp[4 * r * lda];
+      for (int r = 0; r < 4; ++r) {
+        prow[g][r] = perm[rr + lq + 4 * r];
+        acc[g][r] = A[prow[g][r] * lda + c];
+      }
       const double* pa = P + (rr - qrow0 + li) * ps + lq;
 #pragma unroll
       for (int m = 0; m < NB / 4; ++m) qa[g][m] = -pa[4 * m];
@@ -352,9 +358,8 @@ __device__ __forceinline__ void mfma_rows_update(double* __restrict__ A, int lda
     for (int g = 0; g < kRB; ++g) {
       const int rr = rb + 16 * g;
       if (rr < r1) {
-        double* cp = A + (rr + lq) * lda + c;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) cp[4 * r * lda] = acc[g][r];
+        for (int r = 0; r < 4; ++r) A[prow[g][r] * lda + c] = acc[g][r];
       }
     }
   }
@@ -367,15 +372,19 @@ template <int NB>
 __device__ __forceinline__ void lu_strip_forward_mfma(double* __restrict__ A, int lda, int kb,
                                                       int np, int cend16,
                                                       const double* __restrict__ P, int ps,
-                                                      const double* __restrict__ Li, int ls) {
+                                                      const double* __restrict__ Li, int ls,
+                                                      const int* __restrict__ perm) {
   constexpr int KS = NB / 4;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int li = lane & 15, lq = lane >> 4;
+  int bphys[KS];
+#pragma unroll
+  for (int m = 0; m < KS; ++m) bphys[m] = perm[kb + 4 * m + lq];
   for (int c0 = kb + NB + 16 * wv; c0 < cend16; c0 += 16 * (kThreads / 64)) {
     const int c = c0 + li;
     double b[KS];
 #pragma unroll
-    for (int m = 0; m < KS; ++m) b[m] = A[(kb + 4 * m + lq) * lda + c];
+    for (int m = 0; m < KS; ++m) b[m] = A[bphys[m] * lda + c];
 #pragma unroll
     for (int ob = 0; ob < NB / 16; ++ob) {
       doublex4 acc = {0.0, 0.0, 0.0, 0.0};
@@ -384,12 +393,12 @@ __device__ __forceinline__ void lu_strip_forward_mfma(double* __restrict__ A, in
         acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Li[(16 * ob + li) * ls + 4 * m + lq], b[m], acc,
                                                    0, 0, 0);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) A[(kb + 16 * ob + 4 * r + lq) * lda + c] = acc[r];
+      for (int r = 0; r < 4; ++r) A[perm[kb + 16 * ob + 4 * r + lq] * lda + c] = acc[r];
     }
     wave_global_sync();
 #pragma unroll
-    for (int m = 0; m < KS; ++m) b[m] = A[(kb + 4 * m + lq) * lda + c];
-    mfma_rows_update<NB>(A, lda, kb + NB, np, c, P, ps, kb, b);
+    for (int m = 0; m < KS; ++m) b[m] = A[bphys[m] * lda + c];
+    mfma_rows_update<NB>(A, lda, kb + NB, np, c, P, ps, kb, b, perm);
   }
 }
 
@@ -399,15 +408,31 @@ template <int NB>
 __device__ __forceinline__ void lu_strip_backward_mfma(double* __restrict__ A, int lda, int kb,
                                                        int np, int cend16,
                                                        const double* __restrict__ P, int ps,
-                                                       const double* __restrict__ Li, int ls) {
+                                                       const double* __restrict__ Li, int ls,
+                                                       double* __restrict__ Gs, int n,
+                                                       double& dmax,
+                                                       const int* __restrict__ perm) {
   constexpr int KS = NB / 4;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int li = lane & 15, lq = lane >> 4;
+  int bphys[KS];
+#pragma unroll
+  for (int m = 0; m < KS; ++m) bphys[m] = perm[kb + 4 * m + lq];
   for (int c0 = np + 16 * wv; c0 < cend16; c0 += 16 * (kThreads / 64)) {
     const int c = c0 + li;
+    const int gc = c - np;   // column of G
     double b[KS];
 #pragma unroll
-    for (int m = 0; m < KS; ++m) b[m] = A[(kb + 4 * m + lq) * lda + c];
+    for (int m = 0; m < KS; ++m) b[m] = A[bphys[m] * lda + c];
+    // the updated G this block's final rows replace (for the drift)
+    double gold[NB / 16][4];
+#pragma unroll
+    for (int ob = 0; ob < NB / 16; ++ob)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = kb + 16 * ob + 4 * r + lq;
+        gold[ob][r] = (row < n && gc < n) ? Gs[row * n + gc] : 0.0;
+      }
 #pragma unroll
     for (int ob = 0; ob < NB / 16; ++ob) {
       doublex4 acc = {0.0, 0.0, 0.0, 0.0};
@@ -416,12 +441,22 @@ __device__ __forceinline__ void lu_strip_backward_mfma(double* __restrict__ A, i
         acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Li[(16 * ob + li) * ls + 4 * m + lq], b[m], acc,
                                                    0, 0, 0);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) A[(kb + 16 * ob + 4 * r + lq) * lda + c] = acc[r];
+      for (int r = 0; r < 4; ++r) {
+        const int row = kb + 16 * ob + 4 * r + lq;
+        A[perm[row] * lda + c] = acc[r];
+        if (row < n && gc < n) {
+          // rows kb.. are final: write G and record the drift
+          const double x = acc[r];
+          dmax = fmax(dmax, fabs(x - gold[ob][r]));
+          if (!(fabs(x) < INFINITY)) dmax = INFINITY;
+          Gs[row * n + gc] = x;
+        }
+      }
     }
     wave_global_sync();
 #pragma unroll
-    for (int m = 0; m < KS; ++m) b[m] = A[(kb + 4 * m + lq) * lda + c];
-    mfma_rows_update<NB>(A, lda, 0, kb, c, P, ps, 0, b);
+    for (int m = 0; m < KS; ++m) b[m] = A[bphys[m] * lda + c];
+    mfma_rows_update<NB>(A, lda, 0, kb, c, P, ps, 0, b, perm);
   }
 }
 
@@ -473,20 +508,22 @@ __device__ __forceinline__ void panel_factor_regs(double* __restrict__ A, int ld
                                                   double* __restrict__ P, int ps,
                                                   double* __restrict__ cand,
                                                   unsigned long long* __restrict__ keys,
-                                                  int* __restrict__ piv, int* sing) {
+                                                  int* __restrict__ piv, int* sing,
+                                                  int* __restrict__ perm) {
   constexpr int RPT = 512 / kThreads * (NB == 32 ? 1 : 2);
   constexpr int NW = kThreads / 64;
   constexpr int CS = NB + 2;   // staged candidate: window, reciprocal, position
   const int t = threadIdx.x, wv = t >> 6;
   double pr[RPT][NB];
-  int pos[RPT], fz[RPT];
+  int pos[RPT], fz[RPT], phys[RPT];
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
     const int r = t + q * kThreads;
     pos[q] = r;
     fz[q] = NB;
+    phys[q] = perm[kb + min(r, rows - 1)];
 #pragma unroll
-    for (int c = 0; c < NB; ++c) pr[q][c] = (r < rows) ? A[(kb + r) * lda + kb + c] : 0.0;
+    for (int c = 0; c < NB; ++c) pr[q][c] = (r < rows) ? A[phys[q] * lda + kb + c] : 0.0;
   }
   // the old contents of P (previous panel) must have been consumed
   __syncthreads();
@@ -575,18 +612,59 @@ __device__ __forceinline__ void panel_factor_regs(double* __restrict__ A, int ld
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
     const int r = pos[q];
-    if (t + q * kThreads < rows) {
+    const int r0 = t + q * kThreads;
+    if (r0 < rows) {
       const int f = fz[q];
 #pragma unroll
       for (int c = 0; c < NB; ++c) {
         if (c < f) P[r * ps + c] = lm[q][c];
         if (c < NB - f) {
           P[r * ps + f + c] = pr[q][c];
-          A[(kb + r) * lda + kb + f + c] = pr[q][c];
+          A[phys[q] * lda + kb + f + c] = pr[q][c];
         }
       }
+      // the interchanges only relabel rows: position kb + r is now physical row phys
+      perm[kb + r] = phys[q];
     }
   }
+  __syncthreads();
+}
+
+// L11^{-1} (unit lower) and U11^{-1} of the factored panel in P, one column
+// per lane, rows in registers (fully unrolled, uniform loops: the entries
+// above / below the diagonal come out as exact zeros).
+template <int NB>
+__device__ __forceinline__ void tri_inverse_lower(const double* __restrict__ P, int ps,
+                                                  double* __restrict__ Li, int ls) {
+  const int j = threadIdx.x & 63;
+  if (j >= NB) return;
+  double x[NB];
+#pragma unroll
+  for (int r = 0; r < NB; ++r) {
+    double acc = (r == j) ? 1.0 : 0.0;
+#pragma unroll
+    for (int q = 0; q < r; ++q) acc = fma(-P[r * ps + q], x[q], acc);
+    x[r] = acc;
+  }
+#pragma unroll
+  for (int r = 0; r < NB; ++r) Li[r * ls + j] = x[r];
+}
+
+template <int NB>
+__device__ __forceinline__ void tri_inverse_upper(const double* __restrict__ P, int ps,
+                                                  double* __restrict__ Ui) {
+  const int j = threadIdx.x & 63;
+  if (j >= NB) return;
+  double x[NB];
+#pragma unroll
+  for (int r = NB - 1; r >= 0; --r) {
+    double acc = (r == j) ? 1.0 : 0.0;
+#pragma unroll
+    for (int q = r + 1; q < NB; ++q) acc = fma(-P[r * ps + q], x[q], acc);
+    x[r] = acc / P[r * ps + r];
+  }
+#pragma unroll
+  for (int r = 0; r < NB; ++r) Ui[r * NB + j] = x[r];
 }
 
 __device__ __forceinline__ double dyson_recompute(const Chain& ch, int sigma,
@@ -607,22 +685,25 @@ __device__ __forceinline__ double dyson_recompute(const Chain& ch, int sigma,
   const int lane = t & 63, wv = t >> 6;
   long long tc = wall_clock64();
 
-  // [M | G0] with M[i][j] = delta_ij + (delta_ij - G0[i][j]) f_j, f_j = e^{V_sigma(j)} - 1
-  for (int idx = t; idx < np * np; idx += kThreads) {
-    const int i = idx / np, j = idx - i * np;
-    double m, r;
-    if (i < n && j < n) {
-      const double g0 = G0[i * n + j];
-      const double f = (sigma * s[j] > 0) ? ep : em;
-      const double dij = (i == j) ? 1.0 : 0.0;
-      m = axpy_nc(dij, dij - g0, f);
-      r = g0;
-    } else {
-      m = (i == j) ? 1.0 : 0.0;
-      r = 0.0;
+  // [M | G0] with M[i][j] = delta_ij + (delta_ij - G0[i][j]) f_j, f_j = e^{V_sigma(j)} - 1;
+  // a wave per row, lanes along it (several loads in flight per lane)
+  for (int i = wv; i < np; i += kThreads / 64) {
+#pragma unroll 4
+    for (int j = lane; j < np; j += 64) {
+      double m, r;
+      if (i < n && j < n) {
+        const double g0 = G0[i * n + j];
+        const double f = (sigma * s[j] > 0) ? ep : em;
+        const double dij = (i == j) ? 1.0 : 0.0;
+        m = axpy_nc(dij, dij - g0, f);
+        r = g0;
+      } else {
+        m = (i == j) ? 1.0 : 0.0;
+        r = 0.0;
+      }
+      A[i * lda + j] = m;
+      A[i * lda + np + j] = r;
     }
-    A[i * lda + j] = m;
-    A[i * lda + np + j] = r;
   }
 
   double* P = reinterpret_cast<double*>(ch.scratch);     // [np][ps]
@@ -634,6 +715,12 @@ __device__ __forceinline__ double dyson_recompute(const Chain& ch, int sigma,
   double* cand = reinterpret_cast<double*>(piv + 32);    // [2][waves][NB] staged candidate rows
   unsigned long long* pkeys =                            // [2][waves] candidate pivot keys
       reinterpret_cast<unsigned long long*>(cand + 2 * (kThreads / 64) * (NB + 2));
+  // physical row of each position (the matrix-core path relabels rows instead of
+  // exchanging them; the VALU path exchanges rows and keeps the identity)
+  int* perm = reinterpret_cast<int*>(pkeys + 2 * (kThreads / 64));  // [np]
+  double* Uinv = ch.Ui;                                  // [np / NB][NB][NB] U11^{-1} blocks (HBM)
+  if (NB >= 16)
+    for (int i = t; i < np; i += kThreads) perm[i] = i;
   __shared__ int s_sing;
   if (t == 0) s_sing = 0;
   __syncthreads();
@@ -646,9 +733,9 @@ __device__ __forceinline__ double dyson_recompute(const Chain& ch, int sigma,
   for (int kb = 0; kb < np; kb += NB) {
     const int rows = np - kb;
     if (NB == 32) {
-      panel_factor_regs<32>(A, lda, kb, rows, P, ps, cand, pkeys, piv, &s_sing);
+      panel_factor_regs<32>(A, lda, kb, rows, P, ps, cand, pkeys, piv, &s_sing, perm);
     } else if (NB == 16) {
-      panel_factor_regs<16>(A, lda, kb, rows, P, ps, cand, pkeys, piv, &s_sing);
+      panel_factor_regs<16>(A, lda, kb, rows, P, ps, cand, pkeys, piv, &s_sing, perm);
     } else {
       // ---- panel rows kb.., columns kb..kb+NB-1 into LDS, factorized by all waves
       for (int idx = t; idx < rows * NB; idx += kThreads) {
@@ -725,36 +812,21 @@ __device__ __forceinline__ double dyson_recompute(const Chain& ch, int sigma,
     }
     // ---- strip: interchanges, U12, trailing update (RHS included)
     if (NB >= 16) {
-      // row interchanges right of the panel, one column per thread
-      for (int c = kb + NB + t; c < cend16; c += kThreads) {
-#pragma unroll 1
-        for (int j = 0; j < NB; ++j) {
-          const int pj = piv[j];
-          if (pj != j) {
-            double* a = A + (kb + j) * lda + c;
-            double* b = A + (kb + pj) * lda + c;
-            const double tmp = *a;
-            *a = *b;
-            *b = tmp;
-          }
-        }
-      }
-      // Li = L11^{-1} (unit lower), one column per lane of wave 0
-      if (t < NB) {
-        const int j = t;
-#pragma unroll 1
-        for (int r = 0; r < NB; ++r) {
-          double x = (r == j) ? 1.0 : 0.0;
-#pragma unroll 1
-          for (int q = j; q < r; ++q) x = fma(-P[r * ps + q], Li[q * ls + j], x);
-          Li[r * ls + j] = x;
-        }
+      // wave 0: Li = L11^{-1} (LDS); wave 1: U11^{-1} (kept in HBM for the back
+      // substitution)
+      if (wv == 0) {
+        if (NB == 32) tri_inverse_lower<32>(P, ps, Li, ls);
+        else tri_inverse_lower<16>(P, ps, Li, ls);
+      } else if (wv == 1) {
+        double* Ub = Uinv + (kb / NB) * NB * NB;
+        if (NB == 32) tri_inverse_upper<32>(P, ps, Ub);
+        else tri_inverse_upper<16>(P, ps, Ub);
       }
       __syncthreads();
       if (NB == 32)
-        lu_strip_forward_mfma<32>(A, lda, kb, np, cend16, P, ps, Li, ls);
+        lu_strip_forward_mfma<32>(A, lda, kb, np, cend16, P, ps, Li, ls, perm);
       else
-        lu_strip_forward_mfma<16>(A, lda, kb, np, cend16, P, ps, Li, ls);
+        lu_strip_forward_mfma<16>(A, lda, kb, np, cend16, P, ps, Li, ls, perm);
     } else {
       switch (NB) {
         case 8: lu_strip_forward<8>(A, lda, kb, np, cend, P, ps, piv); break;
@@ -769,34 +841,36 @@ __device__ __forceinline__ double dyson_recompute(const Chain& ch, int sigma,
     }
   }
 
-  // ---- back substitution on the right-hand-side columns, block rows from the bottom
+  // ---- back substitution on the right-hand-side columns, block rows from the bottom;
+  // on the matrix-core path the final rows of each block go straight into G
+  double dmax = 0.0;
   for (int kb = np - NB; kb >= 0; kb -= NB) {
-    for (int idx = t; idx < (kb + NB) * NB; idx += kThreads) {
-      const int r = idx / NB, c = idx - r * NB;
-      P[r * ps + c] = A[r * lda + kb + c];
+    // U01 (rows above the block; with U11 on the VALU path) into P, batched loads
+    const int prow = NB >= 16 ? kb : kb + NB;
+    for (int i0 = wv; i0 < prow; i0 += 4 * (kThreads / 64)) {
+      double v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = i0 + u * (kThreads / 64);
+        const int pi = NB >= 16 ? perm[min(i, np - 1)] : i;
+        v[u] = (i < prow && lane < NB) ? A[pi * lda + kb + lane] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = i0 + u * (kThreads / 64);
+        if (i < prow && lane < NB) P[i * ps + lane] = v[u];
+      }
+    }
+    if (NB >= 16) {
+      const double* Ub = Uinv + (kb / NB) * NB * NB;
+      for (int idx = t; idx < NB * NB; idx += kThreads) Li[(idx / NB) * ls + (idx % NB)] = Ub[idx];
     }
     __syncthreads();
     if (NB >= 16) {
-      // Li = U11^{-1} (upper), one column per lane of wave 0
-      if (t < NB) {
-        const int j = t;
-#pragma unroll 1
-        for (int r = NB - 1; r >= 0; --r) {
-          double x = 0.0;
-          if (r <= j) {
-            x = (r == j) ? 1.0 : 0.0;
-#pragma unroll 1
-            for (int q = r + 1; q <= j; ++q) x = fma(-P[(kb + r) * ps + q], Li[q * ls + j], x);
-            x = x / P[(kb + r) * ps + r];
-          }
-          Li[r * ls + j] = x;
-        }
-      }
-      __syncthreads();
       if (NB == 32)
-        lu_strip_backward_mfma<32>(A, lda, kb, np, cend16, P, ps, Li, ls);
+        lu_strip_backward_mfma<32>(A, lda, kb, np, cend16, P, ps, Li, ls, Gs, n, dmax, perm);
       else
-        lu_strip_backward_mfma<16>(A, lda, kb, np, cend16, P, ps, Li, ls);
+        lu_strip_backward_mfma<16>(A, lda, kb, np, cend16, P, ps, Li, ls, Gs, n, dmax, perm);
     } else {
       switch (NB) {
         case 8: lu_strip_backward<8>(A, lda, kb, np, cend, P, ps); break;
@@ -805,15 +879,17 @@ __device__ __forceinline__ double dyson_recompute(const Chain& ch, int sigma,
     }
     __syncthreads();
   }
-
-  // G <- X, drift against the updated G
-  double dmax = 0.0;
-  for (int idx = t; idx < n * n; idx += kThreads) {
-    const int i = idx / n, j = idx - i * n;
-    const double x = A[i * lda + np + j];
-    dmax = fmax(dmax, fabs(x - Gs[idx]));
-    if (!(fabs(x) < INFINITY)) dmax = INFINITY;
-    Gs[idx] = x;
+  if (NB < 16) {
+    // G <- X, drift against the updated G (a wave per row)
+    for (int i = wv; i < n; i += kThreads / 64) {
+#pragma unroll 4
+      for (int j = lane; j < n; j += 64) {
+        const double x = A[i * lda + np + j];
+        dmax = fmax(dmax, fabs(x - Gs[i * n + j]));
+        if (!(fabs(x) < INFINITY)) dmax = INFINITY;
+        Gs[i * n + j] = x;
+      }
+    }
   }
   dmax = block_max(dmax, ch.red);
   if (s_sing && t == 0) ch.st[ST_SINGULAR] = 1;
@@ -1417,7 +1493,8 @@ __device__ __forceinline__ void run_chain(const SweepParams& p, const GridDev* g
   ch.A = ws + 2 * L2;
   {
     const long long np = (L + p.lu_nb - 1) / p.lu_nb * p.lu_nb;
-    ch.wbuf = ch.A + 2 * np * np;  // after the padded L x 2L LU workspace
+    ch.Ui = ch.A + 2 * np * np;    // after the padded L x 2L LU workspace
+    ch.wbuf = ch.Ui + np * kNBMax;
   }
   ch.s = reinterpret_cast<int8_t*>(lds);
   const int s_bytes = (p.Lmax + 15) & ~15;
@@ -1575,14 +1652,14 @@ __global__ void k_reduce(const GridDev* grids, int n_bins) {
 long long workspace_doubles(int Lmax, int kmax) {
   const long long L2 = (long long)Lmax * Lmax;
   const long long Lp = Lmax + kNBMax;  // LU padding
-  long long w = 2 * L2 + 2 * Lp * Lp + 256;
+  long long w = 2 * L2 + 2 * Lp * Lp + Lp * kNBMax + 256;
   if (kmax > 1) w += 4LL * kMaxK * kWin + 4LL * Lmax * kMaxK;
   return (w + 63) & ~63LL;
 }
 
 // LDS bytes of the LU besides the panel and the inverted triangle: reduction
 // slots, pivots and the double-buffered staged candidate rows.
-constexpr long long kLuExtra = 1024 + 2LL * (kThreads / 64) * (kNBMax + 2) * 8 + 256;
+constexpr long long kLuExtra = 1024 + 2LL * (kThreads / 64) * (kNBMax + 2) * 8 + 256 + 4 * 1056;
 
 // LU panel width: the widest of 32/16/8/4 (at most nb_max) whose padded LDS
 // panel fits the budget.
