@@ -71,7 +71,9 @@ enum {
 enum {
   HFQMC_FLAG_EAGER = 1,      /* launch the kernels one by one instead of replaying a captured
                                 HIP graph of the launch sequence (results are identical) */
-  HFQMC_FLAG_HEAT_BATH = 2   /* heat-bath acceptance u < R/(1+R) instead of Metropolis u < R */
+  HFQMC_FLAG_HEAT_BATH = 2,  /* heat-bath acceptance u < R/(1+R) instead of Metropolis u < R */
+  HFQMC_FLAG_DIRECT_RECOMPUTE = 4  /* recompute with the full L x L LU of [M | G0] instead of the
+                                      reduced system against the uniform-field references */
 };
 
 typedef struct {
@@ -114,7 +116,7 @@ typedef struct {
      delayed-update flushes, Dyson recomputes (initial ones included), measurement */
   double chain_s_sweep, chain_s_flush, chain_s_recompute, chain_s_measure;
   /* recompute breakdown (chain-seconds): matrix build, panel factorizations,
-     forward strip passes, back substitution + copy */
+     forward strip passes, back substitution (the reduced form's GEMM: chain_s_lu_gemm) */
   double chain_s_lu_build, chain_s_lu_panel, chain_s_lu_strip, chain_s_lu_back;
   int32_t delay_k;          /* k actually used (delayed modes) */
   int32_t recompute_every;  /* recompute interval actually used */
@@ -123,13 +125,26 @@ typedef struct {
   int32_t graph;            /* 1 if the launch sequence ran as a captured HIP graph */
   int32_t autotuned;        /* 1 if k and the panel width came from the autotuner */
   double seconds_autotune;  /* time spent in trial launches during this call (0 on a cache hit) */
+  int64_t n_reduced_rows;   /* sum over reduced-form recomputes of the system size |S| */
+  int32_t recompute_reduced;/* 1: reduced form (see hfqmc_solve), 0: full-size LU */
+  int32_t reserved;
+  double chain_s_lu_gemm;   /* recompute breakdown: the reduced form's GEMM (chain-seconds) */
+  double chain_s_flush_vectors, chain_s_flush_gemm;  /* flush breakdown: X, Y and G += X Y */
 } hfqmc_stats;
 
 /* Fixed-dtau solve: hfqmc_solve(G0(tau), U, beta, dtau, sweeps, seed) -> G(tau).
  * Hirsch-Fye QMC for the half-filled single-band Anderson impurity with bath
  * g0_tau[k] = G0(k dtau), k = 0..L-1, interaction U >= 0, inverse temperature
  * beta, L = beta/dtau slices (|beta/dtau - L| <= 1e-9 L), HS coupling
- * cosh(lambda) = exp(dtau U/2).  Outputs (host): g_tau[L+1] on tau_k = k dtau,
+ * cosh(lambda) = exp(dtau U/2).  The periodic recompute
+ * G = (1 + (1 - G0)(e^V - 1))^{-1} G0 (FP64) uses, unless
+ * HFQMC_FLAG_DIRECT_RECOMPUTE is set or L is too large for its LDS staging,
+ * the exact block elimination against the uniform-field reference
+ * M_r = 1 + d_r (1 - G0) (d_r the more frequent of e^{+-lambda} - 1 in the
+ * field, Q_r = M_r^{-1}(1 - G0) and H_r = M_r^{-1} G0 computed once per grid on
+ * the device): an LU of size |S| <= L/2 on the slices S where the field
+ * differs from the reference, then one GEMM for the other rows.
+ * Outputs (host): g_tau[L+1] on tau_k = k dtau,
  * k = 0..L (tau_L = beta-); g_err[L+1] (or NULL) standard error over chains
  * (or bins); docc[2] (or NULL) double occupancy and its error; stats (or NULL). */
 int hfqmc_solve(hfqmc_ctx *ctx, const double *g0_tau, int32_t L, double U, double beta,

@@ -49,10 +49,12 @@ class Stats(C.Structure):
         ("chain_s_lu_back", _f64),
         ("delay_k", _i32), ("recompute_every", _i32), ("n_workgroups", _i32), ("lu_panel", _i32),
         ("graph", _i32), ("autotuned", _i32), ("seconds_autotune", _f64),
+        ("n_reduced_rows", _i64), ("recompute_reduced", _i32), ("reserved", _i32),
+        ("chain_s_lu_gemm", _f64), ("chain_s_flush_vectors", _f64), ("chain_s_flush_gemm", _f64),
     ]
 
     def as_dict(self):
-        return {name: getattr(self, name) for name, _ in self._fields_}
+        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
 
 
 _ctx_p = C.c_void_p
@@ -86,6 +88,7 @@ lib.bath_to_tau.restype = C.c_int
 
 FLAG_EAGER = 1       # launch kernels one by one (no captured graph)
 FLAG_HEAT_BATH = 2   # heat-bath acceptance u < R/(1+R)
+FLAG_DIRECT_RECOMPUTE = 4  # full-size LU recompute instead of the reduced system
 
 EXPORTED = ["hfqmc_create", "hfqmc_destroy", "hfqmc_set_stream", "hfqmc_last_error",
             "hfqmc_solve", "hfqmc_solve_dev", "hfqmc_solve_grids", "multigrid_solve", "dmft_bethe_step",

@@ -188,7 +188,8 @@ int resolve_opts(const hfqmc_opts* o, Resolved* r) {
   r->mode = o->mode;
   r->warmup = o->warmup;
   r->sweeps = o->sweeps;
-  if (o->flags & ~(HFQMC_FLAG_EAGER | HFQMC_FLAG_HEAT_BATH)) return fail(HFQMC_EINVAL, "flags=0x%x", o->flags);
+  if (o->flags & ~(HFQMC_FLAG_EAGER | HFQMC_FLAG_HEAT_BATH | HFQMC_FLAG_DIRECT_RECOMPUTE))
+    return fail(HFQMC_EINVAL, "flags=0x%x", o->flags);
   if (o->mode == MODE_RANK1) {
     r->delay_k = 1;
     r->window_b = 1;
@@ -251,7 +252,9 @@ int autotune(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double* g0_tau,
     g0 = g0h.data();
   }
   int nb_widest = 0, scratch = 0;
-  (void)lds_bytes(Lmax, opts->mode, 0, &nb_widest, &scratch);
+  const int direct = (opts->flags & HFQMC_FLAG_DIRECT_RECOMPUTE) ? 1 : 0;
+  if (lds_bytes(Lmax, opts->mode, 0, direct, &nb_widest, &scratch) < 0)
+    (void)lds_bytes(Lmax, opts->mode, 0, 1, &nb_widest, &scratch);
   std::vector<int> nbs = {nb_widest};
   if (nb_widest == 32) nbs.push_back(16);
   hfqmc_opts to;
@@ -262,7 +265,7 @@ int autotune(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double* g0_tau,
   to.sweeps = 2;
   to.recompute_every = opts->recompute_every;
   to.n_bins = 1;
-  to.flags = (opts->flags & HFQMC_FLAG_HEAT_BATH) | HFQMC_FLAG_EAGER;
+  to.flags = (opts->flags & (HFQMC_FLAG_HEAT_BATH | HFQMC_FLAG_DIRECT_RECOMPUTE)) | HFQMC_FLAG_EAGER;
   long long P = 0;
   for (int i = 0; i < n_grids; ++i) P += Ls[i] + 1;
   std::vector<double> gs(P), es(P), ds(2 * n_grids);
@@ -335,6 +338,24 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
   }
 
   // ---- device memory layout (two passes: size, then assign)
+  // ---- launch shape (LDS, LU panel width) and the recompute form
+  int lu_nb = 0, scratch = 0;
+  int direct = (opts->flags & HFQMC_FLAG_DIRECT_RECOMPUTE) ? 1 : 0;
+  int lds = lds_bytes(Lmax, r.mode, nb_max, direct, &lu_nb, &scratch);
+  if (lds < 0) {
+    // the reduced system's LDS staging does not fit: full-size recompute
+    direct = 1;
+    lds = lds_bytes(Lmax, r.mode, nb_max, 1, &lu_nb, &scratch);
+  }
+  if (lds + 1024 > c->lds_max)
+    return fail(HFQMC_EUNSUPPORTED, "L=%d needs %d bytes of LDS, device allows %d", Lmax, lds, c->lds_max);
+  int ref_nb = 0, ref_scratch = 0, ref_lds = 0;
+  if (!direct) {
+    ref_lds = lds_bytes(Lmax, -1, 0, 1, &ref_nb, &ref_scratch);
+    if (ref_lds + 1024 > c->lds_max)
+      return fail(HFQMC_EUNSUPPORTED, "L=%d: reference solve needs %d bytes of LDS", Lmax, ref_lds);
+  }
+
   std::vector<GridDev> gd(n_grids);
   int* d_units = nullptr;
   int* d_queue = nullptr;
@@ -361,6 +382,11 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
       g.g_out = b.take<double>(L + 1);
       g.g_err = b.take<double>(L + 1);
       g.d_out = b.take<double>(2);
+      for (int q = 0; q < 2; ++q) {
+        g.refQ[q] = direct ? nullptr : b.take<double>((size_t)L * L);
+        g.refH[q] = direct ? nullptr : b.take<double>((size_t)L * L);
+      }
+      g.ref_sing = direct ? nullptr : b.take<int>(4);
     }
   };
   Bump sizing(nullptr);
@@ -416,17 +442,14 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
   HIPCHK(hipMemcpyAsync(d_units, units.data(), sizeof(int) * units.size(), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(d_grids, gd.data(), sizeof(GridDev) * n_grids, hipMemcpyHostToDevice, st));
 
-  // ---- launch shape
-  int lu_nb = 0, scratch = 0;
-  const int lds = lds_bytes(Lmax, r.mode, nb_max, &lu_nb, &scratch);
-  if (lds + 1024 > c->lds_max)
-    return fail(HFQMC_EUNSUPPORTED, "L=%d needs %d bytes of LDS, device allows %d", Lmax, lds, c->lds_max);
   // workgroups per CU: limited by LDS (160 KiB per CU) and by 2048 threads per CU
   const int occ = std::max(1, std::min(c->lds_max / (lds + 1024), 2048 / kThreads));
   const int n_units = (int)units.size();
   int n_wg = std::min(n_units, c->n_cu * occ);
   const long long wstride = workspace_doubles(Lmax, r.mode == MODE_RANK1 ? 1 : kMaxK);
-  rc = c->work.ensure((size_t)n_wg * wstride * sizeof(double));
+  // the reference kernel uses workspace slots 0 .. 4 n_grids - 1
+  const int n_slots = direct ? n_wg : std::max(n_wg, 4 * n_grids);
+  rc = c->work.ensure((size_t)n_slots * wstride * sizeof(double));
   if (rc) return rc;
 
   SweepParams p;
@@ -452,10 +475,12 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
   p.Lmax = Lmax;
   p.lds_scratch_bytes = scratch;
   p.heat_bath = (opts->flags & HFQMC_FLAG_HEAT_BATH) ? 1 : 0;
+  p.direct = direct;
 
   // ---- the device launch sequence: bath matrices, zeroed accumulators and
   // counters (fill kernels), the persistent sweep kernel, the chain reduction
   HIPCHK(prepare_sweeps(lds));
+  if (!direct) HIPCHK(prepare_reference(ref_lds));
   auto enqueue = [&](hipStream_t s) -> hipError_t {
     hipError_t e = hipSuccess;
     for (int i = 0; i < n_grids && e == hipSuccess; ++i) {
@@ -467,7 +492,9 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
       if ((e = launch_zero_i64(g.acc_n, (long long)nch * nbin, s)) != hipSuccess) break;
       if ((e = launch_zero_i64(g.cstats, (long long)nch * NSTAT, s)) != hipSuccess) break;
       e = launch_zero(g.cdrift, nch, s);
+      if (e == hipSuccess && !direct) e = launch_zero_i32(g.ref_sing, 4, s);
     }
+    if (e == hipSuccess && !direct) e = launch_reference(p, ref_nb, ref_lds, ref_scratch, s);
     if (e == hipSuccess) e = launch_zero_i32(d_queue, 64, s);
     if (e == hipSuccess) e = launch_sweeps(p, n_wg, lds, s);
     if (e == hipSuccess) e = launch_reduce(d_grids, n_grids, nbin, s);
@@ -543,6 +570,7 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
   };
   std::vector<long long> cst((size_t)nch * NSTAT);
   std::vector<double> cdr(nch);
+  int ref_bad = 0;
   std::vector<double> gcheck;
   long long goff = 0;
   double max_drift = 0.0;
@@ -561,6 +589,8 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
     }
     HIPCHK(hipMemcpyAsync(cst.data(), g.cstats, sizeof(long long) * cst.size(), hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(cdr.data(), g.cdrift, sizeof(double) * nch, hipMemcpyDeviceToHost, st));
+    int rs = 0;
+    if (!direct) HIPCHK(hipMemcpyAsync(&rs, g.ref_sing, sizeof(int), hipMemcpyDeviceToHost, st));
     const size_t cb = (size_t)i * nch;
     if (opts->flip_log) {
       HIPCHK(hipMemcpyAsync(opts->flip_log + cb * opts->flip_cap, g.flip_log,
@@ -576,6 +606,7 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
     if (opts->final_green)
       HIPCHK(hipMemcpyAsync(opts->final_green, g.g_final, sizeof(double) * nch * 2 * L * L, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    ref_bad |= rs;
     hfqmc_stats gs;
     std::memset(&gs, 0, sizeof gs);
     double gdrift = 0.0;
@@ -596,6 +627,10 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
       gs.chain_s_lu_panel += s[ST_T_LU_PANEL] * f;
       gs.chain_s_lu_strip += s[ST_T_LU_STRIP] * f;
       gs.chain_s_lu_back += s[ST_T_LU_BACK] * f;
+      gs.n_reduced_rows += s[ST_RED_ROWS];
+      gs.chain_s_lu_gemm += s[ST_T_LU_GEMM] * f;
+      gs.chain_s_flush_vectors += s[ST_T_FL_VEC] * f;
+      gs.chain_s_flush_gemm += s[ST_T_FL_GEMM] * f;
       gdrift = std::max(gdrift, cdr[ch]);
       if (!(cdr[ch] == cdr[ch])) gdrift = INFINITY;
       if (opts->flip_count) opts->flip_count[cb + ch] = s[ST_FLIPS];
@@ -610,6 +645,7 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
     gs.graph = use_graph ? 1 : 0;
     gs.autotuned = tuned ? 1 : 0;
     gs.seconds_autotune = t_tune;
+    gs.recompute_reduced = direct ? 0 : 1;
     if (stats && n_grids > 1) stats[i] = gs;
     tot.n_proposed += gs.n_proposed;
     tot.n_accepted += gs.n_accepted;
@@ -625,6 +661,10 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
     tot.chain_s_lu_panel += gs.chain_s_lu_panel;
     tot.chain_s_lu_strip += gs.chain_s_lu_strip;
     tot.chain_s_lu_back += gs.chain_s_lu_back;
+    tot.n_reduced_rows += gs.n_reduced_rows;
+    tot.chain_s_lu_gemm += gs.chain_s_lu_gemm;
+    tot.chain_s_flush_vectors += gs.chain_s_flush_vectors;
+    tot.chain_s_flush_gemm += gs.chain_s_flush_gemm;
     max_drift = std::max(max_drift, gdrift);
     const double* gv = call.dev_io ? gcheck.data() : g_tau + goff;
     for (int k = 0; k <= L; ++k)
@@ -646,6 +686,7 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
   tot.graph = use_graph ? 1 : 0;
   tot.autotuned = tuned ? 1 : 0;
   tot.seconds_autotune = t_tune;
+  tot.recompute_reduced = direct ? 0 : 1;
   if (stats) {
     if (n_grids == 1) {
       stats[0] = tot;
@@ -656,6 +697,7 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
       }
     }
   }
+  if (ref_bad) return fail(HFQMC_ENUMERIC, "singular uniform-field reference matrix");
   if (tot.n_singular) return fail(HFQMC_ENUMERIC, "singular Dyson matrix in %lld recomputes", (long long)tot.n_singular);
   if (numeric_bad || !(max_drift < INFINITY)) return fail(HFQMC_ENUMERIC, "non-finite Green function");
   if (opts->drift_limit > 0 && max_drift > opts->drift_limit)

@@ -23,7 +23,11 @@ enum {
   ST_T_LU_PANEL = 13,  // ... panel factorizations
   ST_T_LU_STRIP = 14,  // ... forward strip passes (interchanges, U12, trailing update)
   ST_T_LU_BACK = 15,   // ... back substitution and the copy into G
-  NSTAT = 16
+  ST_RED_ROWS = 16,    // sum over reduced-form solves of the system size |S|
+  ST_T_LU_GEMM = 17,   // recompute breakdown: the reduced form's GEMM for the rows outside S
+  ST_T_FL_VEC = 18,    // flush breakdown: the full update vectors X, Y
+  ST_T_FL_GEMM = 19,   // ... the rank-m product G += X Y
+  NSTAT = 20
 };
 
 enum { MODE_RANK1 = 0, MODE_DELAYED_FP64 = 1, MODE_MIXED = 2 };
@@ -33,6 +37,9 @@ struct GridDev {
   int L;
   int n_chains;
   int grid_id;            // Philox key word 1
+  const double* refQ[2];  // L x L, Q_r = M_r^{-1} (1 - G0) for the uniform references
+  const double* refH[2];  //   r = 0: D = e^{lambda} - 1, r = 1: D = e^{-lambda} - 1; H_r = M_r^{-1} G0
+  int* ref_sing;          // set when a reference solve met a zero pivot
   int unit_base;          // index of chain 0 of this grid in the per-launch chain arrays
   double gp, gm;          // e^{2 lambda} - 1, e^{-2 lambda} - 1  (flip factors gamma)
   double ep, em;          // e^{lambda} - 1,   e^{-lambda} - 1    (Dyson matrix diagonal)
@@ -71,6 +78,7 @@ struct SweepParams {
   int Lmax;
   int lds_scratch_bytes;  // bytes of the phase-shared LDS region
   int heat_bath;          // 1: accept iff u < R/(1+R); 0: Metropolis, u < R
+  int direct;             // 1: recompute with the full L x L system (no reference reduction)
 };
 
 constexpr int kThreads = 512;   // threads per persistent workgroup (8 wave64)
@@ -80,8 +88,10 @@ constexpr int kMaxK = 64;       // largest delayed rank
 // Workspace (doubles) needed per workgroup for chains of length up to Lmax.
 long long workspace_doubles(int Lmax, int kmax);
 // Dynamic LDS bytes of the persistent kernel and the LU panel width for Lmax
-// (the widest that fits the LDS budget, at most nb_max).
-int lds_bytes(int Lmax, int mode, int nb_max, int* lu_nb, int* scratch_bytes);
+// (the widest that fits the LDS budget, at most nb_max).  direct = 0 sizes the
+// LU for the reduced system (at most Lmax/2) and returns -1 if that form does
+// not fit; the reference kernel uses direct = 1.
+int lds_bytes(int Lmax, int mode, int nb_max, int direct, int* lu_nb, int* scratch_bytes);
 // Sets the kernel's dynamic-LDS limit (needed above 64 KiB); call before a
 // launch or a stream capture.
 hipError_t prepare_sweeps(int lds);
@@ -92,6 +102,10 @@ hipError_t launch_zero(double* p, long long n, hipStream_t s);
 hipError_t launch_zero_i64(long long* p, long long n, hipStream_t s);
 hipError_t launch_zero_i32(int* p, long long n, hipStream_t s);
 hipError_t launch_sweeps(const SweepParams& p, int n_wg, int lds, hipStream_t s);
+// Uniform-field reference matrices (Q_r, H_r, r = 0, 1) of every grid: 4
+// workgroups per grid, direct LU with panel width nb, workspace slots 0..4 n_grids-1.
+hipError_t prepare_reference(int lds);
+hipError_t launch_reference(const SweepParams& p, int nb, int lds, int scratch, hipStream_t s);
 hipError_t launch_reduce(const GridDev* grids, int n_grids, int n_bins, hipStream_t s);
 
 }  // namespace hfqmc

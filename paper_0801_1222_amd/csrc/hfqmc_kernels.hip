@@ -150,6 +150,12 @@ __global__ void k_zero(T* p, long long n) {
 
 // ----------------------------------------------------- chain context ----
 
+// Global-memory views of pointers the compiler cannot place itself (loaded from
+// device structs): global_load/store instead of flat accesses, which would also
+// count against the LDS wait counter.
+typedef __attribute__((address_space(1))) double gdouble;
+typedef __attribute__((address_space(1))) const double gcdouble;
+
 constexpr int kStatBytes = 256;   // LDS statistics block: NSTAT counters + drift
 
 struct Chain {
@@ -173,6 +179,9 @@ struct Chain {
   double* red;     // reduction scratch, LDS
   long long* st;   // per-chain statistics [NSTAT] (ST_*), LDS, written by thread 0 only
   double* drift;   // largest recompute drift so far, LDS, thread 0 only
+  int* sr;         // LDS [L]: the reduced solve's slice lists (S, then R)
+  const double* refQ[2];
+  const double* refH[2];
 };
 
 // Control state every thread keeps (uniform); the statistics live in LDS.
@@ -409,7 +418,8 @@ __device__ __forceinline__ void lu_strip_backward_mfma(double* __restrict__ A, i
                                                        int np, int cend16,
                                                        const double* __restrict__ P, int ps,
                                                        const double* __restrict__ Li, int ls,
-                                                       double* __restrict__ Gs, int n,
+                                                       gdouble* __restrict__ Gs, int ns, int L,
+                                                       const int* __restrict__ rowmap,
                                                        double& dmax,
                                                        const int* __restrict__ perm) {
   constexpr int KS = NB / 4;
@@ -424,14 +434,18 @@ __device__ __forceinline__ void lu_strip_backward_mfma(double* __restrict__ A, i
     double b[KS];
 #pragma unroll
     for (int m = 0; m < KS; ++m) b[m] = A[bphys[m] * lda + c];
-    // the updated G this block's final rows replace (for the drift)
+    // the updated G this block's final rows replace (for the drift); solution
+    // row i is row rowmap[i] of G (identity without a map)
     double gold[NB / 16][4];
+    int grow[NB / 16][4];
 #pragma unroll
     for (int ob = 0; ob < NB / 16; ++ob)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = kb + 16 * ob + 4 * r + lq;
-        gold[ob][r] = (row < n && gc < n) ? Gs[row * n + gc] : 0.0;
+        const bool ok = row < ns && gc < L;
+        grow[ob][r] = ok ? (rowmap ? rowmap[row] : row) : 0;
+        gold[ob][r] = ok ? Gs[grow[ob][r] * L + gc] : 0.0;
       }
 #pragma unroll
     for (int ob = 0; ob < NB / 16; ++ob) {
@@ -444,12 +458,12 @@ __device__ __forceinline__ void lu_strip_backward_mfma(double* __restrict__ A, i
       for (int r = 0; r < 4; ++r) {
         const int row = kb + 16 * ob + 4 * r + lq;
         A[perm[row] * lda + c] = acc[r];
-        if (row < n && gc < n) {
+        if (row < ns && gc < L) {
           // rows kb.. are final: write G and record the drift
           const double x = acc[r];
           dmax = fmax(dmax, fabs(x - gold[ob][r]));
           if (!(fabs(x) < INFINITY)) dmax = INFINITY;
-          Gs[row * n + gc] = x;
+          Gs[grow[ob][r] * L + gc] = x;
         }
       }
     }
@@ -527,73 +541,80 @@ __device__ __forceinline__ void panel_factor_regs(double* __restrict__ A, int ld
   }
   // the old contents of P (previous panel) must have been consumed
   __syncthreads();
+  // waves without rows only keep the barriers
+  const int nwa = (min(rows, kThreads) + 63) >> 6;
+  const bool wact = wv < nwa;
 #pragma unroll 1
   for (int j = 0; j < NB; ++j) {
-    unsigned long long best = 0;
-    int bq = 0;
+    if (wact) {
+      unsigned long long best = 0;
+      int bq = 0;
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      const bool act = pos[q] >= j && pos[q] < rows;
-      const unsigned long long bits =
-          (unsigned long long)__double_as_longlong(fabs(pr[q][0])) & ~0x3FFull;
-      const unsigned long long key =
-          act ? (bits | (unsigned long long)(1023 - (t + q * kThreads))) : 0ull;
-      if (key > best) {
-        best = key;
-        bq = q;
+      for (int q = 0; q < RPT; ++q) {
+        const bool act = pos[q] >= j && pos[q] < rows;
+        const unsigned long long bits =
+            (unsigned long long)__double_as_longlong(fabs(pr[q][0])) & ~0x3FFull;
+        const unsigned long long key =
+            act ? (bits | (unsigned long long)(1023 - (t + q * kThreads))) : 0ull;
+        if (key > best) {
+          best = key;
+          bq = q;
+        }
       }
-    }
-    const double head = (RPT == 2 && bq) ? pr[RPT - 1][0] : pr[0][0];
-    const double hinv = 1.0 / head;   // used only if this row wins
-    const unsigned long long wbest = wave_max_key(best);
-    if (best == wbest && wbest != 0ull) {
-      double* cw = cand + wv * CS;
+      const double head = (RPT == 2 && bq) ? pr[RPT - 1][0] : pr[0][0];
+      const double hinv = 1.0 / head;   // used only if this row wins
+      const unsigned long long wbest = wave_max_key(best);
+      if (best == wbest && wbest != 0ull) {
+        double* cw = cand + wv * CS;
 #pragma unroll
-      for (int c = 0; c < NB; ++c) cw[c] = (RPT == 2 && bq) ? pr[RPT - 1][c] : pr[0][c];
-      cw[NB] = hinv;
-      cw[NB + 1] = (double)((RPT == 2 && bq) ? pos[RPT - 1] : pos[0]);
-      keys[wv] = wbest;
-    } else if (wbest == 0ull && (t & 63) == 0) {
-      keys[wv] = 0ull;
+        for (int c = 0; c < NB; ++c) cw[c] = (RPT == 2 && bq) ? pr[RPT - 1][c] : pr[0][c];
+        cw[NB] = hinv;
+        cw[NB + 1] = (double)((RPT == 2 && bq) ? pos[RPT - 1] : pos[0]);
+        keys[wv] = wbest;
+      } else if (wbest == 0ull && (t & 63) == 0) {
+        keys[wv] = 0ull;
+      }
     }
     __syncthreads();
-    unsigned long long gk = keys[0];
+    if (wact) {
+      unsigned long long gk = keys[0];
 #pragma unroll
-    for (int w = 1; w < NW; ++w) {
-      const unsigned long long o = keys[w];
-      gk = o > gk ? o : gk;
-    }
-    const int gw = ((1023 - (int)(gk & 0x3FFull)) & (kThreads - 1)) >> 6;
-    double prow[CS];
-    {
-      const double2* c2 = reinterpret_cast<const double2*>(cand + gw * CS);
-#pragma unroll
-      for (int c = 0; c < CS / 2; ++c) {
-        const double2 v = c2[c];
-        prow[2 * c] = v.x;
-        prow[2 * c + 1] = v.y;
+      for (int w = 1; w < NW; ++w) {
+        const unsigned long long o = (w < nwa) ? keys[w] : 0ull;
+        gk = o > gk ? o : gk;
       }
-    }
-    const double pv = prow[0];
-    const double rinv = prow[NB];
-    const int gp = (int)prow[NB + 1];
-    if (t == 0) {
-      piv[j] = gp;
-      if (!(fabs(pv) > 0.0 && fabs(pv) < INFINITY)) *sing = 1;
-    }
+      const int gw = ((1023 - (int)(gk & 0x3FFull)) & (kThreads - 1)) >> 6;
+      double prow[CS];
+      {
+        const double2* c2 = reinterpret_cast<const double2*>(cand + gw * CS);
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) {
-      if (pos[q] == gp)
-        pos[q] = j;
-      else if (pos[q] == j)
-        pos[q] = gp;
-      if (pos[q] == j) {
-        fz[q] = j;
-      } else if (pos[q] > j && pos[q] < rows) {
-        const double l = pr[q][0] * rinv;
-        P[(t + q * kThreads) * ps + j] = l;
+        for (int c = 0; c < CS / 2; ++c) {
+          const double2 v = c2[c];
+          prow[2 * c] = v.x;
+          prow[2 * c + 1] = v.y;
+        }
+      }
+      const double pv = prow[0];
+      const double rinv = prow[NB];
+      const int gp = (int)prow[NB + 1];
+      if (t == 0) {
+        piv[j] = gp;
+        if (!(fabs(pv) > 0.0 && fabs(pv) < INFINITY)) *sing = 1;
+      }
 #pragma unroll
-        for (int c = 0; c + 1 < NB; ++c) pr[q][c] = fma(-l, prow[c + 1], pr[q][c + 1]);
+      for (int q = 0; q < RPT; ++q) {
+        if (pos[q] == gp)
+          pos[q] = j;
+        else if (pos[q] == j)
+          pos[q] = gp;
+        if (pos[q] == j) {
+          fz[q] = j;
+        } else if (pos[q] > j && pos[q] < rows) {
+          const double l = pr[q][0] * rinv;
+          P[(t + q * kThreads) * ps + j] = l;
+#pragma unroll
+          for (int c = 0; c + 1 < NB; ++c) pr[q][c] = fma(-l, prow[c + 1], pr[q][c + 1]);
+        }
       }
     }
     cand += (j & 1) ? -NW * CS : NW * CS;
@@ -667,41 +688,146 @@ __device__ __forceinline__ void tri_inverse_upper(const double* __restrict__ P, 
   for (int r = 0; r < NB; ++r) Ui[r * NB + j] = x[r];
 }
 
-__device__ __forceinline__ double dyson_recompute(const Chain& ch, int sigma,
-                                                  double* __restrict__ Gs, int NB) {
-  const int n = ch.L;
-  const int np = (n + NB - 1) / NB * NB;
-  const int lda = 2 * np;
-  const int ps = NB + 2;              // LDS row stride of the panel (16-byte aligned rows)
-  // right-hand-side columns beyond n stay zero and are skipped (up to the
-  // next multiple of 16 on the matrix-core path, which works in 16-column tiles)
-  const int cend = np + n;
-  const int cend16 = np + ((n + 15) & ~15);
-  double* __restrict__ A = ch.A;
-  const double* __restrict__ G0 = ch.G0;
-  const double ep = ch.ep, em = ch.em;
-  const int8_t* s = ch.s;
+// Exclusive prefix sum of v over the workgroup (thread order); *total gets the
+// sum.  `red` holds kThreads/64 + 1 ints.
+__device__ __forceinline__ int block_exclusive_scan(int v, int* red, int* total) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  __syncthreads();
+  if (lane == 63) red[wv] = x;
+  __syncthreads();
+  int before = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < kThreads / 64; ++w) {
+    const int r = red[w];
+    before += (w < wv) ? r : 0;
+    tot += r;
+  }
+  *total = tot;
+  return before + x - v;
+}
+
+// ---------------------------------------------------- the Dyson solve ----
+//
+// Direct form: G_sigma = M^{-1} G0 with M = 1 + K D, K = 1 - G0,
+// D = diag(e^{V_sigma} - 1), by the LU of [M | G0].
+//
+// Reduced form (the default inside the sweep): D takes only the two values
+// d_a = e^{lambda} - 1 and d_b = e^{-lambda} - 1.  With the uniform reference
+// M_r = 1 + d_r K of the more frequent value d_r (shared by all chains of a
+// grid, precomputed as Q_r = M_r^{-1} K and H_r = M_r^{-1} G0) and S the
+// slices where D = d_s != d_r (|S| <= L/2), M = M_r + c K P_S with
+// c = d_s - d_r, so that (block elimination, exact in exact arithmetic)
+//   (1 + c Q_r[S,S]) G[S,:] = H_r[S,:],    G[R,:] = H_r[R,:] - c Q_r[R,S] G[S,:].
+// Only the |S| x |S| system goes through the LU; the rest is one GEMM.
+//
+// Both share the LU below: system [A_sys | B] padded to np (identity rows and
+// zero right-hand sides), right-looking with partial pivoting, solution row i
+// written to G row map(i).  Returns the largest elementwise change against
+// the G it replaces (the drift).
+//
+// rhs_k (direct form only): right-hand side K = 1 - G0 instead of G0 (the
+// reference matrices Q_r).
+__device__ __forceinline__ double dyson_solve(const Chain& ch, int sigma, double* Gs_,
+                                              int NB, bool reduced, bool rhs_k) {
+  const int L = ch.L;
   const int t = threadIdx.x;
   const int lane = t & 63, wv = t >> 6;
+  const double ep = ch.ep, em = ch.em;
+  const int8_t* s = ch.s;
+  gdouble* __restrict__ Gs = (gdouble*)Gs_;
+  gcdouble* __restrict__ G0 = (gcdouble*)ch.G0;
+  double* __restrict__ A = ch.A;
+  int* sr = ch.sr;
   long long tc = wall_clock64();
 
-  // [M | G0] with M[i][j] = delta_ij + (delta_ij - G0[i][j]) f_j, f_j = e^{V_sigma(j)} - 1;
-  // a wave per row, lanes along it (several loads in flight per lane)
+  // ---- the system: all slices (direct) or S (reduced)
+  int ns = L;
+  double c = 0.0;
+  gcdouble* __restrict__ Qr = nullptr;
+  gcdouble* __restrict__ Hr = nullptr;
+  if (reduced) {
+    // slices with D = e^{lambda} - 1 (sigma s_l > 0); the other value forms S
+    const int per = (L + kThreads - 1) / kThreads;
+    const int l0 = min(t * per, L), l1 = min(l0 + per, L);
+    int na = 0;
+    for (int l = l0; l < l1; ++l) na += (sigma * s[l] > 0) ? 1 : 0;
+    int n_a = 0;
+    (void)block_exclusive_scan(na, reinterpret_cast<int*>(ch.red), &n_a);
+    const int ref = (n_a >= L - n_a) ? 0 : 1;          // 0: reference d_a, 1: d_b
+    c = ref == 0 ? (em - ep) : (ep - em);
+    Qr = (gcdouble*)ch.refQ[ref];
+    Hr = (gcdouble*)ch.refH[ref];
+    const int want = ref == 0 ? -1 : 1;                // sign of sigma s_l on S
+    int ms = 0;
+    for (int l = l0; l < l1; ++l) ms += (sigma * s[l] == want) ? 1 : 0;
+    const int sb = block_exclusive_scan(ms, reinterpret_cast<int*>(ch.red), &ns);
+    // S in increasing order first, then R
+    int is = sb, ir = ns + (l0 - sb);
+    for (int l = l0; l < l1; ++l) {
+      if (sigma * s[l] == want) sr[is++] = l;
+      else sr[ir++] = l;
+    }
+    __syncthreads();
+    if (ns == 0) {
+      // D is uniform: G = H_r
+      double dm = 0.0;
+      for (int i = wv; i < L; i += kThreads / 64)
+#pragma unroll 4
+        for (int j = lane; j < L; j += 64) {
+          const double x = Hr[i * L + j];
+          dm = fmax(dm, fabs(x - Gs[i * L + j]));
+          if (!(fabs(x) < INFINITY)) dm = INFINITY;
+          Gs[i * L + j] = x;
+        }
+      dm = block_max(dm, ch.red);
+      __syncthreads();
+      stat_add(ch.st, ST_T_LU_BUILD, wall_clock64() - tc);
+      return dm;
+    }
+    stat_add(ch.st, ST_RED_ROWS, ns);
+  }
+  const int np = (ns + NB - 1) / NB * NB;
+  const int rhs16 = (L + 15) & ~15;
+  const int lda = np + (np > rhs16 ? np : rhs16);
+  const int ps = NB + 2;              // LDS row stride of the panel (16-byte aligned rows)
+  // right-hand-side columns beyond L stay zero and are skipped (up to the
+  // next multiple of 16 on the matrix-core path, which works in 16-column tiles)
+  const int cend = np + L;
+  const int cend16 = np + rhs16;
+
+  // ---- build [A_sys | B]: a wave per row, lanes along it
   for (int i = wv; i < np; i += kThreads / 64) {
+    const int gi = reduced ? sr[min(i, ns - 1)] : i;
 #pragma unroll 4
     for (int j = lane; j < np; j += 64) {
-      double m, r;
-      if (i < n && j < n) {
-        const double g0 = G0[i * n + j];
-        const double f = (sigma * s[j] > 0) ? ep : em;
+      double m;
+      if (i < ns && j < ns) {
         const double dij = (i == j) ? 1.0 : 0.0;
-        m = axpy_nc(dij, dij - g0, f);
-        r = g0;
+        if (reduced) {
+          m = dij + c * Qr[gi * L + sr[j]];
+        } else {
+          const double g0 = G0[i * L + j];
+          const double f = (sigma * s[j] > 0) ? ep : em;
+          m = axpy_nc(dij, dij - g0, f);
+        }
       } else {
         m = (i == j) ? 1.0 : 0.0;
-        r = 0.0;
       }
       A[i * lda + j] = m;
+    }
+#pragma unroll 4
+    for (int j = lane; j < lda - np; j += 64) {
+      double r = 0.0;
+      if (i < ns && j < L) {
+        if (reduced) r = Hr[gi * L + j];
+        else r = rhs_k ? ((i == j ? 1.0 : 0.0) - G0[i * L + j]) : G0[i * L + j];
+      }
       A[i * lda + np + j] = r;
     }
   }
@@ -739,8 +865,8 @@ __device__ __forceinline__ double dyson_recompute(const Chain& ch, int sigma,
     } else {
       // ---- panel rows kb.., columns kb..kb+NB-1 into LDS, factorized by all waves
       for (int idx = t; idx < rows * NB; idx += kThreads) {
-        const int r = idx / NB, c = idx - r * NB;
-        P[r * ps + c] = A[(kb + r) * lda + kb + c];
+        const int r = idx / NB, cc = idx - r * NB;
+        P[r * ps + cc] = A[(kb + r) * lda + kb + cc];
       }
       __syncthreads();
   #pragma unroll 1
@@ -793,7 +919,7 @@ __device__ __forceinline__ double dyson_recompute(const Chain& ch, int sigma,
           double* pr = P + r * ps;
           const double l = pr[j] / pv;
           pr[j] = l;
-          for (int c = j + 1; c < NB; ++c) pr[c] = fma(-l, P[j * ps + c], pr[c]);
+          for (int cc = j + 1; cc < NB; ++cc) pr[cc] = fma(-l, P[j * ps + cc], pr[cc]);
         }
         __syncthreads();
       }
@@ -801,8 +927,8 @@ __device__ __forceinline__ double dyson_recompute(const Chain& ch, int sigma,
     // U11 -> A for the back substitution (the register panel wrote it already)
     if (NB < 16) {
       for (int idx = t; idx < NB * NB; idx += kThreads) {
-        const int r = idx / NB, c = idx - r * NB;
-        if (c >= r) A[(kb + r) * lda + kb + c] = P[r * ps + c];
+        const int r = idx / NB, cc = idx - r * NB;
+        if (cc >= r) A[(kb + r) * lda + kb + cc] = P[r * ps + cc];
       }
     }
     {
@@ -810,7 +936,7 @@ __device__ __forceinline__ double dyson_recompute(const Chain& ch, int sigma,
       stat_add(ch.st, ST_T_LU_PANEL, t1 - tc);
       tc = t1;
     }
-    // ---- strip: interchanges, U12, trailing update (RHS included)
+    // ---- strip: U12, trailing update (right-hand side included)
     if (NB >= 16) {
       // wave 0: Li = L11^{-1} (LDS); wave 1: U11^{-1} (kept in HBM for the back
       // substitution)
@@ -843,6 +969,7 @@ __device__ __forceinline__ double dyson_recompute(const Chain& ch, int sigma,
 
   // ---- back substitution on the right-hand-side columns, block rows from the bottom;
   // on the matrix-core path the final rows of each block go straight into G
+  const int* rowmap = reduced ? sr : nullptr;
   double dmax = 0.0;
   for (int kb = np - NB; kb >= 0; kb -= NB) {
     // U01 (rows above the block; with U11 on the VALU path) into P, batched loads
@@ -868,9 +995,11 @@ __device__ __forceinline__ double dyson_recompute(const Chain& ch, int sigma,
     __syncthreads();
     if (NB >= 16) {
       if (NB == 32)
-        lu_strip_backward_mfma<32>(A, lda, kb, np, cend16, P, ps, Li, ls, Gs, n, dmax, perm);
+        lu_strip_backward_mfma<32>(A, lda, kb, np, cend16, P, ps, Li, ls, Gs, ns, L, rowmap, dmax,
+                                   perm);
       else
-        lu_strip_backward_mfma<16>(A, lda, kb, np, cend16, P, ps, Li, ls, Gs, n, dmax, perm);
+        lu_strip_backward_mfma<16>(A, lda, kb, np, cend16, P, ps, Li, ls, Gs, ns, L, rowmap, dmax,
+                                   perm);
     } else {
       switch (NB) {
         case 8: lu_strip_backward<8>(A, lda, kb, np, cend, P, ps); break;
@@ -881,20 +1010,146 @@ __device__ __forceinline__ double dyson_recompute(const Chain& ch, int sigma,
   }
   if (NB < 16) {
     // G <- X, drift against the updated G (a wave per row)
-    for (int i = wv; i < n; i += kThreads / 64) {
+    for (int i = wv; i < ns; i += kThreads / 64) {
+      const int gi = rowmap ? rowmap[i] : i;
 #pragma unroll 4
-      for (int j = lane; j < n; j += 64) {
+      for (int j = lane; j < L; j += 64) {
         const double x = A[i * lda + np + j];
-        dmax = fmax(dmax, fabs(x - Gs[i * n + j]));
+        dmax = fmax(dmax, fabs(x - Gs[gi * L + j]));
         if (!(fabs(x) < INFINITY)) dmax = INFINITY;
-        Gs[i * n + j] = x;
+        Gs[gi * L + j] = x;
+      }
+    }
+  }
+
+  {
+    const long long t1 = wall_clock64();
+    stat_add(ch.st, ST_T_LU_BACK, t1 - tc);
+    tc = t1;
+  }
+  // ---- reduced form: G[R,:] = H_r[R,:] - c Q_r[R,S] G[S,:] on the matrix cores.
+  // -c Q_r[R,S] is first gathered into a dense row-major block (over the LU
+  // workspace, no longer needed); G[S,:] (just written) is staged in LDS by
+  // column chunks.  Lane (i, q) of the 16 x 16 x 4 MFMA walks the contiguous K
+  // range [q ks, (q + 1) ks): the A operand streams as 16-byte loads.
+  if (reduced && ns < L) {
+    const int nR = L - ns;
+    const int kr = (ns + 7) & ~7;                       // K rows (zero padded, 8 | kr)
+    const int ks = kr >> 2;                             // K steps (even)
+    const int* Rl = sr + ns;
+    double* __restrict__ Aq = A;                        // [nR][kr]
+    __syncthreads();   // every read of the LU workspace is done
+    for (int j0 = wv; j0 < nR; j0 += 2 * (kThreads / 64)) {
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int j = j0 + u * (kThreads / 64);
+        if (j < nR) {
+          gcdouble* qrow = Qr + (long long)Rl[j] * L;
+#pragma unroll 4
+          for (int i = lane; i < kr; i += 64) Aq[j * kr + i] = (i < ns) ? -c * qrow[sr[i]] : 0.0;
+        }
+      }
+    }
+    int zw = 64;                                        // chunk width
+    while (zw > 16 && (long long)kr * (zw + 2) * 8 > ch.scratch_bytes) zw >>= 1;
+    const int zs = zw + 2;
+    double* Zl = reinterpret_cast<double*>(ch.scratch);
+    const int li = lane & 15, lq = lane >> 4;
+    const int nrb = (nR + 15) >> 4;
+    for (int c0 = 0; c0 < L; c0 += zw) {
+      __syncthreads();
+      // a wave per row, four rows in flight; lanes along the chunk
+      for (int i0 = wv; i0 < kr; i0 += 4 * (kThreads / 64)) {
+        for (int j = lane; j < zw; j += 64) {
+          double v[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int i = i0 + u * (kThreads / 64);
+            const int gi = sr[min(i, ns - 1)];
+            v[u] = (i < ns && c0 + j < L) ? Gs[gi * L + c0 + j] : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int i = i0 + u * (kThreads / 64);
+            if (i < kr) Zl[i * zs + j] = v[u];
+          }
+        }
+      }
+      __syncthreads();
+      const int ntile = (min(zw, L - c0) + 15) >> 4;   // 16-column tiles in this chunk (<= 4)
+      for (int rb = wv; rb < nrb; rb += kThreads / 64) {
+        // one 16-row block of R against every tile of the chunk; the A operand
+        // is prefetched a batch of kGB steps ahead (two register batches in turn)
+        constexpr int kGB = 16;
+        const int arow = min(rb * 16 + li, nR - 1);
+        const double2* arow2 = reinterpret_cast<const double2*>(Aq + (long long)arow * kr + lq * ks);
+        int orow[4], oR[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          orow[r] = rb * 16 + 4 * r + lq;
+          oR[r] = Rl[min(orow[r], nR - 1)];
+        }
+        doublex4 acc[4];
+        double gold[4][4];
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt) {
+          const int col = min(c0 + 16 * tt + li, L - 1);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            acc[tt][r] = (tt < ntile) ? Hr[oR[r] * L + col] : 0.0;
+            gold[tt][r] = (tt < ntile) ? Gs[oR[r] * L + col] : 0.0;
+          }
+        }
+        // steps q0.. of this lane's K range (clamped, in bounds: ks is even)
+        auto load_a = [&](int q0, double2 (&av)[kGB / 2]) {
+#pragma unroll
+          for (int u = 0; u < kGB / 2; ++u) av[u] = arow2[min(q0 / 2 + u, ks / 2 - 1)];
+        };
+        auto mma = [&](int q0, const double2 (&av)[kGB / 2]) {
+#pragma unroll
+          for (int u = 0; u < kGB; ++u) {
+            if (q0 + u < ks) {
+              const double a = (u & 1) ? av[u >> 1].y : av[u >> 1].x;
+              const double* zb = Zl + (lq * ks + q0 + u) * zs + li;
+#pragma unroll
+              for (int tt = 0; tt < 4; ++tt)
+                if (tt < ntile)
+                  acc[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, zb[16 * tt], acc[tt], 0, 0, 0);
+            }
+          }
+        };
+        double2 a0[kGB / 2], a1[kGB / 2];
+        load_a(0, a0);
+#pragma unroll 1
+        for (int q0 = 0; q0 < ks; q0 += 2 * kGB) {
+          if (q0 + kGB < ks) load_a(q0 + kGB, a1);
+          mma(q0, a0);
+          if (q0 + kGB >= ks) break;
+          if (q0 + 2 * kGB < ks) load_a(q0 + 2 * kGB, a0);
+          mma(q0 + kGB, a1);
+        }
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt) {
+          const int col = c0 + 16 * tt + li;
+          if (tt < ntile && col < L && col < c0 + zw) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              if (orow[r] < nR) {
+                const double x = acc[tt][r];
+                dmax = fmax(dmax, fabs(x - gold[tt][r]));
+                if (!(fabs(x) < INFINITY)) dmax = INFINITY;
+                Gs[oR[r] * L + col] = x;
+              }
+            }
+          }
+        }
       }
     }
   }
   dmax = block_max(dmax, ch.red);
   if (s_sing && t == 0) ch.st[ST_SINGULAR] = 1;
   __syncthreads();
-  stat_add(ch.st, ST_T_LU_BACK, wall_clock64() - tc);
+  stat_add(ch.st, ST_T_LU_GEMM, wall_clock64() - tc);
   return dmax;
 }
 
@@ -998,7 +1253,7 @@ __device__ __forceinline__ void recompute_both(const SweepParams& p, const Chain
   double d = 0.0;
 #pragma unroll 1
   for (int sp = 0; sp < 2; ++sp)
-    d = fmax(d, dyson_recompute(ch, sp ? -1 : +1, sp ? ch.Gd : ch.Gu, p.lu_nb));
+    d = fmax(d, dyson_solve(ch, sp ? -1 : +1, sp ? ch.Gd : ch.Gu, p.lu_nb, p.direct == 0, false));
   if (counted && threadIdx.x == 0) {
     *ch.drift = fmax(*ch.drift, d);
     ch.st[ST_RECOMPUTES] += 1;
@@ -1226,14 +1481,15 @@ __device__ __forceinline__ void flush_gemm(double* __restrict__ G, const double*
   }
 }
 
-// X = C0 T and Y = S R0 of one spin on the matrix cores (FP64), wave-
-// independent 16 x 16 output tiles.  C0[q][i] = G[q][f_i] - delta(q, f_i),
-// R0[i][r] = G[f_i][r] (f_i = l0 + F[i]); T (upper, unit diagonal) and S
-// (lower, diagonal c_j) share the m x m LDS block TS (row stride kKP):
-// T[i][j] = TS[i][j] for i < j, S[j][i] = TS[j][i] for i <= j.
+// The update's two factors for one spin, G += X Y with
+//   X = C0 = G[:, F] - I[:, F]   (gathered, L x m)  and   Y = W R0, R0 = G[F, :],
+// where W = T S (m x m, in LDS with row stride kKP) folds both triangular
+// factors of the delayed update into the right factor (f_i = l0 + F[i]).
+// Y on the matrix cores (FP64) in wave-independent 16 x 16 tiles whose G rows
+// are loaded one tile ahead.
 __device__ __forceinline__ void flush_vectors(const double* __restrict__ G, int L, int l0, int m,
                                               const int* __restrict__ F,
-                                              const double* __restrict__ TS,
+                                              const double* __restrict__ W,
                                               double* __restrict__ X, double* __restrict__ Y) {
   constexpr int KS = kMaxK / 4;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -1241,62 +1497,113 @@ __device__ __forceinline__ void flush_vectors(const double* __restrict__ G, int 
   const int ks = (m + 3) >> 2;
   const int mb = (m + 15) >> 4;
   const int nb = (L + 15) >> 4;
-  // flipped slice of each k-step of this lane (clamped for k >= m; those operands are zeroed)
-  int fk[KS];
+  // X: a wave per row, four rows in flight, lane i gathers column f_i
+  {
+    const int fi = l0 + F[min(lane, m - 1)];
+    for (int q0 = wv; q0 < L; q0 += 4 * (kThreads / 64)) {
+      double v[4];
 #pragma unroll
-  for (int q = 0; q < KS; ++q) {
-    const int i = 4 * q + lq;
-    fk[q] = l0 + F[min(i, m - 1)];
-  }
-  // X tiles: row block rb (of L), column block jb (of m); Y tiles: row block jb (of m),
-  // column block cb.  All operands of a tile are loaded before its MFMA chain.
-  const int nx = nb * mb;
-  for (int tile = wv; tile < 2 * nx; tile += kThreads / 64) {
-    doublex4 acc = {0.0, 0.0, 0.0, 0.0};
-    double av[KS], bv[KS];
-    if (tile < nx) {
-      const int rb = tile / mb, jb = tile - rb * mb;
-      const int q = min(rb * 16 + li, L - 1);
-      const int j = jb * 16 + li;
-#pragma unroll
-      for (int s4 = 0; s4 < KS; ++s4) {
-        const int i = 4 * s4 + lq;
-        const double g = G[q * L + fk[s4]];
-        av[s4] = (i < m) ? g - (q == fk[s4] ? 1.0 : 0.0) : 0.0;
-        const double tsv = TS[min(i, kMaxK - 1) * kKP + min(j, kMaxK - 1)];
-        bv[s4] = (i < m && j < m) ? (i < j ? tsv : (i == j ? 1.0 : 0.0)) : 0.0;
+      for (int u = 0; u < 4; ++u) {
+        const int q = min(q0 + u * (kThreads / 64), L - 1);
+        v[u] = G[q * L + fi] - (q == fi ? 1.0 : 0.0);
       }
 #pragma unroll
-      for (int s4 = 0; s4 < KS; ++s4)
-        if (s4 < ks) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s4], bv[s4], acc, 0, 0, 0);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int qq = rb * 16 + 4 * r + lq;
-        if (qq < L && j < m) X[qq * kMaxK + j] = acc[r];
-      }
-    } else {
-      const int t2 = tile - nx;
-      const int jb = t2 / nb, cb = t2 - jb * nb;
-      const int jr = jb * 16 + li;
-      const int col = min(cb * 16 + li, L - 1);
-#pragma unroll
-      for (int s4 = 0; s4 < KS; ++s4) {
-        const int i = 4 * s4 + lq;
-        const double tsv = TS[min(jr, kMaxK - 1) * kKP + min(i, kMaxK - 1)];
-        av[s4] = (jr < m && i < m && i <= jr) ? tsv : 0.0;
-        const double g = G[fk[s4] * L + col];
-        bv[s4] = (i < m) ? g : 0.0;
-      }
-#pragma unroll
-      for (int s4 = 0; s4 < KS; ++s4)
-        if (s4 < ks) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s4], bv[s4], acc, 0, 0, 0);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int jj = jb * 16 + 4 * r + lq;
-        if (jj < m && cb * 16 + li < L) Y[jj * L + cb * 16 + li] = acc[r];
+      for (int u = 0; u < 4; ++u) {
+        const int q = q0 + u * (kThreads / 64);
+        if (q < L && lane < m) X[q * kMaxK + lane] = v[u];
       }
     }
   }
+  // flipped slice of each k-step of this lane (clamped for k >= m; those operands are zeroed)
+  int fk[KS];
+#pragma unroll
+  for (int q = 0; q < KS; ++q) fk[q] = l0 + F[min(4 * q + lq, m - 1)];
+  const int ny = mb * nb;   // tile = jb * nb + cb
+  auto load_b = [&](int tile, double (&bv)[KS]) {
+    const int col = min((tile % nb) * 16 + li, L - 1);
+#pragma unroll
+    for (int s4 = 0; s4 < KS; ++s4) bv[s4] = (s4 < ks) ? G[fk[s4] * L + col] : 0.0;
+  };
+  auto tile_y = [&](int tile, const double (&bv)[KS]) {
+    const int jb = tile / nb, cb = tile - jb * nb;
+    const int jr = jb * 16 + li;
+    doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s4 = 0; s4 < KS; ++s4) {
+      if (s4 < ks) {
+        const int i = 4 * s4 + lq;
+        const double a = (jr < m && i < m) ? W[min(jr, kMaxK - 1) * kKP + i] : 0.0;
+        const double b = (i < m) ? bv[s4] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int jj = jb * 16 + 4 * r + lq;
+      if (jj < m && cb * 16 + li < L) Y[jj * L + cb * 16 + li] = acc[r];
+    }
+  };
+  double b0[KS], b1[KS];
+  if (wv < ny) load_b(wv, b0);
+#pragma unroll 1
+  for (int tile = wv; tile < ny; tile += 2 * (kThreads / 64)) {
+    const int t1 = tile + kThreads / 64;
+    if (t1 < ny) load_b(t1, b1);
+    tile_y(tile, b0);
+    if (t1 >= ny) break;
+    if (t1 + kThreads / 64 < ny) load_b(t1 + kThreads / 64, b0);
+    tile_y(t1, b1);
+  }
+}
+
+// W = T S for both spins on the matrix cores: T (upper, unit diagonal) and S
+// (lower, diagonal c_j) share the m x m block TS (T[i][j] = TS[i][j] for
+// i < j, S[j][i] = TS[j][i] for i <= j); W overwrites TS once every wave has
+// read it.  Tiles (spin, 16 x 16 block) are spread over the waves.
+__device__ __forceinline__ void flush_fold(double* __restrict__ TSu, double* __restrict__ TSd, int m) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int li = lane & 15, lq = lane >> 4;
+  const int mb = (m + 15) >> 4;
+  const int ks = (m + 3) >> 2;
+  const int nt = 2 * mb * mb;                      // at most 32 tiles: 4 per wave
+  doublex4 acc[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    acc[u] = doublex4{0.0, 0.0, 0.0, 0.0};
+    const int tile = wv + u * (kThreads / 64);
+    if (tile < nt) {
+      const int sp = tile / (mb * mb), e = tile - sp * mb * mb;
+      const int ib = e / mb, jb = e - ib * mb;
+      const double* TS = sp ? TSd : TSu;
+      const int i = ib * 16 + li;          // A row (of T)
+      const int j = jb * 16 + li;          // B column (of S)
+#pragma unroll 1
+      for (int s4 = 0; s4 < ks; ++s4) {
+        const int k = 4 * s4 + lq;
+        double a = 0.0, b = 0.0;
+        if (i < m && k < m) a = (k > i) ? TS[i * kKP + k] : (k == i ? 1.0 : 0.0);
+        if (j < m && k < m && k >= j) b = TS[k * kKP + j];
+        acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[u], 0, 0, 0);
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int tile = wv + u * (kThreads / 64);
+    if (tile < nt) {
+      const int sp = tile / (mb * mb), e = tile - sp * mb * mb;
+      const int ib = e / mb, jb = e - ib * mb;
+      double* TS = sp ? TSd : TSu;
+      const int j = jb * 16 + li;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = ib * 16 + 4 * r + lq;
+        if (i < m && j < m) TS[i * kKP + j] = acc[u][r];
+      }
+    }
+  }
+  __syncthreads();
 }
 
 template <bool MIXED>
@@ -1368,16 +1675,23 @@ __device__ __forceinline__ void flush_window(const Chain& ch, int l0, int m) {
     }
   }
   __syncthreads();
+  const long long t1 = wall_clock64();
+  flush_fold(ULu, ULd, m);
 #pragma unroll 1
   for (int sp = 0; sp < 2; ++sp)
     flush_vectors(sp ? ch.Gd : ch.Gu, L, l0, m, F, sp ? ULd : ULu, X + (long long)sp * L * kMaxK,
                   Y + (long long)sp * kMaxK * L);
   __syncthreads();
+  const long long t2 = wall_clock64();
 #pragma unroll 1
   for (int sp = 0; sp < 2; ++sp)
     flush_gemm<MIXED>(sp ? ch.Gd : ch.Gu, X + (long long)sp * L * kMaxK,
                       Y + (long long)sp * kMaxK * L, L, m, un, ch.scratch_bytes - kSmall);
   __syncthreads();
+  if (threadIdx.x == 0) {
+    ch.st[ST_T_FL_VEC] += t2 - t1;
+    ch.st[ST_T_FL_GEMM] += wall_clock64() - t2;
+  }
 }
 
 template <bool MIXED>
@@ -1477,22 +1791,29 @@ __device__ __forceinline__ int sweep_window(const SweepParams& p, const Chain& c
 
 // ----------------------------------------------------------- the chain ----
 
-__device__ __forceinline__ void run_chain(const SweepParams& p, const GridDev* gd, int chain, double* ws,
-                          char* lds) {
-  Chain ch;
+// Pointers of one chain: workspace ws (G_up, G_dn, LU, U11^{-1} blocks,
+// delayed-update buffers) and the LDS layout (field, uniforms, reduction
+// slots, statistics, slice lists, then the phase-shared scratch).
+__device__ __forceinline__ void setup_chain(Chain& ch, const SweepParams& p, const GridDev* gd,
+                                            int chain, double* ws, char* lds, int lu_nb,
+                                            int scratch_bytes) {
   ch.G0 = gd->G0;
   ch.ep = gd->ep;
   ch.em = gd->em;
   ch.L = gd->L;
   ch.chain = chain;
   ch.key0 = p.seed + (uint64_t)chain;
+  ch.refQ[0] = gd->refQ[0];
+  ch.refQ[1] = gd->refQ[1];
+  ch.refH[0] = gd->refH[0];
+  ch.refH[1] = gd->refH[1];
   const int L = ch.L;
   const long long L2 = (long long)L * L;
   ch.Gu = ws;
   ch.Gd = ws + L2;
   ch.A = ws + 2 * L2;
   {
-    const long long np = (L + p.lu_nb - 1) / p.lu_nb * p.lu_nb;
+    const long long np = (L + lu_nb - 1) / lu_nb * lu_nb;
     ch.Ui = ch.A + 2 * np * np;    // after the padded L x 2L LU workspace
     ch.wbuf = ch.Ui + np * kNBMax;
   }
@@ -1502,8 +1823,17 @@ __device__ __forceinline__ void run_chain(const SweepParams& p, const GridDev* g
   ch.red = ch.u + p.Lmax;
   ch.st = reinterpret_cast<long long*>(ch.red + 64);
   ch.drift = reinterpret_cast<double*>(ch.st + NSTAT);
-  ch.scratch = reinterpret_cast<char*>(ch.red + 64) + kStatBytes;
-  ch.scratch_bytes = p.lds_scratch_bytes;
+  ch.sr = reinterpret_cast<int*>(reinterpret_cast<char*>(ch.red + 64) + kStatBytes);
+  ch.scratch = reinterpret_cast<char*>(ch.sr) + ((4 * p.Lmax + 15) & ~15);
+  ch.scratch_bytes = scratch_bytes;
+}
+
+__device__ __forceinline__ void run_chain(const SweepParams& p, const GridDev* gd, int chain, double* ws,
+                          char* lds) {
+  Chain ch;
+  setup_chain(ch, p, gd, chain, ws, lds, p.lu_nb, p.lds_scratch_bytes);
+  const int L = ch.L;
+  const long long L2 = (long long)L * L;
 
   // this chain's accumulators
   const int nb = p.n_bins;
@@ -1610,6 +1940,24 @@ __global__ void __launch_bounds__(kThreads) k_sweeps(SweepParams p) {
   }
 }
 
+// Uniform-field references of every grid: workgroup 4 g + 2 r + kind solves
+// M_r X = G0 (kind 0, X = H_r) or M_r X = 1 - G0 (kind 1, X = Q_r) with the
+// direct LU, M_r = 1 + d_r (1 - G0), d_0 = e^{lambda} - 1, d_1 = e^{-lambda} - 1
+// (the field s = +1 everywhere, spin up for r = 0 and down for r = 1).
+__global__ void __launch_bounds__(kThreads) k_reference(SweepParams p, int nb, int scratch_bytes) {
+  extern __shared__ __align__(16) char lds[];
+  const int gi = blockIdx.x >> 2, r = (blockIdx.x >> 1) & 1, kind = blockIdx.x & 1;
+  const GridDev* gd = p.grids + gi;
+  Chain ch;
+  setup_chain(ch, p, gd, 0, p.work + (long long)blockIdx.x * p.work_stride, lds, nb, scratch_bytes);
+  for (int l = threadIdx.x; l < ch.L; l += kThreads) ch.s[l] = 1;
+  if (threadIdx.x < NSTAT) ch.st[threadIdx.x] = 0;
+  __syncthreads();
+  double* out = const_cast<double*>(kind ? gd->refQ[r] : gd->refH[r]);
+  (void)dyson_solve(ch, r == 0 ? 1 : -1, out, nb, false, kind == 1);
+  if (threadIdx.x == 0 && ch.st[ST_SINGULAR]) *gd->ref_sing = 1;
+}
+
 // ---------------------------------------------------- chain reduction ----
 // Per grid: mean over all (chain, bin) sample means and standard error
 // (sample standard deviation / sqrt(number of samples)).
@@ -1675,18 +2023,20 @@ static int lu_panel(int Lmax, long long budget, int nb_max) {
   return 4;
 }
 
-int lds_bytes(int Lmax, int mode, int nb_max, int* lu_nb, int* scratch_bytes) {
-  const long long head = ((Lmax + 15) & ~15) + (long long)Lmax * 8 + 64 * 8 + kStatBytes;
+int lds_bytes(int Lmax, int mode, int nb_max, int direct, int* lu_nb, int* scratch_bytes) {
+  const long long head = ((Lmax + 15) & ~15) + (long long)Lmax * 8 + 64 * 8 + kStatBytes +
+                         ((4LL * Lmax + 15) & ~15);
   const long long budget = 150 * 1024 - head;
-  const int nb = lu_panel(Lmax, budget, nb_max > 0 ? nb_max : kNBMax);
+  const int nsys = direct ? Lmax : (Lmax / 2 > 0 ? Lmax / 2 : 1);
+  const int nb = lu_panel(nsys, budget, nb_max > 0 ? nb_max : kNBMax);
   *lu_nb = nb;
-  const long long np = (Lmax + nb - 1) / nb * nb;
+  const long long np = (nsys + nb - 1) / nb * nb;
   const long long lu = np * (nb + 2) * 8 + (long long)nb * (nb + 1) * 8 + kLuExtra;
   long long sc = lu;
   if (mode == MODE_RANK1) {
     const long long r1 = 4LL * Lmax * 8;
     sc = sc > r1 ? sc : r1;
-  } else {
+  } else if (mode == MODE_DELAYED_FP64 || mode == MODE_MIXED) {
     const long long win = kSmall + (2LL * kWin * kWP + 4LL * kWin) * 8;
     const long long ul = kSmall + 2LL * kMaxK * kKP * 8;
     // flush GEMM: at least one kCW-wide FP64 panel of Y
@@ -1695,7 +2045,19 @@ int lds_bytes(int Lmax, int mode, int nb_max, int* lu_nb, int* scratch_bytes) {
     w = w > yp ? w : yp;
     sc = sc > w ? sc : w;
   }
+  if (!direct) {
+    // reduced form: G[S,:] staged in LDS 64 columns wide where that fits, at least 16
+    const long long kr = (nsys + 7LL) & ~7LL;
+    for (int zw = 64; zw >= 16; zw >>= 1) {
+      const long long z = kr * (zw + 2) * 8;
+      if (head + (sc > z ? sc : z) <= 150 * 1024 || zw == 16) {
+        sc = sc > z ? sc : z;
+        break;
+      }
+    }
+  }
   sc = (sc + 15) & ~15LL;
+  if (!direct && head + sc > 150 * 1024) return -1;
   *scratch_bytes = (int)sc;
   return (int)(head + sc);
 }
@@ -1747,6 +2109,16 @@ hipError_t prepare_sweeps(int lds) {
 
 hipError_t launch_sweeps(const SweepParams& p, int n_wg, int lds, hipStream_t s) {
   hipLaunchKernelGGL(k_sweeps, dim3(n_wg), dim3(kThreads), lds, s, p);
+  return hipGetLastError();
+}
+
+hipError_t prepare_reference(int lds) {
+  if (lds <= 64 * 1024) return hipSuccess;
+  return hipFuncSetAttribute((const void*)k_reference, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+}
+
+hipError_t launch_reference(const SweepParams& p, int nb, int lds, int scratch, hipStream_t s) {
+  hipLaunchKernelGGL(k_reference, dim3(4 * p.n_grids), dim3(kThreads), lds, s, p, nb, scratch);
   return hipGetLastError();
 }
 

@@ -127,3 +127,22 @@ def test_heat_bath_matches_oracle(ctx, mode, k):
         got = out["chain_g"][c][0] / n
         exp = ref["bins_g"][0] / ref["bins_n"][0]
         assert np.abs(got - exp).max() < 1e-10
+
+
+@pytest.mark.parametrize("mode,k,L", [("rank1", 0, 60), ("delayed", 16, 130), ("mixed", 32, 400)])
+def test_reduced_recompute_equals_direct(ctx, mode, k, L):
+    # the block elimination against the uniform-field references and the full
+    # L x L LU give the same chain: identical flips, accumulators within 1e-10
+    import paper_0801_1222_amd as P
+    beta, U, seed = L / 10.0, 4.5, 8
+    g0 = _bath(beta, L)
+    kw = dict(n_chains=3, warmup=1, sweeps=4, mode=mode, delay_k=k, flip_cap=20000,
+              want_chain=True)
+    red = P.hfqmc_solve(ctx, g0, U, beta, beta / L, seed, **kw)
+    dirc = P.hfqmc_solve(ctx, g0, U, beta, beta / L, seed, direct=True, **kw)
+    assert red["stats"]["recompute_reduced"] == 1 and dirc["stats"]["recompute_reduced"] == 0
+    assert 0 < red["stats"]["n_reduced_rows"] <= (L // 2) * 2 * (red["stats"]["n_recomputes"] + 3)
+    for c in range(3):
+        assert np.array_equal(red["flips"][c], dirc["flips"][c])
+        assert np.abs(red["chain_g"][c] - dirc["chain_g"][c]).max() < 1e-10 * red["chain_n"][c][0]
+    assert red["stats"]["max_drift"] < (1e-3 if mode == "mixed" else 1e-10)
