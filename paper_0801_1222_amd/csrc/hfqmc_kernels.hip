@@ -157,6 +157,15 @@ typedef __attribute__((address_space(1))) double gdouble;
 typedef __attribute__((address_space(1))) const double gcdouble;
 
 constexpr int kStatBytes = 256;   // LDS statistics block: NSTAT counters + drift
+constexpr int kUW = 64;           // acceptance uniforms held in LDS at a time
+
+// Acceptance uniforms u(l, sweep) (stream 0) of slices l0 .. l0 + n - 1 into uw.
+__device__ __forceinline__ void fill_uniforms(double* uw, uint64_t key0, uint64_t grid, long long sw,
+                                              int l0, int n) {
+  if ((int)threadIdx.x < n)
+    uw[threadIdx.x] = uniform53(key0, grid, (uint64_t)(l0 + threadIdx.x), (uint64_t)sw, 0ull);
+  __syncthreads();
+}
 
 struct Chain {
   const double* G0;
@@ -173,13 +182,14 @@ struct Chain {
   double* Ui;      // U11^{-1} blocks of the LU
   double* wbuf;    // delayed-update buffers
   int8_t* s;       // field, LDS
-  double* u;       // uniforms, LDS
+  double* uw;      // LDS [kUW]: acceptance uniforms of the current block of slices
+  int grid;        // Philox key word 1
   char* scratch;   // phase-shared LDS
   int scratch_bytes;
   double* red;     // reduction scratch, LDS
   long long* st;   // per-chain statistics [NSTAT] (ST_*), LDS, written by thread 0 only
   double* drift;   // largest recompute drift so far, LDS, thread 0 only
-  int* sr;         // LDS [L]: the reduced solve's slice lists (S, then R)
+  int* sr;         // LDS [L] at the start of the scratch during a reduced solve: S, then R
   const double* refQ[2];
   const double* refH[2];
 };
@@ -743,7 +753,9 @@ __device__ __forceinline__ double dyson_solve(const Chain& ch, int sigma, double
   gdouble* __restrict__ Gs = (gdouble*)Gs_;
   gcdouble* __restrict__ G0 = (gcdouble*)ch.G0;
   double* __restrict__ A = ch.A;
-  int* sr = ch.sr;
+  int* sr = ch.sr;                                       // reduced form only
+  char* const lu_scr = ch.scratch + (reduced ? ((4 * L + 15) & ~15) : 0);
+  const int lu_scr_bytes = ch.scratch_bytes - (int)(lu_scr - ch.scratch);
   long long tc = wall_clock64();
 
   // ---- the system: all slices (direct) or S (reduced)
@@ -832,7 +844,7 @@ __device__ __forceinline__ double dyson_solve(const Chain& ch, int sigma, double
     }
   }
 
-  double* P = reinterpret_cast<double*>(ch.scratch);     // [np][ps]
+  double* P = reinterpret_cast<double*>(lu_scr);         // [np][ps]
   const int ls = NB + 1;
   double* Li = P + np * ps;                              // [NB][ls] inverted diagonal triangle
   double* redv = Li + NB * ls;                           // [kThreads/64]
@@ -1051,9 +1063,9 @@ __device__ __forceinline__ double dyson_solve(const Chain& ch, int sigma, double
       }
     }
     int zw = 64;                                        // chunk width
-    while (zw > 16 && (long long)kr * (zw + 2) * 8 > ch.scratch_bytes) zw >>= 1;
+    while (zw > 16 && (long long)kr * (zw + 2) * 8 > lu_scr_bytes) zw >>= 1;
     const int zs = zw + 2;
-    double* Zl = reinterpret_cast<double*>(ch.scratch);
+    double* Zl = reinterpret_cast<double*>(lu_scr);
     const int li = lane & 15, lq = lane >> 4;
     const int nrb = (nR + 15) >> 4;
     for (int c0 = 0; c0 < L; c0 += zw) {
@@ -1278,7 +1290,11 @@ __device__ __forceinline__ int sweep_rank1(const SweepParams& p, const Chain& ch
   for (int l = l_begin; l < L; ++l) {
     const long long dl = (long long)l * L + l;
     const int sl = ch.s[l];
-    const Flip f = propose(ch.Gu[dl], ch.Gd[dl], sl, io.gp, io.gm, ch.u[l], io.rlog, io.rlen,
+    if (l == l_begin || (l & (kUW - 1)) == 0) {
+      const int c0 = l & ~(kUW - 1);
+      fill_uniforms(ch.uw, ch.key0, (uint64_t)ch.grid, sw, c0, min(kUW, L - c0));
+    }
+    const Flip f = propose(ch.Gu[dl], ch.Gd[dl], sl, io.gp, io.gm, ch.uw[l & (kUW - 1)], io.rlog, io.rlen,
                            sw * L + l, k, ch.st, io.hb);
     if (!f.accept) continue;
     log_flip(io, ch.st, sw * L + l);
@@ -1343,25 +1359,30 @@ __device__ __forceinline__ int sweep_rank1(const SweepParams& p, const Chain& ch
 
 // -------------------------------------------- windowed delayed update ----
 //
-// The sweep visits l = l0, l0+1, ... inside a window of at most kWin
-// consecutive slices.  Deciding and updating inside the window only needs
-// the kWin x kWin diagonal blocks of G_up and G_dn, which live in LDS and get
-// the exact rank-1 updates of each accepted flip.  The window closes after
-// delay_k accepted flips (or at the recompute point, or the sweep end); the
-// m accepted flips are then applied to the full matrices as one rank-m update
-//   G <- G + X Y,   X = [x_1..x_m] (L x m),  Y = [y_1..y_m]^T (m x L),
-// the delayed-update form of m successive Sherman-Morrison steps.  Their full
-// vectors follow from the untouched G and the in-window values:
-//   x_j = G(:, f_j) - e_{f_j} + sum_{i<j} x_i y_i(f_j)
-//   y_j = c_j (G(f_j, :) + sum_{i<j} x_i(f_j) y_i),  c_j = gamma_j / R_j.
-// The rank-m product runs in FP64 (MODE_DELAYED_FP64) or with FP32 inputs and
-// FP32 accumulation on the matrix cores (MODE_MIXED); ratios, decisions and
-// the in-window updates are FP64 in both.
+// The sweep visits l = l0, l0+1, ... in windows of at most kWin consecutive
+// slices.  Deciding and updating inside a window only needs the kWin x kWin
+// diagonal blocks of G_up and G_dn, which live in LDS and get the exact
+// rank-1 updates of each accepted flip.  Accepted flips stay pending across
+// windows until delay_k of them are pending, a recompute is due or the sweep
+// ends; then the m pending flips are applied to the full matrices as one
+// rank-m update, the delayed-update form of m successive Sherman-Morrison
+// steps.  With f_i the flipped slices, c_i = gamma_i / R_i, C0 = G(:,F) - I(:,F)
+// and R0 = G(F,:) of the matrix before the first pending flip,
+//   x_j = G(:, f_j) - e_{f_j} + sum_{i<j} x_i y_i(f_j)     ->  X = C0 T, T = (I - U)^{-1}
+//   y_j = c_j (G(f_j, :) + sum_{i<j} x_i(f_j) y_i)        ->  Y = S R0, S = (I - Dc Lw)^{-1} Dc
+// with U(i,j) = y_i(f_j) and Lw(j,i) = x_i(f_j) (i < j), and G += X Y = C0 (T S) R0.
+// A window opened while flips are pending starts from G(B,B) + X(B,:) Y(:,B);
+// X(B,:) and Y(:,B) are also the in-window parts of the pending flips' vectors,
+// from which the coefficients U, Lw of the window's new flips are read.  T and
+// S are built in place over U and Lw, one column / row per flip, as flips are
+// added.  The rank-m product runs in FP64 (MODE_DELAYED_FP64) or with FP32
+// inputs and FP32 accumulation on the matrix cores (MODE_MIXED); ratios,
+// decisions, window blocks and in-window updates are FP64 in both.
 
 constexpr int kWin = 64;        // slices per window (diagonal block edge)
 constexpr int kWP = kWin + 1;   // LDS row stride of the window blocks
 constexpr int kKP = kMaxK + 1;  // LDS row stride of the m x m coefficient blocks
-constexpr int kSmall = 1536;    // bytes for flip positions and coefficients
+constexpr int kSmall = 1536;    // bytes for flip positions (global slices) and coefficients
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 // G += X Y for one spin.  X: [L][kMaxK] row-major, Y: [kMaxK][L] row-major,
@@ -1403,9 +1424,21 @@ __device__ __forceinline__ void flush_gemm(double* __restrict__ G, const double*
   for (int c0 = 0; c0 < L; c0 += pw) {
     const int w = min(pw, L - c0);
     __syncthreads();
-    for (int idx = t; idx < rows * pw; idx += kThreads) {
-      const int kk = idx / pw, c = idx - kk * pw;
-      Yl[c * kYK + kk] = (kk < m && c < w) ? (T)Y[kk * L + c0 + c] : (T)0;
+    // a wave per Y row, four rows in flight; lanes along the panel
+    for (int k0 = wv; k0 < rows; k0 += 4 * (kThreads / 64)) {
+      for (int c = lane; c < pw; c += 64) {
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int kk = k0 + u * (kThreads / 64);
+          v[u] = (kk < m && c < w) ? Y[kk * L + c0 + c] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int kk = k0 + u * (kThreads / 64);
+          if (kk < rows) Yl[c * kYK + kk] = (T)v[u];
+        }
+      }
     }
     __syncthreads();
     const int nchunk = (w + kCW - 1) / kCW;
@@ -1426,19 +1459,10 @@ __device__ __forceinline__ void flush_gemm(double* __restrict__ G, const double*
         }
       }
     };
-    double gnxt[kCT][4];
-    load_g(lo, gnxt);
     T a[KS];
     int cur_strip = -1;
-#pragma unroll 1
-    for (int it = lo; it < hi; ++it) {
+    auto process = [&](int it, const double (&gcur)[kCT][4]) {
       const int st = it / nchunk, chk = it - st * nchunk;
-      double gcur[kCT][4];
-#pragma unroll
-      for (int ct = 0; ct < kCT; ++ct)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) gcur[ct][r] = gnxt[ct][r];
-      if (it + 1 < hi) load_g(it + 1, gnxt);
       if (st != cur_strip) {
         cur_strip = st;
         const int arow = min(16 * st + li, L - 1);
@@ -1477,6 +1501,22 @@ __device__ __forceinline__ void flush_gemm(double* __restrict__ G, const double*
           if (cok && row < L) G[row * L + col] = gcur[ct][r] + (double)acc[ct][r];
         }
       }
+    };
+    // three G buffers in turn: the loads of the next two items are in flight
+    // while one item runs on the matrix cores
+    double g0[kCT][4], g1[kCT][4], g2[kCT][4];
+    load_g(lo, g0);
+    if (lo + 1 < hi) load_g(lo + 1, g1);
+#pragma unroll 1
+    for (int it = lo; it < hi; it += 3) {
+      if (it + 2 < hi) load_g(it + 2, g2);
+      process(it, g0);
+      if (it + 1 >= hi) break;
+      if (it + 3 < hi) load_g(it + 3, g0);
+      process(it + 1, g1);
+      if (it + 2 >= hi) break;
+      if (it + 4 < hi) load_g(it + 4, g1);
+      process(it + 2, g2);
     }
   }
 }
@@ -1606,50 +1646,55 @@ __device__ __forceinline__ void flush_fold(double* __restrict__ TSu, double* __r
   __syncthreads();
 }
 
-template <bool MIXED>
-__device__ __forceinline__ void flush_window(const Chain& ch, int l0, int m) {
-  const int L = ch.L;
-  const int t = threadIdx.x;
-  const int lane = t & 63, wv = t >> 6;
-  const int* F = reinterpret_cast<const int*>(ch.scratch);
-  const double* cU = reinterpret_cast<const double*>(ch.scratch + 256);
-  const double* cD = cU + kMaxK;
-  char* un = ch.scratch + kSmall;
-  double* ULu = reinterpret_cast<double*>(un);
-  double* ULd = ULu + kMaxK * kKP;
-  const double* Xrec = ch.wbuf;                       // [2][kMaxK][kWin]
-  const double* Yrec = Xrec + 2 * kMaxK * kWin;       // [2][kMaxK][kWin]
-  double* X = ch.wbuf + 4 * kMaxK * kWin;             // [2][L][kMaxK]
-  double* Y = X + 2LL * L * kMaxK;                    // [2][kMaxK][L]
-  // in-window coefficients: U(i,j) = y_i(f_j) (i < j) above, x_j(f_i) (i > j) below
-  for (int idx = t; idx < m * m; idx += kThreads) {
-    const int i = idx / m, j = idx - i * m;
-    double vu = 0.0, vd = 0.0;
-    if (i < j) {
-      vu = Yrec[(0 * kMaxK + i) * kWin + F[j]];
-      vd = Yrec[(1 * kMaxK + i) * kWin + F[j]];
-    } else if (i > j) {
-      vu = Xrec[(0 * kMaxK + j) * kWin + F[i]];
-      vd = Xrec[(1 * kMaxK + j) * kWin + F[i]];
-    }
-    ULu[i * kKP + j] = vu;
-    ULd[i * kKP + j] = vd;
-  }
-  __syncthreads();
-  // In place, one wave per triangle:
-  //   T = (I - U)^{-1}: lane r builds row r, T[r][j] = sum_{r <= i < j} T[r][i] U[i][j] (T[r][r] = 1);
-  //   S = (I - Dc Lw)^{-1} Dc: lane c builds column c, S[c][c] = c_c,
-  //   S[j][c] = c_j sum_{c <= i < j} Lw[j][i] S[i][c].
-  // Each step j reads only entries the wave has not yet overwritten at that step.
+// LDS of the window phase (after kSmall): window blocks Wu, Wd [kWin][kWP],
+// the last flip's in-window vectors, then the coefficient blocks ULu, ULd
+// [kMaxK][kKP] (U above, Lw below the diagonal; the first m_inv columns and
+// rows already turned into T and S).
+struct WinLds {
+  int* F;            // [kMaxK] flipped slices (global)
+  double* cU;        // [kMaxK] gamma / R, spin up
+  double* cD;
+  double* Wu;
+  double* Wd;
+  double* xu;
+  double* yu;
+  double* xd;
+  double* yd;
+  double* ULu;
+  double* ULd;
+};
+
+__device__ __forceinline__ WinLds win_lds(const Chain& ch) {
+  WinLds w;
+  w.F = reinterpret_cast<int*>(ch.scratch);
+  w.cU = reinterpret_cast<double*>(ch.scratch + 256);
+  w.cD = w.cU + kMaxK;
+  w.Wu = reinterpret_cast<double*>(ch.scratch + kSmall);
+  w.Wd = w.Wu + kWin * kWP;
+  w.xu = w.Wd + kWin * kWP;
+  w.yu = w.xu + kWin;
+  w.xd = w.yu + kWin;
+  w.yd = w.xd + kWin;
+  w.ULu = w.yd + kWin;
+  w.ULd = w.ULu + kMaxK * kKP;
+  return w;
+}
+
+// Columns / rows m_inv .. m-1 of U and Lw into T and S, in place, one wave per
+// triangle and spin (waves 0, 1: T; waves 2, 3: S):
+//   T[r][j] = U[r][j] + sum_{r < i < j} T[r][i] U[i][j]      (T[r][r] = 1)
+//   S[c][c] = c_c,  S[j][c] = c_j sum_{c <= i < j} Lw[j][i] S[i][c]
+// All lanes step through j together, so every read of column / row j happens
+// before any lane overwrites it at the end of the same step.
+__device__ __forceinline__ void invert_ts(const WinLds& w, int m_inv, int m) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (wv < 4 && lane < m) {
-    double* UL = (wv & 1) ? ULd : ULu;
-    const double* cc = (wv & 1) ? cD : cU;
-    // all lanes step through j together, so every read of column / row j
-    // happens before any lane overwrites it at the end of the same step
+    double* UL = (wv & 1) ? w.ULd : w.ULu;
+    const double* cc = (wv & 1) ? w.cD : w.cU;
     if (wv < 2) {
       const int r = lane;
 #pragma unroll 1
-      for (int j = 1; j < m; ++j) {
+      for (int j = max(m_inv, 1); j < m; ++j) {
         if (r < j) {
           double acc = UL[r * kKP + j];
 #pragma unroll 1
@@ -1660,10 +1705,10 @@ __device__ __forceinline__ void flush_window(const Chain& ch, int l0, int m) {
       }
     } else {
       const int c = lane;
-      UL[c * kKP + c] = cc[c];
+      if (c >= m_inv) UL[c * kKP + c] = cc[c];
       wave_sync();
 #pragma unroll 1
-      for (int j = 1; j < m; ++j) {
+      for (int j = max(m_inv, 1); j < m; ++j) {
         if (c < j) {
           double acc = 0.0;
 #pragma unroll 1
@@ -1675,14 +1720,140 @@ __device__ __forceinline__ void flush_window(const Chain& ch, int l0, int m) {
     }
   }
   __syncthreads();
+}
+
+// Opening a window at l0 (b slices) with m flips pending (T, S complete):
+// the pending flips' in-window vector parts
+//   Xrec[i][r] = X(l0 + r, i) = sum_{i'} C0(l0 + r, i') T[i'][i],
+//   Yrec[i][c] = Y(i, l0 + c) = sum_{i'} S[i][i'] G(f_i', l0 + c),
+// then the window blocks W = G(B,B) + X(B,:) Y(:,B), all FP64 on the matrix cores.
+__device__ __forceinline__ void window_apply(const Chain& ch, const WinLds& w, int l0, int b, int m) {
+  const int L = ch.L;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int li = lane & 15, lq = lane >> 4;
+  const int ks = (m + 3) >> 2;
+  const int mb = (m + 15) >> 4;
+  double* Xrec = ch.wbuf;                       // [2][kMaxK][kWin]
+  double* Yrec = Xrec + 2 * kMaxK * kWin;       // [2][kMaxK][kWin]
+  // (1) X tiles (4 row blocks x mb) and Y tiles (mb x 4) of both spins
+  const int nx = 4 * mb, ntile = 2 * (2 * nx);
+  for (int tile = wv; tile < ntile; tile += kThreads / 64) {
+    const int sp = tile >= 2 * nx;
+    const int e = tile - sp * 2 * nx;
+    const double* G = sp ? ch.Gd : ch.Gu;
+    const double* TS = sp ? w.ULd : w.ULu;
+    doublex4 acc = {0.0, 0.0, 0.0, 0.0};
+    if (e < nx) {
+      // X(B, :): rows rb (window), columns jb (flips); A = C0 (gathered), B = T
+      const int rb = e / mb, jb = e - rb * mb;
+      const int q = l0 + min(rb * 16 + li, b - 1);
+      const int j = jb * 16 + li;
+#pragma unroll 1
+      for (int s4 = 0; s4 < ks; ++s4) {
+        const int i = 4 * s4 + lq;
+        const int fi = w.F[min(i, m - 1)];
+        const double g = G[q * L + fi];
+        const double a = (i < m) ? g - (q == fi ? 1.0 : 0.0) : 0.0;
+        const double tv = TS[min(i, kMaxK - 1) * kKP + min(j, kMaxK - 1)];
+        const double bv = (i < m && j < m) ? (i < j ? tv : (i == j ? 1.0 : 0.0)) : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int rr = rb * 16 + 4 * r + lq;
+        if (rr < b && j < m) Xrec[(sp * kMaxK + j) * kWin + rr] = acc[r];
+      }
+    } else {
+      // Y(:, B): rows jb (flips), columns cb (window); A = S, B = G(F, B)
+      const int e2 = e - nx;
+      const int jb = e2 / 4, cb = e2 - jb * 4;
+      const int jr = jb * 16 + li;
+      const int col = l0 + min(cb * 16 + li, b - 1);
+#pragma unroll 1
+      for (int s4 = 0; s4 < ks; ++s4) {
+        const int i = 4 * s4 + lq;
+        const double sv = TS[min(jr, kMaxK - 1) * kKP + min(i, kMaxK - 1)];
+        const double a = (jr < m && i < m && i <= jr) ? sv : 0.0;
+        const double g = G[w.F[min(i, m - 1)] * L + col];
+        const double bv = (i < m) ? g : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int jj = jb * 16 + 4 * r + lq;
+        const int cc = cb * 16 + li;
+        if (jj < m && cc < b) Yrec[(sp * kMaxK + jj) * kWin + cc] = acc[r];
+      }
+    }
+  }
+  __syncthreads();
+  // (2) W = G(B,B) + X(B,:) Y(:,B): 4 x 4 tiles per spin, 32 tiles over the waves
+  for (int tile = wv; tile < 32; tile += kThreads / 64) {
+    const int sp = tile >> 4, e = tile & 15;
+    const int rb = e >> 2, cb = e & 3;
+    const double* G = sp ? ch.Gd : ch.Gu;
+    double* W = sp ? w.Wd : w.Wu;
+    const int col = cb * 16 + li;
+    doublex4 acc;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int rr = rb * 16 + 4 * r + lq;
+      acc[r] = (rr < b && col < b) ? G[(l0 + rr) * L + l0 + col] : 0.0;
+    }
+    const int ar = rb * 16 + li;
+#pragma unroll 1
+    for (int s4 = 0; s4 < ks; ++s4) {
+      const int i = 4 * s4 + lq;
+      const int ic = min(i, kMaxK - 1);
+      const double a = (i < m && ar < b) ? Xrec[(sp * kMaxK + ic) * kWin + min(ar, kWin - 1)] : 0.0;
+      const double bv = (i < m && col < b) ? Yrec[(sp * kMaxK + ic) * kWin + min(col, kWin - 1)] : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int rr = rb * 16 + 4 * r + lq;
+      if (rr < b && col < b) W[rr * kWP + col] = acc[r];
+    }
+  }
+  __syncthreads();
+}
+
+// Coefficients of the window's new flips j = m0 .. m-1 (window at l0):
+// U(i, j) = y_i(f_j), Lw(j, i) = x_i(f_j) for i < j, from the window's records.
+__device__ __forceinline__ void capture_coefficients(const Chain& ch, const WinLds& w, int l0,
+                                                     int m0, int m) {
+  const double* Xrec = ch.wbuf;
+  const double* Yrec = Xrec + 2 * kMaxK * kWin;
+  const int n_new = m - m0;
+  for (int idx = threadIdx.x; idx < 2 * n_new * m; idx += kThreads) {
+    const int sp = idx >= n_new * m;
+    const int e = idx - sp * n_new * m;
+    const int j = m0 + e / m, i = e % m;
+    if (i < j) {
+      const int pj = w.F[j] - l0;
+      double* UL = sp ? w.ULd : w.ULu;
+      UL[i * kKP + j] = Yrec[(sp * kMaxK + i) * kWin + pj];
+      UL[j * kKP + i] = Xrec[(sp * kMaxK + i) * kWin + pj];
+    }
+  }
+  __syncthreads();
+}
+
+// Applies the m pending flips (T, S complete up to m) to G_up and G_dn.
+template <bool MIXED>
+__device__ __forceinline__ void flush_pending(const Chain& ch, const WinLds& w, int m) {
+  const int L = ch.L;
+  double* X = ch.wbuf + 4 * kMaxK * kWin;             // [2][L][kMaxK]
+  double* Y = X + 2LL * L * kMaxK;                    // [2][kMaxK][L]
   const long long t1 = wall_clock64();
-  flush_fold(ULu, ULd, m);
+  flush_fold(w.ULu, w.ULd, m);
 #pragma unroll 1
   for (int sp = 0; sp < 2; ++sp)
-    flush_vectors(sp ? ch.Gd : ch.Gu, L, l0, m, F, sp ? ULd : ULu, X + (long long)sp * L * kMaxK,
+    flush_vectors(sp ? ch.Gd : ch.Gu, L, 0, m, w.F, sp ? w.ULd : w.ULu, X + (long long)sp * L * kMaxK,
                   Y + (long long)sp * kMaxK * L);
   __syncthreads();
   const long long t2 = wall_clock64();
+  char* un = ch.scratch + kSmall;
 #pragma unroll 1
   for (int sp = 0; sp < 2; ++sp)
     flush_gemm<MIXED>(sp ? ch.Gd : ch.Gu, X + (long long)sp * L * kMaxK,
@@ -1699,72 +1870,74 @@ __device__ __forceinline__ int sweep_window(const SweepParams& p, const Chain& c
                                             Counters& k, const ChainIO& io, int l_begin) {
   const int L = ch.L;
   const int t = threadIdx.x;
-  int* F = reinterpret_cast<int*>(ch.scratch);
-  double* cU = reinterpret_cast<double*>(ch.scratch + 256);
-  double* cD = cU + kMaxK;
-  char* un = ch.scratch + kSmall;
-  double* Wu = reinterpret_cast<double*>(un);
-  double* Wd = Wu + kWin * kWP;
-  double* xu = Wd + kWin * kWP;
-  double* yu = xu + kWin;
-  double* xd = yu + kWin;
-  double* yd = xd + kWin;
+  const WinLds w = win_lds(ch);
   double* Xrec = ch.wbuf;
   double* Yrec = Xrec + 2 * kMaxK * kWin;
+  int m = 0, m_inv = 0;          // pending flips; those already in T and S
   int l0 = l_begin;
   while (l0 < L) {
     const int b = min(kWin, L - l0);
-    for (int idx = t; idx < kWin * kWin; idx += kThreads) {
-      const int q = idx >> 6, r = idx & 63;
-      if (q < b && r < b) {
-        const long long o = (long long)(l0 + q) * L + l0 + r;
-        Wu[q * kWP + r] = ch.Gu[o];
-        Wd[q * kWP + r] = ch.Gd[o];
+    fill_uniforms(ch.uw, ch.key0, (uint64_t)ch.grid, sw, l0, b);
+    if (m > 0) {
+      const long long t0 = wall_clock64();
+      invert_ts(w, m_inv, m);
+      m_inv = m;
+      window_apply(ch, w, l0, b, m);
+      if (t == 0) ch.st[ST_T_FLUSH] += wall_clock64() - t0;
+    } else {
+      for (int idx = t; idx < kWin * kWin; idx += kThreads) {
+        const int q = idx >> 6, r = idx & 63;
+        if (q < b && r < b) {
+          const long long o = (long long)(l0 + q) * L + l0 + r;
+          w.Wu[q * kWP + r] = ch.Gu[o];
+          w.Wd[q * kWP + r] = ch.Gd[o];
+        }
       }
+      __syncthreads();
     }
-    __syncthreads();
-    int m = 0, pos = 0;
+    const int m0 = m;
+    int pos = 0;
     bool close = false;
     while (pos < b && !close) {
       const int l = l0 + pos;
       const int sl = ch.s[l];
-      const Flip f = propose(Wu[pos * kWP + pos], Wd[pos * kWP + pos], sl, io.gp, io.gm, ch.u[l],
-                             io.rlog, io.rlen, sw * L + l, k, ch.st, io.hb);
+      const Flip f = propose(w.Wu[pos * kWP + pos], w.Wd[pos * kWP + pos], sl, io.gp, io.gm,
+                             ch.uw[pos], io.rlog, io.rlen, sw * L + l, k, ch.st, io.hb);
       if (f.accept) {
         log_flip(io, ch.st, sw * L + l);
         const double cu = f.g_up / f.r_up, cd = f.g_dn / f.r_dn;
-        // in-window parts of x = G(:,l) - e_l and y = c G(l,:), kept for the flush
+        // in-window parts of x = G(:,l) - e_l and y = c G(l,:)
         if (t < b) {
-          const double v = Wu[t * kWP + pos] - (t == pos ? 1.0 : 0.0);
-          xu[t] = v;
+          const double v = w.Wu[t * kWP + pos] - (t == pos ? 1.0 : 0.0);
+          w.xu[t] = v;
           Xrec[(0 * kMaxK + m) * kWin + t] = v;
         } else if (t >= 64 && t < 64 + b) {
           const int r = t - 64;
-          const double v = mul_nc(cu, Wu[pos * kWP + r]);
-          yu[r] = v;
+          const double v = mul_nc(cu, w.Wu[pos * kWP + r]);
+          w.yu[r] = v;
           Yrec[(0 * kMaxK + m) * kWin + r] = v;
         } else if (t >= 128 && t < 128 + b) {
           const int q = t - 128;
-          const double v = Wd[q * kWP + pos] - (q == pos ? 1.0 : 0.0);
-          xd[q] = v;
+          const double v = w.Wd[q * kWP + pos] - (q == pos ? 1.0 : 0.0);
+          w.xd[q] = v;
           Xrec[(1 * kMaxK + m) * kWin + q] = v;
         } else if (t >= 192 && t < 192 + b) {
           const int r = t - 192;
-          const double v = mul_nc(cd, Wd[pos * kWP + r]);
-          yd[r] = v;
+          const double v = mul_nc(cd, w.Wd[pos * kWP + r]);
+          w.yd[r] = v;
           Yrec[(1 * kMaxK + m) * kWin + r] = v;
         }
         if (t == 0) {
-          F[m] = pos;
-          cU[m] = cu;
-          cD[m] = cd;
+          w.F[m] = l;
+          w.cU[m] = cu;
+          w.cD[m] = cd;
         }
         __syncthreads();
         for (int idx = t; idx < kWin * kWin; idx += kThreads) {
           const int q = idx >> 6, r = idx & 63;
           if (q < b && r < b) {
-            Wu[q * kWP + r] = axpy_nc(Wu[q * kWP + r], xu[q], yu[r]);
-            Wd[q * kWP + r] = axpy_nc(Wd[q * kWP + r], xd[q], yd[r]);
+            w.Wu[q * kWP + r] = axpy_nc(w.Wu[q * kWP + r], w.xu[q], w.yu[r]);
+            w.Wd[q * kWP + r] = axpy_nc(w.Wd[q * kWP + r], w.xd[q], w.yd[r]);
           }
         }
         if (t == 0) ch.s[l] = (int8_t)(-sl);
@@ -1775,15 +1948,24 @@ __device__ __forceinline__ int sweep_window(const SweepParams& p, const Chain& c
       }
       ++pos;
     }
-    if (m > 0) {
+    l0 += pos;
+    if (m > m0) {
       const long long t0 = wall_clock64();
-      flush_window<MIXED>(ch, l0, m);
-      if (threadIdx.x == 0) {
+      capture_coefficients(ch, w, l0 - pos, m0, m);
+      if (t == 0) ch.st[ST_T_FLUSH] += wall_clock64() - t0;
+    }
+    // flush at delay_k pending, before a recompute and at the sweep end
+    if (m > 0 && (close || l0 >= L)) {
+      const long long t0 = wall_clock64();
+      invert_ts(w, m_inv, m);
+      flush_pending<MIXED>(ch, w, m);
+      if (t == 0) {
         ch.st[ST_T_FLUSH] += wall_clock64() - t0;
         ch.st[ST_FLUSHES] += 1;
       }
+      m = 0;
+      m_inv = 0;
     }
-    l0 += pos;
     if (k.acc_since == p.n_rec) return l0;
   }
   return L;
@@ -1817,14 +1999,15 @@ __device__ __forceinline__ void setup_chain(Chain& ch, const SweepParams& p, con
     ch.Ui = ch.A + 2 * np * np;    // after the padded L x 2L LU workspace
     ch.wbuf = ch.Ui + np * kNBMax;
   }
+  ch.grid = gd->grid_id;
   ch.s = reinterpret_cast<int8_t*>(lds);
   const int s_bytes = (p.Lmax + 15) & ~15;
-  ch.u = reinterpret_cast<double*>(lds + s_bytes);
-  ch.red = ch.u + p.Lmax;
+  ch.uw = reinterpret_cast<double*>(lds + s_bytes);
+  ch.red = ch.uw + kUW;
   ch.st = reinterpret_cast<long long*>(ch.red + 64);
   ch.drift = reinterpret_cast<double*>(ch.st + NSTAT);
-  ch.sr = reinterpret_cast<int*>(reinterpret_cast<char*>(ch.red + 64) + kStatBytes);
-  ch.scratch = reinterpret_cast<char*>(ch.sr) + ((4 * p.Lmax + 15) & ~15);
+  ch.scratch = reinterpret_cast<char*>(ch.red + 64) + kStatBytes;
+  ch.sr = reinterpret_cast<int*>(ch.scratch);
   ch.scratch_bytes = scratch_bytes;
 }
 
@@ -1887,11 +2070,6 @@ __device__ __forceinline__ void run_chain(const SweepParams& p, const GridDev* g
       l = 0;
     }
     if (sw >= total) break;
-    if (l == 0) {
-      for (int q = threadIdx.x; q < L; q += kThreads)
-        ch.u[q] = uniform53(ch.key0, (uint64_t)gd->grid_id, (uint64_t)q, (uint64_t)sw, 0ull);
-      __syncthreads();
-    }
     const long long t0 = wall_clock64();
     const long long f0 = threadIdx.x == 0 ? ch.st[ST_T_FLUSH] : 0;
     int nl;
@@ -2024,21 +2202,21 @@ static int lu_panel(int Lmax, long long budget, int nb_max) {
 }
 
 int lds_bytes(int Lmax, int mode, int nb_max, int direct, int* lu_nb, int* scratch_bytes) {
-  const long long head = ((Lmax + 15) & ~15) + (long long)Lmax * 8 + 64 * 8 + kStatBytes +
-                         ((4LL * Lmax + 15) & ~15);
-  const long long budget = 150 * 1024 - head;
+  const long long head = ((Lmax + 15) & ~15) + kUW * 8 + 64 * 8 + kStatBytes;
+  const long long srb = direct ? 0 : ((4LL * Lmax + 15) & ~15);   // reduced form's slice lists
+  const long long budget = 150 * 1024 - head - srb;
   const int nsys = direct ? Lmax : (Lmax / 2 > 0 ? Lmax / 2 : 1);
   const int nb = lu_panel(nsys, budget, nb_max > 0 ? nb_max : kNBMax);
   *lu_nb = nb;
   const long long np = (nsys + nb - 1) / nb * nb;
-  const long long lu = np * (nb + 2) * 8 + (long long)nb * (nb + 1) * 8 + kLuExtra;
+  const long long lu = srb + np * (nb + 2) * 8 + (long long)nb * (nb + 1) * 8 + kLuExtra;
   long long sc = lu;
   if (mode == MODE_RANK1) {
     const long long r1 = 4LL * Lmax * 8;
     sc = sc > r1 ? sc : r1;
   } else if (mode == MODE_DELAYED_FP64 || mode == MODE_MIXED) {
-    const long long win = kSmall + (2LL * kWin * kWP + 4LL * kWin) * 8;
-    const long long ul = kSmall + 2LL * kMaxK * kKP * 8;
+    const long long win = kSmall + (2LL * kWin * kWP + 4LL * kWin + 2LL * kMaxK * kKP) * 8;
+    const long long ul = win;
     // flush GEMM: at least one kCW-wide FP64 panel of Y
     const long long yp = kSmall + 1LL * kCW * kYK * 8;
     long long w = win > ul ? win : ul;
@@ -2049,7 +2227,7 @@ int lds_bytes(int Lmax, int mode, int nb_max, int direct, int* lu_nb, int* scrat
     // reduced form: G[S,:] staged in LDS 64 columns wide where that fits, at least 16
     const long long kr = (nsys + 7LL) & ~7LL;
     for (int zw = 64; zw >= 16; zw >>= 1) {
-      const long long z = kr * (zw + 2) * 8;
+      const long long z = srb + kr * (zw + 2) * 8;
       if (head + (sc > z ? sc : z) <= 150 * 1024 || zw == 16) {
         sc = sc > z ? sc : z;
         break;
