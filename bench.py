@@ -72,6 +72,22 @@ def algorithmic_work(L, st, n_chains, measured_sweeps, mode):
     return bytes_, f64, f32
 
 
+def executed_recompute_flops(L, st, n_chains):
+    """FP64 flops the recompute actually executes.
+
+    Reduced form (the default): per spin solve with |S| = s rows, an LU of the
+    s x s system (2/3 s^3), its forward and back substitution on L right-hand
+    sides (2 s^2 L) and the GEMM for the other L - s rows (2 (L - s) s L);
+    |S| is the mean over all solves (stats n_reduced_rows).  Full form:
+    (8/3) L^3 per spin.
+    """
+    n_solves = 2.0 * (st["n_recomputes"] + n_chains)
+    if not st.get("recompute_reduced"):
+        return n_solves * (8.0 / 3.0) * float(L) ** 3
+    s = st["n_reduced_rows"] / max(n_solves, 1.0)
+    return n_solves * ((2.0 / 3.0) * s ** 3 + 2.0 * s * s * L + 2.0 * (L - s) * s * L)
+
+
 def composite_bound_s(L, st, n_chains, measured_sweeps, mode):
     """Sum over phases of max(bytes / HBM peak, flops / matrix-core peak) (phases not overlapped)."""
     L2 = float(L) * L
@@ -106,7 +122,20 @@ def roofline(L, st, n_chains, measured_sweeps, mode, t_kernel):
     main["lower_bound_s"] = {"hbm": t_hbm, "mfma_fp64_equiv": t_mfma}
     main["algorithmic"] = {"bytes": by, "fp64_flops": f64, "fp32_flops": f32}
     main["composite_frac"] = composite_bound_s(L, st, n_chains, measured_sweeps, mode) / t_kernel
+    # the recompute's algorithmic flops above are those of the full (8/3) L^3 solve per
+    # spin; the reduced form computes the same G with fewer
+    ex = executed_recompute_flops(L, st, n_chains)
+    main["executed"] = {"recompute_fp64_flops": ex,
+                        "mean_reduced_rows": st["n_reduced_rows"]
+                        / max(2.0 * (st["n_recomputes"] + n_chains), 1.0),
+                        "fp64_equiv_tflops": (ex + f32 * FP64_PEAK_TFLOPS / FP32_PEAK_TFLOPS
+                                              + (f64 - n_rec_flops(L, st, n_chains)))
+                        / t_kernel / 1e12}
     return main
+
+
+def n_rec_flops(L, st, n_chains):
+    return (st["n_recomputes"] + n_chains) * 2.0 * (8.0 / 3.0) * float(L) ** 3
 
 
 def kernel_source_hash():
@@ -187,7 +216,7 @@ def main():
     ap.add_argument("--rank1-sweeps", type=int, default=40,
                     help="sweeps per chain of the plain FP64 rank-1 comparison solve (0 = skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sweeps", type=int, default=12)
+    ap.add_argument("--cpu-sweeps", type=int, default=100)
     ap.add_argument("--calib-copy", action="store_true")
     args = ap.parse_args()
 
