@@ -134,6 +134,50 @@ def roofline(L, st, n_chains, measured_sweeps, mode, t_kernel):
     return main
 
 
+def add_measured_peaks(entry, peaks):
+    """Fraction of the achievable peak the library's probe kernels measured."""
+    if not peaks:
+        return
+    m = (max(peaks["hbm_copy_gbs"], peaks["hbm_read_gbs"]) if entry["bound"] == "hbm"
+         else peaks["fp64_mfma_tflops"])
+    entry["measured_peak"] = m
+    entry["frac_of_measured_peak"] = entry["achieved"] / m if m > 0 else None
+
+
+def batched_grids(P, ctx, name, beta, U, dtaus, n_chains, warmup, sweeps, mode, t=1.0):
+    """One persistent launch over several grids; per-grid work and the whole-launch rate.
+
+    Each grid's chain-seconds come from the kernel's own phase clocks; its
+    L=400-equivalent chain-sweeps scale by (L/400)^3, the rank-1 cost law.
+    """
+    Ls = [int(round(beta / d)) for d in dtaus]
+    bath = P.bethe_semicircle_bath(beta, t, 20000)
+    g0s = [P.bath_to_tau(bath, t * t, beta, L) for L in Ls]
+    kw = dict(n_chains=n_chains, warmup=warmup, sweeps=sweeps, mode=mode)
+    P.hfqmc_solve_grids(ctx, Ls, g0s, U, beta, 0, **kw)           # autotune, capture
+    out = P.hfqmc_solve_grids(ctx, Ls, g0s, U, beta, 0, **kw)
+    st = out["stats"]
+    tk = st[0]["seconds_kernel"]
+    per = []
+    eq = 0.0
+    flips = 0
+    for L, s_ in zip(Ls, st):
+        cs = n_chains * (warmup + sweeps)
+        busy = sum(s_[k] for k in ("chain_s_sweep", "chain_s_flush", "chain_s_recompute",
+                                   "chain_s_measure"))
+        per.append(dict(L=L, chain_sweeps=cs, accepted=s_["n_accepted"],
+                        acc_rate=s_["acc_rate"], chain_seconds=busy,
+                        chain_sweeps_per_chain_s=cs / busy if busy > 0 else None,
+                        recomputes=s_["n_recomputes"], delay_k=s_["delay_k"]))
+        eq += cs * (L / 400.0) ** 3
+        flips += s_["n_accepted"]
+    return dict(workload="%s: beta=%g U=%g L=%s, %d chains per grid x (%d+%d) sweeps, mode %s"
+                % (name, beta, U, Ls, n_chains, warmup, sweeps, mode),
+                kernel_s=tk, chain_sweeps_per_s=sum(p_["chain_sweeps"] for p_ in per) / tk,
+                l400_equiv_sweeps_per_s=eq / tk, accepted_flips_per_s=flips / tk, grids=per,
+                workgroups=st[0]["n_workgroups"])
+
+
 def n_rec_flops(L, st, n_chains):
     return (st["n_recomputes"] + n_chains) * 2.0 * (8.0 / 3.0) * float(L) ** 3
 
@@ -218,6 +262,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=100)
     ap.add_argument("--calib-copy", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the peak probes and the small-L / three-grid workloads")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -309,6 +355,31 @@ def main():
         g_beta_half=float(g[L // 2]),
         g_beta_half_err=float(ge[L // 2]),
     )
+    peaks = None
+    extra = {}
+    if not args.no_extra:
+        peaks = P.hfqmc_measure_peaks(ctx)
+        progress("measured peaks: copy %.0f GB/s, read %.0f GB/s, FP64 MFMA %.1f TF/s, "
+                 "FP32 MFMA %.1f TF/s, FP64 FMA %.1f TF/s"
+                 % (peaks["hbm_copy_gbs"], peaks["hbm_read_gbs"], peaks["fp64_mfma_tflops"],
+                    peaks["fp32_mfma_tflops"], peaks["fp64_fma_tflops"]))
+        # small grids, FP64 rank-1, all in one launch: latency of the per-flip dependency
+        small = batched_grids(P, ctx, "seven grids", 20.0, 4.8,
+                              [0.4, 1 / 3, 2 / 7, 0.25, 0.2, 1 / 6, 0.125], 64, 20, 200, "rank1")
+        fl = sum(4.0 * g_["L"] ** 2 * g_["accepted"] for g_ in small["grids"])
+        small["fp64_update_tflops"] = fl / small["kernel_s"] / 1e12
+        small["frac_of_measured_fp64_fma"] = (small["fp64_update_tflops"] / peaks["fp64_fma_tflops"]
+                                              if peaks["fp64_fma_tflops"] > 0 else None)
+        extra["small_grids_rank1"] = small
+        progress("seven small grids (rank-1): %.0f chain-sweeps/s, %.3g accepted flips/s"
+                 % (small["chain_sweeps_per_s"], small["accepted_flips_per_s"]))
+        three = batched_grids(P, ctx, "three grids", 50.0, 5.0, [0.125, 0.1, 0.0625], 128, 2, 10,
+                              "mixed")
+        extra["three_grids_mixed"] = three
+        progress("three grids L=400/500/800 (mixed): %.0f L=400-equivalent chain-sweeps/s"
+                 % three["l400_equiv_sweeps_per_s"])
+    add_measured_peaks(rf, peaks)
+    add_measured_peaks(rf["secondary"], peaks)
     rank1 = None
     if args.rank1_sweeps > 0 and args.mode != "rank1":
         r = solve("rank1", 0, args.rank1_sweeps)
@@ -360,6 +431,8 @@ def main():
         "checks": checks,
         "phases_chain_s": ph,
         "kernel_sweeps_per_s": chain_sweeps / t_k,
+        "measured_peaks": peaks,
+        "other_workloads": extra or None,
     }
     print(json.dumps(line), flush=True)
 

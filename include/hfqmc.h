@@ -173,6 +173,25 @@ int hfqmc_solve_grids(hfqmc_ctx *ctx, int32_t n_grids, const int32_t *L, const d
                       double U, double beta, uint64_t seed, const hfqmc_opts *opts,
                       double *g_tau, double *g_err, double *docc, hfqmc_stats *stats);
 
+/* Achievable peaks of the context's device, the ceilings next to the
+ * datasheet ones that the sweep kernel's roofline is quoted against (the
+ * method's cost model: the update streams the L x L Green matrices through
+ * memory, the recompute is a dense FP64 solve; Introduction, effort ~ dtau^-3).
+ * Measured with the library's own probe kernels on the context's stream,
+ * best of three timed launches each:
+ *   hbm_copy_gbs      (read + written bytes) / time, device copy of 1 GiB
+ *   hbm_read_gbs      read-only stream of 1 GiB
+ *   fp64_mfma_tflops  v_mfma_f64_16x16x4f64 issue loop on every compute unit
+ *   fp32_mfma_tflops  v_mfma_f32_16x16x4f32 issue loop
+ *   fp64_fma_tflops   FP64 vector FMA loop
+ * Allocates and frees 2 GiB of device memory; takes well under a second.
+ * EINVAL for NULL arguments, ENOMEM, EDEVICE on a runtime error. */
+typedef struct {
+  double hbm_copy_gbs, hbm_read_gbs;
+  double fp64_mfma_tflops, fp32_mfma_tflops, fp64_fma_tflops;
+} hfqmc_peaks;
+int hfqmc_measure_peaks(hfqmc_ctx *ctx, hfqmc_peaks *out);
+
 /* Multigrid solve: multigrid_solve(list of dtau) -> G(tau) extrapolated to dtau -> 0.
  * bath_iw[2 n_iw]: bath on the Matsubara axis with high-frequency moment
  * bath_m3 (bath ~ 1/(i w) + m3/(i w)^3, particle-hole symmetric).  For each

@@ -57,6 +57,14 @@ class Stats(C.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
 
 
+class Peaks(C.Structure):
+    _fields_ = [("hbm_copy_gbs", _f64), ("hbm_read_gbs", _f64), ("fp64_mfma_tflops", _f64),
+                ("fp32_mfma_tflops", _f64), ("fp64_fma_tflops", _f64)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 _ctx_p = C.c_void_p
 
 lib.hfqmc_create.argtypes = [C.POINTER(_ctx_p), C.c_int]
@@ -85,6 +93,8 @@ lib.bethe_semicircle_bath.argtypes = [_f64, _f64, _i32, _pd]
 lib.bethe_semicircle_bath.restype = C.c_int
 lib.bath_to_tau.argtypes = [_pd, _i32, _f64, _f64, _i32, _pd]
 lib.bath_to_tau.restype = C.c_int
+lib.hfqmc_measure_peaks.argtypes = [_ctx_p, C.POINTER(Peaks)]
+lib.hfqmc_measure_peaks.restype = C.c_int
 
 FLAG_EAGER = 1       # launch kernels one by one (no captured graph)
 FLAG_HEAT_BATH = 2   # heat-bath acceptance u < R/(1+R)
@@ -92,7 +102,7 @@ FLAG_DIRECT_RECOMPUTE = 4  # full-size LU recompute instead of the reduced syste
 
 EXPORTED = ["hfqmc_create", "hfqmc_destroy", "hfqmc_set_stream", "hfqmc_last_error",
             "hfqmc_solve", "hfqmc_solve_dev", "hfqmc_solve_grids", "multigrid_solve", "dmft_bethe_step",
-            "bethe_semicircle_bath", "bath_to_tau"]
+            "bethe_semicircle_bath", "bath_to_tau", "hfqmc_measure_peaks"]
 
 
 def ptr(a, ctype=C.c_double):

@@ -6,6 +6,7 @@
   out = hfqmc_solve_grids(ctx, Ls, [g0_tau_i], U, beta, seed, ...)
   out = multigrid_solve(ctx, bath_iw, m3, U, beta, dtaus, seed, n_fine, ...)
   new_bath = dmft_bethe_step(g_fine, bath_iw, m3, U, beta, t)
+  peaks = hfqmc_measure_peaks(ctx)                                    # achievable peaks
 """
 import ctypes as C
 import sys
@@ -189,6 +190,14 @@ def hfqmc_solve_dev(ctx, g0_tau, L, U, beta, dtau, seed, g_tau, g_err=None, docc
                                C.c_void_p(int(docc) if docc else None), C.byref(st))
     N.check(rc, "hfqmc_solve_dev")
     return st.as_dict()
+
+
+def hfqmc_measure_peaks(ctx):
+    """Achievable HBM bandwidth (GB/s) and matrix-core / FMA rates (TFLOP/s)
+    of the context's device, from the library's probe kernels."""
+    pk = N.Peaks()
+    N.check(N.lib.hfqmc_measure_peaks(ctx.handle, C.byref(pk)), "hfqmc_measure_peaks")
+    return pk.as_dict()
 
 
 def hfqmc_solve_grids(ctx, Ls, g0_taus, U, beta, seed, n_chains=1, warmup=0, sweeps=1,

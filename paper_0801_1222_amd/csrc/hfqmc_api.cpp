@@ -727,6 +727,54 @@ extern "C" int hfqmc_solve_dev(hfqmc_ctx* c, const double* g0_tau, int32_t L, do
   return solve_grids_impl(c, 1, Ls, g0_tau, U, beta, seed, opts, g_tau, g_err, docc, stats, call);
 }
 
+extern "C" int hfqmc_measure_peaks(hfqmc_ctx* c, hfqmc_peaks* out) {
+  if (!c || !out) return fail(HFQMC_EINVAL, "hfqmc_measure_peaks: NULL argument");
+  HIPCHK(hipSetDevice(c->device));
+  std::memset(out, 0, sizeof *out);
+  // streams: 1 GiB each way (four times the last-level cache); arithmetic:
+  // 4 workgroups of 8 waves per compute unit
+  const long long n16 = (1LL << 30) / 16;
+  const int sblocks = c->n_cu * 8;
+  const int ablocks = c->n_cu * 4;
+  const int nthr = peak_threads();
+  const size_t out_bytes = (size_t)std::max(sblocks, ablocks) * nthr * sizeof(double);
+  DevBuf buf;
+  if (int e = buf.ensure(2 * n16 * 16 + out_bytes)) return e;
+  char* src = (char*)buf.p;
+  char* dst = src + n16 * 16;
+  double* o = (double*)(dst + n16 * 16);
+  hipStream_t s = c->stream;
+  hipError_t he = launch_zero((double*)src, 4 * n16, s);   // defined values in both buffers
+  auto best_ms = [&](int kind, int blocks, int iters, float* ms) -> hipError_t {
+    *ms = 1e30f;
+    for (int rep = 0; rep < 4 && he == hipSuccess; ++rep) {   // first launch warms up
+      he = hipEventRecord(c->ev0, s);
+      if (he == hipSuccess) he = launch_peak(kind, src, dst, n16, blocks, iters, o, s);
+      if (he == hipSuccess) he = hipEventRecord(c->ev1, s);
+      if (he == hipSuccess) he = hipEventSynchronize(c->ev1);
+      float t = 0.f;
+      if (he == hipSuccess) he = hipEventElapsedTime(&t, c->ev0, c->ev1);
+      if (he == hipSuccess && rep > 0 && t < *ms) *ms = t;
+    }
+    return he;
+  };
+  float ms = 0.f;
+  const int it64 = 4096, it32 = 8192, itv = 16384;
+  if (best_ms(PEAK_COPY, sblocks, 0, &ms) == hipSuccess) out->hbm_copy_gbs = 2.0 * n16 * 16 / (ms * 1e-3) / 1e9;
+  if (best_ms(PEAK_READ, sblocks, 0, &ms) == hipSuccess) out->hbm_read_gbs = 1.0 * n16 * 16 / (ms * 1e-3) / 1e9;
+  if (best_ms(PEAK_MFMA64, ablocks, it64, &ms) == hipSuccess)
+    out->fp64_mfma_tflops = peak_flops(PEAK_MFMA64, ablocks, it64) / (ms * 1e-3) / 1e12;
+  if (best_ms(PEAK_MFMA32, ablocks, it32, &ms) == hipSuccess)
+    out->fp32_mfma_tflops = peak_flops(PEAK_MFMA32, ablocks, it32) / (ms * 1e-3) / 1e12;
+  if (best_ms(PEAK_FMA64, ablocks, itv, &ms) == hipSuccess)
+    out->fp64_fma_tflops = peak_flops(PEAK_FMA64, ablocks, itv) / (ms * 1e-3) / 1e12;
+  const hipError_t se = hipStreamSynchronize(s);
+  buf.release();
+  if (he != hipSuccess) return fail(HFQMC_EDEVICE, "peak probe: %s", hipGetErrorString(he));
+  if (se != hipSuccess) return fail(HFQMC_EDEVICE, "peak probe: %s", hipGetErrorString(se));
+  return HFQMC_OK;
+}
+
 extern "C" int hfqmc_solve_grids(hfqmc_ctx* c, int32_t n_grids, const int32_t* L,
                                  const double* g0_tau, double U, double beta, uint64_t seed,
                                  const hfqmc_opts* opts, double* g_tau, double* g_err,

@@ -108,4 +108,12 @@ hipError_t prepare_reference(int lds);
 hipError_t launch_reference(const SweepParams& p, int nb, int lds, int scratch, hipStream_t s);
 hipError_t launch_reduce(const GridDev* grids, int n_grids, int n_bins, hipStream_t s);
 
+// Achievable-peak probes (hfqmc_peaks.hip).  Copy / read: n16 16-byte
+// elements of src (and dst); out holds blocks * peak_threads() doubles.
+enum { PEAK_COPY = 0, PEAK_READ = 1, PEAK_MFMA64 = 2, PEAK_MFMA32 = 3, PEAK_FMA64 = 4 };
+hipError_t launch_peak(int kind, const void* src, void* dst, long long n16, int blocks, int iters,
+                       double* out, hipStream_t s);
+double peak_flops(int kind, int blocks, int iters);
+int peak_threads();
+
 }  // namespace hfqmc

@@ -146,3 +146,15 @@ def test_reduced_recompute_equals_direct(ctx, mode, k, L):
         assert np.array_equal(red["flips"][c], dirc["flips"][c])
         assert np.abs(red["chain_g"][c] - dirc["chain_g"][c]).max() < 1e-10 * red["chain_n"][c][0]
     assert red["stats"]["max_drift"] < (1e-3 if mode == "mixed" else 1e-10)
+
+
+def test_measured_peaks_are_plausible(ctx):
+    # the probes measure what the device achieves: positive and not above
+    # the datasheet figures (8 TB/s, 78.6 / 157.3 / 78.6 TFLOP/s)
+    import paper_0801_1222_amd as P
+    pk = P.hfqmc_measure_peaks(ctx)
+    assert 500.0 < pk["hbm_copy_gbs"] < 8000.0 * 1.05
+    assert 500.0 < pk["hbm_read_gbs"] < 8000.0 * 1.05
+    assert 5.0 < pk["fp64_mfma_tflops"] < 78.6 * 1.05
+    assert 5.0 < pk["fp32_mfma_tflops"] < 157.3 * 1.05
+    assert 2.0 < pk["fp64_fma_tflops"] < 78.6 * 1.05
