@@ -45,10 +45,11 @@ def progress(msg):
     print("[bench %7.1fs] %s" % (time.perf_counter() - _T0, msg), file=sys.stderr, flush=True)
 
 
-def algorithmic_work(L, st, n_chains, measured_sweeps, mode):
+def algorithmic_work(L, st, n_chains, measured_sweeps, mode, spins=2):
     """Algorithmic HBM bytes and FP64/FP32 flops of one solve.
 
-    Per unit (both spins, L x L FP64 Green matrices):
+    Per unit (both spins, L x L FP64 Green matrices; with spins=1, the
+    particle-hole symmetric single-matrix form, every figure halves):
       rank-1 accepted flip     32 L^2 bytes (read + write G), 4 L^2 FP64 flops
       delayed flush of rank m  32 L^2 bytes; its flips cost 4 L^2 flops each
                                (FP32 in the mixed path, FP64 otherwise)
@@ -69,10 +70,11 @@ def algorithmic_work(L, st, n_chains, measured_sweeps, mode):
         f64, f32 = (0.0, 4.0 * L2 * n_acc) if mode == "mixed" else (4.0 * L2 * n_acc, 0.0)
     bytes_ = upd_bytes + 16.0 * L2 * meas + 24.0 * L2 * n_rec
     f64 += n_rec * 2.0 * (8.0 / 3.0) * L2 * L
-    return bytes_, f64, f32
+    h = spins / 2.0
+    return bytes_ * h, f64 * h, f32 * h
 
 
-def executed_recompute_flops(L, st, n_chains):
+def executed_recompute_flops(L, st, n_chains, spins=2):
     """FP64 flops the recompute actually executes.
 
     Reduced form (the default): per spin solve with |S| = s rows, an LU of the
@@ -81,14 +83,14 @@ def executed_recompute_flops(L, st, n_chains):
     |S| is the mean over all solves (stats n_reduced_rows).  Full form:
     (8/3) L^3 per spin.
     """
-    n_solves = 2.0 * (st["n_recomputes"] + n_chains)
+    n_solves = spins * (st["n_recomputes"] + n_chains)
     if not st.get("recompute_reduced"):
         return n_solves * (8.0 / 3.0) * float(L) ** 3
     s = st["n_reduced_rows"] / max(n_solves, 1.0)
     return n_solves * ((2.0 / 3.0) * s ** 3 + 2.0 * s * s * L + 2.0 * (L - s) * s * L)
 
 
-def composite_bound_s(L, st, n_chains, measured_sweeps, mode):
+def composite_bound_s(L, st, n_chains, measured_sweeps, mode, spins=2):
     """Sum over phases of max(bytes / HBM peak, flops / matrix-core peak) (phases not overlapped)."""
     L2 = float(L) * L
     n_acc = st["n_accepted"]
@@ -101,12 +103,12 @@ def composite_bound_s(L, st, n_chains, measured_sweeps, mode):
         upd = max(32.0 * L2 * n_flush / bw, 4.0 * L2 * n_acc / (f32p if mode == "mixed" else f64p))
     rec = max(24.0 * L2 * n_rec / bw, n_rec * 2.0 * (8.0 / 3.0) * L2 * L / f64p)
     meas = 16.0 * L2 * n_chains * measured_sweeps / bw
-    return upd + rec + meas
+    return (upd + rec + meas) * spins / 2.0
 
 
-def roofline(L, st, n_chains, measured_sweeps, mode, t_kernel):
+def roofline(L, st, n_chains, measured_sweeps, mode, t_kernel, spins=2):
     """Roofline entry of the sweep kernel: the resource whose lower-bound time is largest."""
-    by, f64, f32 = algorithmic_work(L, st, n_chains, measured_sweeps, mode)
+    by, f64, f32 = algorithmic_work(L, st, n_chains, measured_sweeps, mode, spins)
     t_hbm = by / (HBM_PEAK_GBS * 1e9)
     t_mfma = f64 / (FP64_PEAK_TFLOPS * 1e12) + f32 / (FP32_PEAK_TFLOPS * 1e12)
     hbm = {"bound": "hbm", "achieved": by / t_kernel / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
@@ -121,15 +123,16 @@ def roofline(L, st, n_chains, measured_sweeps, mode, t_kernel):
     main["secondary"] = other
     main["lower_bound_s"] = {"hbm": t_hbm, "mfma_fp64_equiv": t_mfma}
     main["algorithmic"] = {"bytes": by, "fp64_flops": f64, "fp32_flops": f32}
-    main["composite_frac"] = composite_bound_s(L, st, n_chains, measured_sweeps, mode) / t_kernel
+    main["composite_frac"] = composite_bound_s(L, st, n_chains, measured_sweeps, mode,
+                                               spins) / t_kernel
     # the recompute's algorithmic flops above are those of the full (8/3) L^3 solve per
     # spin; the reduced form computes the same G with fewer
-    ex = executed_recompute_flops(L, st, n_chains)
+    ex = executed_recompute_flops(L, st, n_chains, spins)
     main["executed"] = {"recompute_fp64_flops": ex,
                         "mean_reduced_rows": st["n_reduced_rows"]
-                        / max(2.0 * (st["n_recomputes"] + n_chains), 1.0),
+                        / max(spins * (st["n_recomputes"] + n_chains), 1.0),
                         "fp64_equiv_tflops": (ex + f32 * FP64_PEAK_TFLOPS / FP32_PEAK_TFLOPS
-                                              + (f64 - n_rec_flops(L, st, n_chains)))
+                                              + (f64 - n_rec_flops(L, st, n_chains, spins)))
                         / t_kernel / 1e12}
     return main
 
@@ -178,8 +181,8 @@ def batched_grids(P, ctx, name, beta, U, dtaus, n_chains, warmup, sweeps, mode, 
                 workgroups=st[0]["n_workgroups"])
 
 
-def n_rec_flops(L, st, n_chains):
-    return (st["n_recomputes"] + n_chains) * 2.0 * (8.0 / 3.0) * float(L) ** 3
+def n_rec_flops(L, st, n_chains, spins=2):
+    return (st["n_recomputes"] + n_chains) * spins * (8.0 / 3.0) * float(L) ** 3
 
 
 def kernel_source_hash():
@@ -380,6 +383,29 @@ def main():
                  % three["l400_equiv_sweeps_per_s"])
     add_measured_peaks(rf, peaks)
     add_measured_peaks(rf["secondary"], peaks)
+    ph = None
+    if not args.no_extra and args.mode != "rank1":
+        # the same workload through the particle-hole symmetric single-matrix form
+        # (the bath is symmetric): G_dn = 1 - G_up^T, one matrix updated and recomputed
+        sp = P.hfqmc_solve_dev(ctx, g0_d.data_ptr(), L, w["U"], w["beta"], w["dtau"], w["seed"],
+                               g_d.data_ptr(), e_d.data_ptr(), d_d.data_ptr(),
+                               n_chains=w["n_chains"], warmup=w["warmup"], sweeps=w["sweeps"],
+                               mode=args.mode, delay_k=args.delay_k, ph=True)
+        torch.cuda.synchronize()
+        rph = roofline(L, sp, w["n_chains"], w["sweeps"], args.mode, sp["seconds_kernel"], spins=1)
+        add_measured_peaks(rph, peaks)
+        add_measured_peaks(rph["secondary"], peaks)
+        gp_ = g_d.cpu().numpy()
+        ph = dict(sweeps_per_s=chain_sweeps / sp["seconds_kernel"], kernel_s=sp["seconds_kernel"],
+                  speedup_vs_two_matrix=t_k / sp["seconds_kernel"], delay_k=sp["delay_k"],
+                  lu_panel=sp["lu_panel"], acc_rate=sp["acc_rate"], max_drift=sp["max_drift"],
+                  docc=float(d_d.cpu().numpy()[0]),
+                  max_abs_dg_vs_two_matrix=float(np.abs(gp_ - g).max()),
+                  roofline={k_: rph[k_] for k_ in ("bound", "achieved", "peak", "unit", "frac",
+                                                    "composite_frac")},
+                  note="same chains and sweeps; only G_up stored (G_dn = 1 - G_up^T holds for "
+                       "a particle-hole symmetric bath); not the headline value")
+        progress("single-matrix (particle-hole symmetric) form: %.0f sweeps/s" % ph["sweeps_per_s"])
     rank1 = None
     if args.rank1_sweeps > 0 and args.mode != "rank1":
         r = solve("rank1", 0, args.rank1_sweeps)
@@ -432,6 +458,7 @@ def main():
         "phases_chain_s": ph,
         "kernel_sweeps_per_s": chain_sweeps / t_k,
         "measured_peaks": peaks,
+        "ph_single_matrix": ph,
         "other_workloads": extra or None,
     }
     print(json.dumps(line), flush=True)

@@ -72,8 +72,14 @@ enum {
   HFQMC_FLAG_EAGER = 1,      /* launch the kernels one by one instead of replaying a captured
                                 HIP graph of the launch sequence (results are identical) */
   HFQMC_FLAG_HEAT_BATH = 2,  /* heat-bath acceptance u < R/(1+R) instead of Metropolis u < R */
-  HFQMC_FLAG_DIRECT_RECOMPUTE = 4  /* recompute with the full L x L LU of [M | G0] instead of the
+  HFQMC_FLAG_DIRECT_RECOMPUTE = 4, /* recompute with the full L x L LU of [M | G0] instead of the
                                       reduced system against the uniform-field references */
+  HFQMC_FLAG_PH_SYMMETRIC = 8  /* particle-hole symmetric bath (G0(tau) = G0(beta - tau),
+                                  G0(0+) = 1/2): only G_up is stored and updated, G_dn being
+                                  1 - G_up^T for every field (V_dn = -V_up); R_dn, the
+                                  estimators and final_green use that identity.  Halves the
+                                  update, recompute and measurement work.  EINVAL unless every
+                                  bath satisfies the symmetry to 1e-9 */
 };
 
 typedef struct {

@@ -60,9 +60,10 @@ class Context:
             pass
 
 
-def _flags(eager=False, heat_bath=False, direct=False):
+def _flags(eager=False, heat_bath=False, direct=False, ph=False):
     return ((N.FLAG_EAGER if eager else 0) | (N.FLAG_HEAT_BATH if heat_bath else 0)
-            | (N.FLAG_DIRECT_RECOMPUTE if direct else 0))
+            | (N.FLAG_DIRECT_RECOMPUTE if direct else 0)
+            | (N.FLAG_PH_SYMMETRIC if ph else 0))
 
 
 def _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drift_limit, flags=0):
@@ -149,12 +150,12 @@ class _Hooks:
 def hfqmc_solve(ctx, g0_tau, U, beta, dtau, seed, n_chains=1, warmup=0, sweeps=1,
                 mode="rank1", recompute_every=0, delay_k=0, n_bins=0, drift_limit=0.0,
                 flip_cap=0, replay=None, want_chain=False, want_green=False, eager=False,
-                heat_bath=False, direct=False):
+                heat_bath=False, direct=False, ph=False):
     """Fixed-dtau solve; returns dict(g, g_err, D, D_err, stats, [hooks])."""
     g0 = np.ascontiguousarray(g0_tau, dtype=np.float64)
     L = g0.shape[0]
     o = _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drift_limit,
-              _flags(eager, heat_bath, direct))
+              _flags(eager, heat_bath, direct, ph))
     hk = _Hooks(o, 1, n_chains, [L], n_bins, flip_cap,
                 [replay] if replay is not None else None, want_chain, want_green)
     g = np.zeros(L + 1)
@@ -178,11 +179,12 @@ def hfqmc_solve(ctx, g0_tau, U, beta, dtau, seed, n_chains=1, warmup=0, sweeps=1
 
 def hfqmc_solve_dev(ctx, g0_tau, L, U, beta, dtau, seed, g_tau, g_err=None, docc=None,
                     n_chains=1, warmup=0, sweeps=1, mode="rank1", recompute_every=0, delay_k=0,
-                    n_bins=0, drift_limit=0.0, eager=False, heat_bath=False, direct=False):
+                    n_bins=0, drift_limit=0.0, eager=False, heat_bath=False, direct=False,
+                    ph=False):
     """hfqmc_solve on device buffers (raw device addresses as ints, e.g. a torch
     tensor's data_ptr(), on the context's device and stream); returns the stats."""
     o = _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drift_limit,
-              _flags(eager, heat_bath, direct))
+              _flags(eager, heat_bath, direct, ph))
     st = N.Stats()
     rc = N.lib.hfqmc_solve_dev(ctx.handle, C.c_void_p(int(g0_tau)), int(L), float(U), float(beta),
                                float(dtau), int(seed), C.byref(o), C.c_void_p(int(g_tau)),
@@ -203,7 +205,7 @@ def hfqmc_measure_peaks(ctx):
 def hfqmc_solve_grids(ctx, Ls, g0_taus, U, beta, seed, n_chains=1, warmup=0, sweeps=1,
                       mode="rank1", recompute_every=0, delay_k=0, n_bins=0, drift_limit=0.0,
                       flip_cap=0, replay=None, want_chain=False, eager=False, heat_bath=False,
-                      direct=False):
+                      direct=False, ph=False):
     """Several grids in one persistent launch; per-grid lists in the result."""
     Ls = [int(L) for L in Ls]
     n = len(Ls)
@@ -211,7 +213,7 @@ def hfqmc_solve_grids(ctx, Ls, g0_taus, U, beta, seed, n_chains=1, warmup=0, swe
     g0 = np.ascontiguousarray(np.concatenate([np.asarray(x, dtype=np.float64) for x in g0_taus]))
     assert g0.shape[0] == sum(Ls)
     o = _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drift_limit,
-              _flags(eager, heat_bath, direct))
+              _flags(eager, heat_bath, direct, ph))
     hk = _Hooks(o, n, n_chains, Ls, n_bins, flip_cap, replay, want_chain, False)
     P = sum(L + 1 for L in Ls)
     g = np.zeros(P)
@@ -235,13 +237,14 @@ def hfqmc_solve_grids(ctx, Ls, g0_taus, U, beta, seed, n_chains=1, warmup=0, swe
 
 def multigrid_solve(ctx, bath_iw, bath_m3, U, beta, dtaus, seed, n_fine=200, n_chains=1,
                     warmup=0, sweeps=1, mode="rank1", recompute_every=0, delay_k=0, n_bins=0,
-                    drift_limit=0.0, eager=False, heat_bath=False, direct=False):
+                    drift_limit=0.0, eager=False, heat_bath=False, direct=False,
+                    ph=False):
     """dtau -> 0 extrapolated G(tau_j), tau_j = j beta/(n_fine-1)."""
     b = np.ascontiguousarray(np.asarray(bath_iw, dtype=np.complex128)).view(np.float64)
     n_iw = b.shape[0] // 2
     dt = np.ascontiguousarray(dtaus, dtype=np.float64)
     o = _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drift_limit,
-              _flags(eager, heat_bath, direct))
+              _flags(eager, heat_bath, direct, ph))
     Ls = [int(round(beta / x)) for x in dt]
     gf = np.zeros(n_fine)
     ef = np.zeros(n_fine)

@@ -188,7 +188,8 @@ int resolve_opts(const hfqmc_opts* o, Resolved* r) {
   r->mode = o->mode;
   r->warmup = o->warmup;
   r->sweeps = o->sweeps;
-  if (o->flags & ~(HFQMC_FLAG_EAGER | HFQMC_FLAG_HEAT_BATH | HFQMC_FLAG_DIRECT_RECOMPUTE))
+  if (o->flags & ~(HFQMC_FLAG_EAGER | HFQMC_FLAG_HEAT_BATH | HFQMC_FLAG_DIRECT_RECOMPUTE |
+                   HFQMC_FLAG_PH_SYMMETRIC))
     return fail(HFQMC_EINVAL, "flags=0x%x", o->flags);
   if (o->mode == MODE_RANK1) {
     r->delay_k = 1;
@@ -230,7 +231,7 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
 int autotune(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double* g0_tau, bool dev_io,
              double U, double beta, uint64_t seed, const hfqmc_opts* opts, int Lmax,
              TuneChoice* out, double* seconds) {
-  std::vector<int> key = {opts->mode, opts->n_chains};
+  std::vector<int> key = {opts->mode, opts->n_chains, opts->flags & HFQMC_FLAG_PH_SYMMETRIC};
   long long Lsum = 0;
   for (int i = 0; i < n_grids; ++i) {
     key.push_back(Ls[i]);
@@ -246,9 +247,17 @@ int autotune(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double* g0_tau,
   std::vector<double> g0h;
   const double* g0 = g0_tau;
   if (dev_io) {
+    // the caller's buffer may belong to another HIP runtime of the process:
+    // a kernel copies it into memory of this one before it crosses to the host
+    DevBuf tmp;
+    if (int e = tmp.ensure(sizeof(double) * Lsum)) return e;
     g0h.resize(Lsum);
-    HIPCHK(hipMemcpyAsync(g0h.data(), g0_tau, sizeof(double) * Lsum, hipMemcpyDeviceToHost, c->stream));
-    HIPCHK(hipStreamSynchronize(c->stream));
+    hipError_t he = launch_copy(g0_tau, (double*)tmp.p, Lsum, c->stream);
+    if (he == hipSuccess)
+      he = hipMemcpyAsync(g0h.data(), tmp.p, sizeof(double) * Lsum, hipMemcpyDeviceToHost, c->stream);
+    if (he == hipSuccess) he = hipStreamSynchronize(c->stream);
+    tmp.release();
+    if (he != hipSuccess) return fail(HFQMC_EDEVICE, "autotune: bath copy: %s", hipGetErrorString(he));
     g0 = g0h.data();
   }
   int nb_widest = 0, scratch = 0;
@@ -265,7 +274,8 @@ int autotune(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double* g0_tau,
   to.sweeps = 2;
   to.recompute_every = opts->recompute_every;
   to.n_bins = 1;
-  to.flags = (opts->flags & (HFQMC_FLAG_HEAT_BATH | HFQMC_FLAG_DIRECT_RECOMPUTE)) | HFQMC_FLAG_EAGER;
+  to.flags = (opts->flags & (HFQMC_FLAG_HEAT_BATH | HFQMC_FLAG_DIRECT_RECOMPUTE |
+                             HFQMC_FLAG_PH_SYMMETRIC)) | HFQMC_FLAG_EAGER;
   long long P = 0;
   for (int i = 0; i < n_grids; ++i) P += Ls[i] + 1;
   std::vector<double> gs(P), es(P), ds(2 * n_grids);
@@ -423,6 +433,26 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
     HIPCHK(launch_copy(g0_tau, d_gtau, Lsum, st));
   else
     HIPCHK(hipMemcpyAsync(d_gtau, g0_tau, sizeof(double) * Lsum, hipMemcpyHostToDevice, st));
+  if (opts->flags & HFQMC_FLAG_PH_SYMMETRIC) {
+    // G_dn = 1 - G_up^T needs G0 = 1 - G0^T: G0(0+) = 1/2 and G0(tau) = G0(beta - tau)
+    std::vector<double> gh_tau;
+    const double* gt = g0_tau;
+    if (call.dev_io) {
+      gh_tau.resize(Lsum);
+      HIPCHK(hipMemcpyAsync(gh_tau.data(), d_gtau, sizeof(double) * Lsum, hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      gt = gh_tau.data();
+    }
+    for (int i = 0; i < n_grids; ++i) {
+      const double* g = gt + goff0[i];
+      const int L = Ls[i];
+      double dev = std::fabs(g[0] - 0.5);
+      for (int q = 1; q < L; ++q) dev = std::max(dev, std::fabs(g[q] - g[L - q]));
+      if (!(dev <= 1e-9))
+        return fail(HFQMC_EINVAL, "HFQMC_FLAG_PH_SYMMETRIC: bath of grid %d deviates from "
+                    "particle-hole symmetry by %.3e", i, dev);
+    }
+  }
   if (opts->replay_log) {
     for (int i = 0; i < n_grids; ++i) {
       HIPCHK(hipMemcpyAsync((void*)gd[i].replay, opts->replay_log + (size_t)i * nch * opts->replay_cap,
@@ -476,6 +506,7 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
   p.lds_scratch_bytes = scratch;
   p.heat_bath = (opts->flags & HFQMC_FLAG_HEAT_BATH) ? 1 : 0;
   p.direct = direct;
+  p.ph = (opts->flags & HFQMC_FLAG_PH_SYMMETRIC) ? 1 : 0;
 
   // ---- the device launch sequence: bath matrices, zeroed accumulators and
   // counters (fill kernels), the persistent sweep kernel, the chain reduction

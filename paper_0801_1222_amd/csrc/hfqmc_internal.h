@@ -79,6 +79,7 @@ struct SweepParams {
   int lds_scratch_bytes;  // bytes of the phase-shared LDS region
   int heat_bath;          // 1: accept iff u < R/(1+R); 0: Metropolis, u < R
   int direct;             // 1: recompute with the full L x L system (no reference reduction)
+  int ph;                 // 1: particle-hole symmetric bath, only G_up kept (G_dn = 1 - G_up^T)
 };
 
 constexpr int kThreads = 512;   // threads per persistent workgroup (8 wave64)

@@ -1170,7 +1170,12 @@ __device__ __forceinline__ double dyson_solve(const Chain& ch, int sigma, double
 // (sgn = -1 where l + k wraps) and D = (1/L) sum_l (1 - Gu_ll)(1 - Gd_ll)
 // into the chain's bin.  Thread k walks rows i and reads G(i, (i-k) mod L),
 // so every step of a wave reads one contiguous stretch of a row.
-__device__ __forceinline__ void measure(const Chain& ch, int bin) {
+//
+// With only G_up stored (ph): G_dn(i, j) = delta_ij - G_up(j, i), and the
+// spin-down sum over i becomes, with j = (i - k) mod L,
+//   sum_i sgn G_dn(i, j) = L delta_k0 - sum_j sgn' G_up(j, (j + k) mod L),
+// sgn' = -1 where j + k wraps: again one contiguous stretch of a row per step.
+__device__ __forceinline__ void measure(const Chain& ch, int bin, bool ph) {
   const int L = ch.L;
   double* accg = ch.accg;
   for (int k = threadIdx.x; k < L; k += kThreads) {
@@ -1184,7 +1189,20 @@ __device__ __forceinline__ void measure(const Chain& ch, int bin) {
       }
       const long long o = (long long)i * L + j;
       acc += sg * ch.Gu[o];
-      acc += sg * ch.Gd[o];
+      if (!ph) acc += sg * ch.Gd[o];
+    }
+    if (ph) {
+      double dn = 0.0;
+      for (int j = 0; j < L; ++j) {
+        int i = j + k;
+        double sg = 1.0;
+        if (i >= L) {
+          i -= L;
+          sg = -1.0;
+        }
+        dn += sg * ch.Gu[(long long)j * L + i];
+      }
+      acc += (k == 0 ? (double)L : 0.0) - dn;
     }
     const double val = acc / (2.0 * L);
     const long long base = (long long)bin * (L + 1);
@@ -1194,7 +1212,8 @@ __device__ __forceinline__ void measure(const Chain& ch, int bin) {
   double dsum = 0.0;
   for (int l = threadIdx.x; l < L; l += kThreads) {
     const long long o = (long long)l * L + l;
-    dsum += (1.0 - ch.Gu[o]) * (1.0 - ch.Gd[o]);
+    const double gu = ch.Gu[o];
+    dsum += (1.0 - gu) * (ph ? gu : 1.0 - ch.Gd[o]);
   }
   dsum = block_sum(dsum, ch.red);
   if (threadIdx.x == 0) {
@@ -1263,8 +1282,9 @@ __device__ __forceinline__ void recompute_both(const SweepParams& p, const Chain
                                                bool counted) {
   const long long t0 = wall_clock64();
   double d = 0.0;
+  const int nsp = p.ph ? 1 : 2;
 #pragma unroll 1
-  for (int sp = 0; sp < 2; ++sp)
+  for (int sp = 0; sp < nsp; ++sp)
     d = fmax(d, dyson_solve(ch, sp ? -1 : +1, sp ? ch.Gd : ch.Gu, p.lu_nb, p.direct == 0, false));
   if (counted && threadIdx.x == 0) {
     *ch.drift = fmax(*ch.drift, d);
@@ -1287,6 +1307,7 @@ __device__ __forceinline__ int sweep_rank1(const SweepParams& p, const Chain& ch
   double* xd = xu + p.Lmax;
   double* yu = xd + p.Lmax;
   double* yd = yu + p.Lmax;
+  const bool ph = p.ph != 0;
   for (int l = l_begin; l < L; ++l) {
     const long long dl = (long long)l * L + l;
     const int sl = ch.s[l];
@@ -1294,8 +1315,9 @@ __device__ __forceinline__ int sweep_rank1(const SweepParams& p, const Chain& ch
       const int c0 = l & ~(kUW - 1);
       fill_uniforms(ch.uw, ch.key0, (uint64_t)ch.grid, sw, c0, min(kUW, L - c0));
     }
-    const Flip f = propose(ch.Gu[dl], ch.Gd[dl], sl, io.gp, io.gm, ch.uw[l & (kUW - 1)], io.rlog, io.rlen,
-                           sw * L + l, k, ch.st, io.hb);
+    const double gul = ch.Gu[dl];
+    const Flip f = propose(gul, ph ? 1.0 - gul : ch.Gd[dl], sl, io.gp, io.gm, ch.uw[l & (kUW - 1)],
+                           io.rlog, io.rlen, sw * L + l, k, ch.st, io.hb);
     if (!f.accept) continue;
     log_flip(io, ch.st, sw * L + l);
     // update vectors x = G(:,l) - e_l and y = (gamma/R_sigma) G(l,:)
@@ -1303,14 +1325,47 @@ __device__ __forceinline__ int sweep_rank1(const SweepParams& p, const Chain& ch
     for (int i = threadIdx.x; i < L; i += kThreads) {
       const long long ci = (long long)i * L + l;
       xu[i] = ch.Gu[ci] - (i == l ? 1.0 : 0.0);
-      xd[i] = ch.Gd[ci] - (i == l ? 1.0 : 0.0);
       yu[i] = mul_nc(cu, ch.Gu[(long long)l * L + i]);
-      yd[i] = mul_nc(cd, ch.Gd[(long long)l * L + i]);
+      if (!ph) {
+        xd[i] = ch.Gd[ci] - (i == l ? 1.0 : 0.0);
+        yd[i] = mul_nc(cd, ch.Gd[(long long)l * L + i]);
+      }
     }
     __syncthreads();
-    // G += x y^T, both spins: thread -> (column pair, row group); the pair's
-    // y values stay in registers, x is an LDS broadcast per row
-    {
+    if (ph) {
+      // G_up only: thread -> (column pair, row group) as below
+      const int ncp = (L + 1) >> 1;
+      const int rg = max(1, kThreads / ncp);
+      const int t = threadIdx.x;
+      if (t < ncp * rg) {
+        const int cp = t % ncp, r0 = t / ncp;
+        const int j = 2 * cp;
+        const bool two = j + 1 < L;
+        const double yu0 = yu[j];
+        const double yu1 = two ? yu[j + 1] : 0.0;
+        if ((L & 1) == 0) {
+#pragma unroll 4
+          for (int i = r0; i < L; i += rg) {
+            const double xui = xu[i];
+            double2* gu = reinterpret_cast<double2*>(ch.Gu + (long long)i * L + j);
+            double2 a = *gu;
+            a.x = axpy_nc(a.x, xui, yu0);
+            a.y = axpy_nc(a.y, xui, yu1);
+            *gu = a;
+          }
+        } else {
+#pragma unroll 4
+          for (int i = r0; i < L; i += rg) {
+            const double xui = xu[i];
+            double* gu = ch.Gu + (long long)i * L + j;
+            gu[0] = axpy_nc(gu[0], xui, yu0);
+            if (two) gu[1] = axpy_nc(gu[1], xui, yu1);
+          }
+        }
+      }
+    } else {
+      // G += x y^T, both spins: thread -> (column pair, row group); the pair's
+      // y values stay in registers, x is an LDS broadcast per row
       const int ncp = (L + 1) >> 1;
       const int rg = max(1, kThreads / ncp);
       const int t = threadIdx.x;
@@ -1600,12 +1655,13 @@ __device__ __forceinline__ void flush_vectors(const double* __restrict__ G, int 
 // (lower, diagonal c_j) share the m x m block TS (T[i][j] = TS[i][j] for
 // i < j, S[j][i] = TS[j][i] for i <= j); W overwrites TS once every wave has
 // read it.  Tiles (spin, 16 x 16 block) are spread over the waves.
-__device__ __forceinline__ void flush_fold(double* __restrict__ TSu, double* __restrict__ TSd, int m) {
+__device__ __forceinline__ void flush_fold(double* __restrict__ TSu, double* __restrict__ TSd, int m,
+                                           int nsp) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int li = lane & 15, lq = lane >> 4;
   const int mb = (m + 15) >> 4;
   const int ks = (m + 3) >> 2;
-  const int nt = 2 * mb * mb;                      // at most 32 tiles: 4 per wave
+  const int nt = nsp * mb * mb;                    // at most 32 tiles: 4 per wave
   doublex4 acc[4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
@@ -1686,9 +1742,9 @@ __device__ __forceinline__ WinLds win_lds(const Chain& ch) {
 //   S[c][c] = c_c,  S[j][c] = c_j sum_{c <= i < j} Lw[j][i] S[i][c]
 // All lanes step through j together, so every read of column / row j happens
 // before any lane overwrites it at the end of the same step.
-__device__ __forceinline__ void invert_ts(const WinLds& w, int m_inv, int m) {
+__device__ __forceinline__ void invert_ts(const WinLds& w, int m_inv, int m, int nsp) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  if (wv < 4 && lane < m) {
+  if (wv < 4 && lane < m && ((wv & 1) == 0 || nsp == 2)) {
     double* UL = (wv & 1) ? w.ULd : w.ULu;
     const double* cc = (wv & 1) ? w.cD : w.cU;
     if (wv < 2) {
@@ -1727,7 +1783,8 @@ __device__ __forceinline__ void invert_ts(const WinLds& w, int m_inv, int m) {
 //   Xrec[i][r] = X(l0 + r, i) = sum_{i'} C0(l0 + r, i') T[i'][i],
 //   Yrec[i][c] = Y(i, l0 + c) = sum_{i'} S[i][i'] G(f_i', l0 + c),
 // then the window blocks W = G(B,B) + X(B,:) Y(:,B), all FP64 on the matrix cores.
-__device__ __forceinline__ void window_apply(const Chain& ch, const WinLds& w, int l0, int b, int m) {
+__device__ __forceinline__ void window_apply(const Chain& ch, const WinLds& w, int l0, int b, int m,
+                                             int nsp) {
   const int L = ch.L;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int li = lane & 15, lq = lane >> 4;
@@ -1736,7 +1793,7 @@ __device__ __forceinline__ void window_apply(const Chain& ch, const WinLds& w, i
   double* Xrec = ch.wbuf;                       // [2][kMaxK][kWin]
   double* Yrec = Xrec + 2 * kMaxK * kWin;       // [2][kMaxK][kWin]
   // (1) X tiles (4 row blocks x mb) and Y tiles (mb x 4) of both spins
-  const int nx = 4 * mb, ntile = 2 * (2 * nx);
+  const int nx = 4 * mb, ntile = nsp * (2 * nx);
   for (int tile = wv; tile < ntile; tile += kThreads / 64) {
     const int sp = tile >= 2 * nx;
     const int e = tile - sp * 2 * nx;
@@ -1788,7 +1845,7 @@ __device__ __forceinline__ void window_apply(const Chain& ch, const WinLds& w, i
   }
   __syncthreads();
   // (2) W = G(B,B) + X(B,:) Y(:,B): 4 x 4 tiles per spin, 32 tiles over the waves
-  for (int tile = wv; tile < 32; tile += kThreads / 64) {
+  for (int tile = wv; tile < 16 * nsp; tile += kThreads / 64) {
     const int sp = tile >> 4, e = tile & 15;
     const int rb = e >> 2, cb = e & 3;
     const double* G = sp ? ch.Gd : ch.Gu;
@@ -1821,11 +1878,11 @@ __device__ __forceinline__ void window_apply(const Chain& ch, const WinLds& w, i
 // Coefficients of the window's new flips j = m0 .. m-1 (window at l0):
 // U(i, j) = y_i(f_j), Lw(j, i) = x_i(f_j) for i < j, from the window's records.
 __device__ __forceinline__ void capture_coefficients(const Chain& ch, const WinLds& w, int l0,
-                                                     int m0, int m) {
+                                                     int m0, int m, int nsp) {
   const double* Xrec = ch.wbuf;
   const double* Yrec = Xrec + 2 * kMaxK * kWin;
   const int n_new = m - m0;
-  for (int idx = threadIdx.x; idx < 2 * n_new * m; idx += kThreads) {
+  for (int idx = threadIdx.x; idx < nsp * n_new * m; idx += kThreads) {
     const int sp = idx >= n_new * m;
     const int e = idx - sp * n_new * m;
     const int j = m0 + e / m, i = e % m;
@@ -1839,23 +1896,24 @@ __device__ __forceinline__ void capture_coefficients(const Chain& ch, const WinL
   __syncthreads();
 }
 
-// Applies the m pending flips (T, S complete up to m) to G_up and G_dn.
+// Applies the m pending flips (T, S complete up to m) to G_up and G_dn (nsp = 2)
+// or to G_up alone (nsp = 1).
 template <bool MIXED>
-__device__ __forceinline__ void flush_pending(const Chain& ch, const WinLds& w, int m) {
+__device__ __forceinline__ void flush_pending(const Chain& ch, const WinLds& w, int m, int nsp) {
   const int L = ch.L;
   double* X = ch.wbuf + 4 * kMaxK * kWin;             // [2][L][kMaxK]
   double* Y = X + 2LL * L * kMaxK;                    // [2][kMaxK][L]
   const long long t1 = wall_clock64();
-  flush_fold(w.ULu, w.ULd, m);
+  flush_fold(w.ULu, w.ULd, m, nsp);
 #pragma unroll 1
-  for (int sp = 0; sp < 2; ++sp)
+  for (int sp = 0; sp < nsp; ++sp)
     flush_vectors(sp ? ch.Gd : ch.Gu, L, 0, m, w.F, sp ? w.ULd : w.ULu, X + (long long)sp * L * kMaxK,
                   Y + (long long)sp * kMaxK * L);
   __syncthreads();
   const long long t2 = wall_clock64();
   char* un = ch.scratch + kSmall;
 #pragma unroll 1
-  for (int sp = 0; sp < 2; ++sp)
+  for (int sp = 0; sp < nsp; ++sp)
     flush_gemm<MIXED>(sp ? ch.Gd : ch.Gu, X + (long long)sp * L * kMaxK,
                       Y + (long long)sp * kMaxK * L, L, m, un, ch.scratch_bytes - kSmall);
   __syncthreads();
@@ -1875,14 +1933,16 @@ __device__ __forceinline__ int sweep_window(const SweepParams& p, const Chain& c
   double* Yrec = Xrec + 2 * kMaxK * kWin;
   int m = 0, m_inv = 0;          // pending flips; those already in T and S
   int l0 = l_begin;
+  const bool ph = p.ph != 0;     // G_up only; G_dn = 1 - G_up^T
+  const int nsp = ph ? 1 : 2;
   while (l0 < L) {
     const int b = min(kWin, L - l0);
     fill_uniforms(ch.uw, ch.key0, (uint64_t)ch.grid, sw, l0, b);
     if (m > 0) {
       const long long t0 = wall_clock64();
-      invert_ts(w, m_inv, m);
+      invert_ts(w, m_inv, m, nsp);
       m_inv = m;
-      window_apply(ch, w, l0, b, m);
+      window_apply(ch, w, l0, b, m, nsp);
       if (t == 0) ch.st[ST_T_FLUSH] += wall_clock64() - t0;
     } else {
       for (int idx = t; idx < kWin * kWin; idx += kThreads) {
@@ -1890,7 +1950,7 @@ __device__ __forceinline__ int sweep_window(const SweepParams& p, const Chain& c
         if (q < b && r < b) {
           const long long o = (long long)(l0 + q) * L + l0 + r;
           w.Wu[q * kWP + r] = ch.Gu[o];
-          w.Wd[q * kWP + r] = ch.Gd[o];
+          if (!ph) w.Wd[q * kWP + r] = ch.Gd[o];
         }
       }
       __syncthreads();
@@ -1901,7 +1961,8 @@ __device__ __forceinline__ int sweep_window(const SweepParams& p, const Chain& c
     while (pos < b && !close) {
       const int l = l0 + pos;
       const int sl = ch.s[l];
-      const Flip f = propose(w.Wu[pos * kWP + pos], w.Wd[pos * kWP + pos], sl, io.gp, io.gm,
+      const double wul = w.Wu[pos * kWP + pos];
+      const Flip f = propose(wul, ph ? 1.0 - wul : w.Wd[pos * kWP + pos], sl, io.gp, io.gm,
                              ch.uw[pos], io.rlog, io.rlen, sw * L + l, k, ch.st, io.hb);
       if (f.accept) {
         log_flip(io, ch.st, sw * L + l);
@@ -1916,12 +1977,12 @@ __device__ __forceinline__ int sweep_window(const SweepParams& p, const Chain& c
           const double v = mul_nc(cu, w.Wu[pos * kWP + r]);
           w.yu[r] = v;
           Yrec[(0 * kMaxK + m) * kWin + r] = v;
-        } else if (t >= 128 && t < 128 + b) {
+        } else if (!ph && t >= 128 && t < 128 + b) {
           const int q = t - 128;
           const double v = w.Wd[q * kWP + pos] - (q == pos ? 1.0 : 0.0);
           w.xd[q] = v;
           Xrec[(1 * kMaxK + m) * kWin + q] = v;
-        } else if (t >= 192 && t < 192 + b) {
+        } else if (!ph && t >= 192 && t < 192 + b) {
           const int r = t - 192;
           const double v = mul_nc(cd, w.Wd[pos * kWP + r]);
           w.yd[r] = v;
@@ -1937,7 +1998,7 @@ __device__ __forceinline__ int sweep_window(const SweepParams& p, const Chain& c
           const int q = idx >> 6, r = idx & 63;
           if (q < b && r < b) {
             w.Wu[q * kWP + r] = axpy_nc(w.Wu[q * kWP + r], w.xu[q], w.yu[r]);
-            w.Wd[q * kWP + r] = axpy_nc(w.Wd[q * kWP + r], w.xd[q], w.yd[r]);
+            if (!ph) w.Wd[q * kWP + r] = axpy_nc(w.Wd[q * kWP + r], w.xd[q], w.yd[r]);
           }
         }
         if (t == 0) ch.s[l] = (int8_t)(-sl);
@@ -1951,14 +2012,14 @@ __device__ __forceinline__ int sweep_window(const SweepParams& p, const Chain& c
     l0 += pos;
     if (m > m0) {
       const long long t0 = wall_clock64();
-      capture_coefficients(ch, w, l0 - pos, m0, m);
+      capture_coefficients(ch, w, l0 - pos, m0, m, nsp);
       if (t == 0) ch.st[ST_T_FLUSH] += wall_clock64() - t0;
     }
     // flush at delay_k pending, before a recompute and at the sweep end
     if (m > 0 && (close || l0 >= L)) {
       const long long t0 = wall_clock64();
-      invert_ts(w, m_inv, m);
-      flush_pending<MIXED>(ch, w, m);
+      invert_ts(w, m_inv, m, nsp);
+      flush_pending<MIXED>(ch, w, m, nsp);
       if (t == 0) {
         ch.st[ST_T_FLUSH] += wall_clock64() - t0;
         ch.st[ST_FLUSHES] += 1;
@@ -2062,7 +2123,7 @@ __device__ __forceinline__ void run_chain(const SweepParams& p, const GridDev* g
         const long long t1 = wall_clock64();
         const long long msw = sw - p.warmup;
         const int bin = (int)((msw * nb) / p.sweeps);
-        measure(ch, bin);
+        measure(ch, bin, p.ph != 0);
         stat_add(ch.st, ST_T_MEAS, wall_clock64() - t1);
       }
       __syncthreads();
@@ -2094,7 +2155,12 @@ __device__ __forceinline__ void run_chain(const SweepParams& p, const GridDev* g
     double* out = gd->g_final + (long long)chain * 2 * L2;
     for (long long idx = threadIdx.x; idx < L2; idx += kThreads) {
       out[idx] = ch.Gu[idx];
-      out[L2 + idx] = ch.Gd[idx];
+      if (p.ph) {
+        const long long i = idx / L, j = idx - i * L;   // G_dn(i, j) = delta_ij - G_up(j, i)
+        out[L2 + idx] = (i == j ? 1.0 : 0.0) - ch.Gu[j * L + i];
+      } else {
+        out[L2 + idx] = ch.Gd[idx];
+      }
     }
   }
   __syncthreads();
