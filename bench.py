@@ -383,7 +383,7 @@ def main():
                  % three["l400_equiv_sweeps_per_s"])
     add_measured_peaks(rf, peaks)
     add_measured_peaks(rf["secondary"], peaks)
-    ph = None
+    phv = None
     if not args.no_extra and args.mode != "rank1":
         # the same workload through the particle-hole symmetric single-matrix form
         # (the bath is symmetric): G_dn = 1 - G_up^T, one matrix updated and recomputed
@@ -396,7 +396,7 @@ def main():
         add_measured_peaks(rph, peaks)
         add_measured_peaks(rph["secondary"], peaks)
         gp_ = g_d.cpu().numpy()
-        ph = dict(sweeps_per_s=chain_sweeps / sp["seconds_kernel"], kernel_s=sp["seconds_kernel"],
+        phv = dict(sweeps_per_s=chain_sweeps / sp["seconds_kernel"], kernel_s=sp["seconds_kernel"],
                   speedup_vs_two_matrix=t_k / sp["seconds_kernel"], delay_k=sp["delay_k"],
                   lu_panel=sp["lu_panel"], acc_rate=sp["acc_rate"], max_drift=sp["max_drift"],
                   docc=float(d_d.cpu().numpy()[0]),
@@ -405,7 +405,7 @@ def main():
                                                     "composite_frac")},
                   note="same chains and sweeps; only G_up stored (G_dn = 1 - G_up^T holds for "
                        "a particle-hole symmetric bath); not the headline value")
-        progress("single-matrix (particle-hole symmetric) form: %.0f sweeps/s" % ph["sweeps_per_s"])
+        progress("single-matrix (particle-hole symmetric) form: %.0f sweeps/s" % phv["sweeps_per_s"])
     rank1 = None
     if args.rank1_sweeps > 0 and args.mode != "rank1":
         r = solve("rank1", 0, args.rank1_sweeps)
@@ -458,7 +458,7 @@ def main():
         "phases_chain_s": ph,
         "kernel_sweeps_per_s": chain_sweeps / t_k,
         "measured_peaks": peaks,
-        "ph_single_matrix": ph,
+        "ph_single_matrix": phv,
         "other_workloads": extra or None,
     }
     print(json.dumps(line), flush=True)

@@ -1179,32 +1179,44 @@ __device__ __forceinline__ void measure(const Chain& ch, int bin, bool ph) {
   const int L = ch.L;
   double* accg = ch.accg;
   for (int k = threadIdx.x; k < L; k += kThreads) {
-    double acc = 0.0;
-    for (int i = 0; i < L; ++i) {
-      int j = i - k;
-      double sg = 1.0;
-      if (j < 0) {
-        j += L;
-        sg = -1.0;
-      }
-      const long long o = (long long)i * L + j;
-      acc += sg * ch.Gu[o];
-      if (!ph) acc += sg * ch.Gd[o];
-    }
-    if (ph) {
-      double dn = 0.0;
-      for (int j = 0; j < L; ++j) {
-        int i = j + k;
+    // step i: every thread of a wave reads row i (one contiguous stretch):
+    // G(i, i - k), with sign - where i - k wraps
+    double up = 0.0, dn = 0.0;
+    if (!ph) {
+#pragma unroll 8
+      for (int i = 0; i < L; ++i) {
+        int j = i - k;
         double sg = 1.0;
-        if (i >= L) {
-          i -= L;
+        if (j < 0) {
+          j += L;
           sg = -1.0;
         }
-        dn += sg * ch.Gu[(long long)j * L + i];
+        const long long o = (long long)i * L + j;
+        up += sg * ch.Gu[o];
+        dn += sg * ch.Gd[o];
       }
-      acc += (k == 0 ? (double)L : 0.0) - dn;
+    } else {
+      // and G_up(i, i + k), with sign - where i + k wraps, for the spin-down term
+      double tr = 0.0;
+#pragma unroll 8
+      for (int i = 0; i < L; ++i) {
+        int j = i - k, j2 = i + k;
+        double sg = 1.0, sg2 = 1.0;
+        if (j < 0) {
+          j += L;
+          sg = -1.0;
+        }
+        if (j2 >= L) {
+          j2 -= L;
+          sg2 = -1.0;
+        }
+        const double* row = ch.Gu + (long long)i * L;
+        up += sg * row[j];
+        tr += sg2 * row[j2];
+      }
+      dn = (k == 0 ? (double)L : 0.0) - tr;
     }
-    const double val = acc / (2.0 * L);
+    const double val = (up + dn) / (2.0 * L);
     const long long base = (long long)bin * (L + 1);
     accg[base + k] += val;
     if (k == 0) accg[base + L] += 1.0 - val;
@@ -1455,9 +1467,10 @@ constexpr int kCT = kCW / 16;
 constexpr int kYK = kMaxK + 4;   // LDS stride of a staged Y column
 
 template <bool MIXED>
-__device__ __forceinline__ void flush_gemm(double* __restrict__ G, const double* __restrict__ X,
-                                           const double* __restrict__ Y, int L, int m,
-                                           char* __restrict__ ybuf, int ybytes) {
+__device__ __forceinline__ void flush_gemm(
+    double* __restrict__ G, const typename std::conditional<MIXED, float, double>::type* __restrict__ X,
+    const typename std::conditional<MIXED, float, double>::type* __restrict__ Y, int L, int m,
+    char* __restrict__ ybuf, int ybytes) {
   typedef typename std::conditional<MIXED, float, double>::type T;
   typedef T Tx4 __attribute__((ext_vector_type(4)));
   constexpr int KS = kMaxK / 4;
@@ -1482,16 +1495,16 @@ __device__ __forceinline__ void flush_gemm(double* __restrict__ G, const double*
     // a wave per Y row, four rows in flight; lanes along the panel
     for (int k0 = wv; k0 < rows; k0 += 4 * (kThreads / 64)) {
       for (int c = lane; c < pw; c += 64) {
-        double v[4];
+        T v[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int kk = k0 + u * (kThreads / 64);
-          v[u] = (kk < m && c < w) ? Y[kk * L + c0 + c] : 0.0;
+          v[u] = (kk < m && c < w) ? Y[kk * L + c0 + c] : (T)0;
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int kk = k0 + u * (kThreads / 64);
-          if (kk < rows) Yl[c * kYK + kk] = (T)v[u];
+          if (kk < rows) Yl[c * kYK + kk] = v[u];
         }
       }
     }
@@ -1525,8 +1538,8 @@ __device__ __forceinline__ void flush_gemm(double* __restrict__ G, const double*
 #pragma unroll
         for (int q = 0; q < KS; ++q) {
           const int kk = 4 * q + lq;
-          const double v = X[arow * kMaxK + kk];
-          a[q] = (arow_ok && kk < m) ? (T)v : (T)0;
+          const T v = X[arow * kMaxK + kk];
+          a[q] = (arow_ok && kk < m) ? v : (T)0;
         }
       }
       Tx4 acc[kCT];
@@ -1581,11 +1594,13 @@ __device__ __forceinline__ void flush_gemm(double* __restrict__ G, const double*
 // where W = T S (m x m, in LDS with row stride kKP) folds both triangular
 // factors of the delayed update into the right factor (f_i = l0 + F[i]).
 // Y on the matrix cores (FP64) in wave-independent 16 x 16 tiles whose G rows
-// are loaded one tile ahead.
+// are loaded one tile ahead.  X and Y are stored in the product's operand
+// type T (FP32 in the mixed path: the product rounds them to FP32 anyway).
+template <typename T>
 __device__ __forceinline__ void flush_vectors(const double* __restrict__ G, int L, int l0, int m,
                                               const int* __restrict__ F,
                                               const double* __restrict__ W,
-                                              double* __restrict__ X, double* __restrict__ Y) {
+                                              T* __restrict__ X, T* __restrict__ Y) {
   constexpr int KS = kMaxK / 4;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int li = lane & 15, lq = lane >> 4;
@@ -1605,7 +1620,7 @@ __device__ __forceinline__ void flush_vectors(const double* __restrict__ G, int 
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int q = q0 + u * (kThreads / 64);
-        if (q < L && lane < m) X[q * kMaxK + lane] = v[u];
+        if (q < L && lane < m) X[q * kMaxK + lane] = (T)v[u];
       }
     }
   }
@@ -1635,7 +1650,7 @@ __device__ __forceinline__ void flush_vectors(const double* __restrict__ G, int 
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int jj = jb * 16 + 4 * r + lq;
-      if (jj < m && cb * 16 + li < L) Y[jj * L + cb * 16 + li] = acc[r];
+      if (jj < m && cb * 16 + li < L) Y[jj * L + cb * 16 + li] = (T)acc[r];
     }
   };
   double b0[KS], b1[KS];
@@ -1900,9 +1915,10 @@ __device__ __forceinline__ void capture_coefficients(const Chain& ch, const WinL
 // or to G_up alone (nsp = 1).
 template <bool MIXED>
 __device__ __forceinline__ void flush_pending(const Chain& ch, const WinLds& w, int m, int nsp) {
+  typedef typename std::conditional<MIXED, float, double>::type T;
   const int L = ch.L;
-  double* X = ch.wbuf + 4 * kMaxK * kWin;             // [2][L][kMaxK]
-  double* Y = X + 2LL * L * kMaxK;                    // [2][kMaxK][L]
+  T* X = reinterpret_cast<T*>(ch.wbuf + 4 * kMaxK * kWin);   // [2][L][kMaxK]
+  T* Y = X + 2LL * L * kMaxK;                                 // [2][kMaxK][L]
   const long long t1 = wall_clock64();
   flush_fold(w.ULu, w.ULd, m, nsp);
 #pragma unroll 1
