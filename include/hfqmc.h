@@ -223,6 +223,25 @@ int dmft_bethe_step(const double *g_fine, int32_t n_fine, const double *bath_iw_
                     int32_t n_iw, double bath_m3, double U, double beta, double t,
                     double *bath_iw_new);
 
+/* The multigrid DMFT cycle on the Bethe lattice (Fig. 1(c): impurity solve
+ * on several grids, dtau -> 0 extrapolation, self-consistency), n_iter times:
+ *   g_fine   = multigrid_solve(bath, dtaus, seed + (it << 32), opts)
+ *   bath_new = 1/(i w - t^2 G(i w))          (dmft_bethe_step)
+ *   bath     = mixing * bath + (1 - mixing) * bath_new,  0 <= mixing < 1.
+ * bath_iw[2 n_iw] holds the starting bath on entry (e.g. bethe_semicircle_bath,
+ * the U = 0 solution) and the last bath on return; its 1/(i w)^3 moment is t^2
+ * throughout (the Bethe closure keeps it).  g_fine[n_fine] (and g_fine_err,
+ * or NULL) is the last iteration's extrapolated G(tau_j), tau_j =
+ * j beta/(n_fine-1).  history[2 n_iter] (or NULL): per iteration, the largest
+ * |g_fine - g_fine of the previous iteration| (for the first, against the
+ * starting bath's G0(tau_j)) and the largest error bar of g_fine.  Each
+ * iteration draws fresh Philox streams.  Errors as multigrid_solve; EINVAL for
+ * n_iter < 1, mixing outside [0, 1), t <= 0. */
+int dmft_solve(hfqmc_ctx *ctx, double U, double beta, double t, const double *dtaus,
+               int32_t n_grids, uint64_t seed, const hfqmc_opts *opts, int32_t n_fine,
+               int32_t n_iw, int32_t n_iter, double mixing, double *bath_iw, double *g_fine,
+               double *g_fine_err, double *history);
+
 /* U = 0 starting bath: Bethe-lattice local Green function, half-bandwidth 2t. */
 int bethe_semicircle_bath(double beta, double t, int32_t n_iw, double *bath_iw);
 

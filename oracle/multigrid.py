@@ -146,3 +146,27 @@ def dmft_bethe_step(g_fine, tau_fine, bath_iw, m3, U, beta, t):
     """One Bethe-lattice self-consistency step: the new bath on the same frequencies."""
     g_iw = g_tau_to_iw(g_fine, tau_fine, bath_iw, m3, U, beta)
     return B.bethe_step_iw(g_iw, beta, t)
+
+
+def dmft_loop(bath_iw, U, beta, t, dtaus, seed, n_iter, n_chains, warmup, sweeps, n_rec=100,
+              n_fine=200, mixing=0.0):
+    """The DMFT cycle of Fig. 1(c) on the Bethe lattice, n_iter times: a multigrid
+    impurity solve at the current bath (fresh random streams per iteration: the
+    seed moves by 2^32), then the closure Bath_new = 1/(i w - t^2 G(i w)), mixed
+    as mixing * old + (1 - mixing) * new.  The bath's 1/(i w)^3 moment stays t^2.
+    history[it] = (max |g - g_prev|, max g_err), g_prev of the first iteration
+    being the starting bath's own G0(tau_j)."""
+    m3 = t * t
+    bath = np.asarray(bath_iw, dtype=np.complex128).copy()
+    tau_f = fine_grid(beta, n_fine)
+    prev = reference_tau(bath, m3, 0.0, beta, tau_f)
+    hist = []
+    r = None
+    for it in range(n_iter):
+        r = multigrid_solve(bath, m3, U, beta, dtaus, seed + (it << 32), n_chains, warmup, sweeps,
+                            n_rec=n_rec, n_fine=n_fine)
+        hist.append((float(np.abs(r["g"] - prev).max()), float(r["g_err"].max())))
+        prev = r["g"]
+        new = dmft_bethe_step(r["g"], r["tau"], bath, m3, U, beta, t)
+        bath = mixing * bath + (1.0 - mixing) * new
+    return dict(bath=bath, g=r["g"], g_err=r["g_err"], tau=tau_f, history=np.array(hist))

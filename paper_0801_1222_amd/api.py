@@ -6,6 +6,7 @@
   out = hfqmc_solve_grids(ctx, Ls, [g0_tau_i], U, beta, seed, ...)
   out = multigrid_solve(ctx, bath_iw, m3, U, beta, dtaus, seed, n_fine, ...)
   new_bath = dmft_bethe_step(g_fine, bath_iw, m3, U, beta, t)
+  out = dmft_solve(ctx, U, beta, t, dtaus, seed, n_iter, ...)        # the whole DMFT cycle
   peaks = hfqmc_measure_peaks(ctx)                                    # achievable peaks
 """
 import ctypes as C
@@ -260,6 +261,31 @@ def multigrid_solve(ctx, bath_iw, bath_m3, U, beta, dtaus, seed, n_fine=200, n_c
         off += L + 1
     return dict(g=gf, g_err=ef, tau=np.arange(n_fine) * (beta / (n_fine - 1)), Ls=Ls,
                 g_grids=grids, stats=[st[i].as_dict() for i in range(len(Ls))])
+
+
+def dmft_solve(ctx, U, beta, t, dtaus, seed, n_iter, bath_iw=None, n_iw=4096, n_fine=200,
+               mixing=0.0, n_chains=1, warmup=0, sweeps=1, mode="rank1", recompute_every=0,
+               delay_k=0, n_bins=0, drift_limit=0.0, eager=False, heat_bath=False, direct=False,
+               ph=False):
+    """Multigrid DMFT cycle on the Bethe lattice; starts from bath_iw (default:
+    the U = 0 semicircle).  Returns dict(bath, g, g_err, tau, history) with
+    history[it] = (max |g - g_prev|, max g_err)."""
+    if bath_iw is None:
+        bath_iw = bethe_semicircle_bath(beta, t, n_iw)
+    b = np.ascontiguousarray(np.asarray(bath_iw, dtype=np.complex128)).copy().view(np.float64)
+    n_iw = b.shape[0] // 2
+    dt = np.ascontiguousarray(dtaus, dtype=np.float64)
+    o = _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drift_limit,
+              _flags(eager, heat_bath, direct, ph))
+    gf = np.zeros(n_fine)
+    ef = np.zeros(n_fine)
+    hist = np.zeros(2 * int(n_iter))
+    rc = N.lib.dmft_solve(ctx.handle, float(U), float(beta), float(t), N.ptr(dt), dt.shape[0],
+                          int(seed), C.byref(o), int(n_fine), n_iw, int(n_iter), float(mixing),
+                          N.ptr(b), N.ptr(gf), N.ptr(ef), N.ptr(hist))
+    N.check(rc, "dmft_solve")
+    return dict(bath=b.view(np.complex128), g=gf, g_err=ef,
+                tau=np.arange(n_fine) * (beta / (n_fine - 1)), history=hist.reshape(-1, 2))
 
 
 def dmft_bethe_step(g_fine, bath_iw_prev, bath_m3, U, beta, t):

@@ -901,3 +901,46 @@ extern "C" int dmft_bethe_step(const double* g_fine, int32_t n_fine, const doubl
     if (!std::isfinite(g_fine[j])) return fail(HFQMC_EINVAL, "dmft_bethe_step: g_fine[%d] not finite", j);
   return host::bethe_step(g_fine, n_fine, bath_iw_prev, n_iw, bath_m3, U, beta, t, bath_iw_new);
 }
+
+extern "C" int dmft_solve(hfqmc_ctx* c, double U, double beta, double t, const double* dtaus,
+                          int32_t n_grids, uint64_t seed, const hfqmc_opts* opts, int32_t n_fine,
+                          int32_t n_iw, int32_t n_iter, double mixing, double* bath_iw,
+                          double* g_fine, double* g_fine_err, double* history) {
+  if (!bath_iw || !g_fine || !dtaus || !opts) return fail(HFQMC_EINVAL, "dmft_solve: null pointer");
+  if (n_iter < 1) return fail(HFQMC_EINVAL, "dmft_solve: n_iter=%d", n_iter);
+  if (!(mixing >= 0.0 && mixing < 1.0)) return fail(HFQMC_EINVAL, "dmft_solve: mixing=%g", mixing);
+  if (!(t > 0)) return fail(HFQMC_EINVAL, "dmft_solve: t=%g", t);
+  if (n_fine < 4 || n_iw < 16) return fail(HFQMC_EINVAL, "dmft_solve: n_fine=%d n_iw=%d", n_fine, n_iw);
+  // the Bethe closure keeps the bath's 1/(i w)^3 moment at t^2
+  const double m3 = t * t;
+  std::vector<double> prev(n_fine), err(n_fine), nb(2 * (size_t)n_iw);
+  {
+    // distance of the first iteration: to the input bath's own G0(tau_j)
+    std::vector<double> tf(n_fine);
+    for (int j = 0; j < n_fine; ++j) tf[j] = j * (beta / (n_fine - 1));
+    host::reference_tau(bath_iw, n_iw, m3, 0.0, beta, tf.data(), n_fine, prev.data());
+  }
+  for (int it = 0; it < n_iter; ++it) {
+    // independent Philox streams per iteration: the seed moves by 2^32 (chain keys
+    // are seed + chain with fewer than 2^20 chains)
+    const uint64_t s_it = seed + ((uint64_t)it << 32);
+    int rc = multigrid_solve(c, bath_iw, n_iw, m3, U, beta, dtaus, n_grids, s_it, opts, n_fine,
+                             g_fine, err.data(), nullptr, nullptr);
+    if (rc) return rc;
+    double dmax = 0.0, emax = 0.0;
+    for (int j = 0; j < n_fine; ++j) {
+      dmax = std::max(dmax, std::fabs(g_fine[j] - prev[j]));
+      emax = std::max(emax, err[j]);
+      prev[j] = g_fine[j];
+    }
+    if (history) {
+      history[2 * it] = dmax;
+      history[2 * it + 1] = emax;
+    }
+    rc = host::bethe_step(g_fine, n_fine, bath_iw, n_iw, m3, U, beta, t, nb.data());
+    if (rc) return fail(rc, "dmft_solve: Bethe step failed in iteration %d", it);
+    for (size_t q = 0; q < nb.size(); ++q) bath_iw[q] = mixing * bath_iw[q] + (1.0 - mixing) * nb[q];
+  }
+  if (g_fine_err) std::memcpy(g_fine_err, err.data(), sizeof(double) * n_fine);
+  return HFQMC_OK;
+}

@@ -1,0 +1,77 @@
+"""GPU tests of the multigrid DMFT cycle (dmft_solve) on the Bethe lattice.
+
+* U = 0: the semicircle is a fixed point of the whole cycle.
+* Parity: the C-ABI cycle against the oracle's cycle (same Philox streams per
+  iteration, FP64 rank-1 updates): identical arithmetic up to rounding.
+* Self-consistency at U > 0 (reduced statistics): the iteration-to-iteration
+  change falls to the statistical noise, and the dtau -> 0 result at the
+  converged bath does not depend on which range of dtau is extrapolated
+  (within the combined error bars), the behaviour the multigrid method rests
+  on (section "Multigrid HF-QMC method", benchmark section).
+"""
+import numpy as np
+import pytest
+
+from oracle import bath as OB
+from oracle import multigrid as OM
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch  # noqa: F401  (PyTorch's runtime comes up before the library's)
+    import paper_0801_1222_amd as P
+    c = P.Context(0)
+    yield c
+    c.close()
+
+
+def test_dmft_u0_semicircle_is_fixed_point(ctx):
+    import paper_0801_1222_amd as P
+    beta, t = 10.0, 1.0
+    bath = P.bethe_semicircle_bath(beta, t, 4000)
+    out = P.dmft_solve(ctx, 0.0, beta, t, [0.5, 0.4, 0.25], 1, 2, bath_iw=bath, n_chains=2,
+                       warmup=1, sweeps=2)
+    assert np.abs(out["bath"] - bath).max() < 1e-10
+    assert out["history"][0][0] < 1e-12 and out["history"][1][0] < 1e-10
+
+
+@pytest.mark.parametrize("ph", [False, True])
+def test_dmft_cycle_matches_oracle(ctx, ph):
+    import paper_0801_1222_amd as P
+    beta, U, t, seed = 4.0, 4.0, 1.0, 7
+    dtaus = [0.5, 0.4, 0.25]
+    bath = OB.semicircle_iw(beta, t, 2000)
+    out = P.dmft_solve(ctx, U, beta, t, dtaus, seed, 2, bath_iw=bath, n_fine=81, n_chains=3,
+                       warmup=5, sweeps=40, mode="rank1", ph=ph)
+    ref = OM.dmft_loop(bath, U, beta, t, dtaus, seed, 2, n_chains=3, warmup=5, sweeps=40,
+                       n_fine=81)
+    assert np.abs(out["g"] - ref["g"]).max() < 1e-9
+    assert np.abs(out["g_err"] - ref["g_err"]).max() < 1e-9
+    assert np.abs(out["bath"] - ref["bath"]).max() < 1e-9
+    assert np.abs(out["history"] - ref["history"]).max() < 1e-9
+
+
+def test_dmft_converges_and_is_grid_range_insensitive(ctx):
+    import paper_0801_1222_amd as P
+    beta, U, t, seed = 10.0, 2.5, 1.0, 11
+    range_a = [0.4, 1.0 / 3.0, 0.25, 0.2]           # L = 25, 30, 40, 50
+    range_b = [1.0 / 3.0, 2.0 / 7.0, 0.2, 1.0 / 6.0]  # L = 30, 35, 50, 60
+    kw = dict(n_chains=64, warmup=50, sweeps=400, mode="delayed", delay_k=16, ph=True)
+    out = P.dmft_solve(ctx, U, beta, t, range_a, seed, 6, n_fine=101, **kw)
+    h = out["history"]
+    # the first step moves far from the U = 0 bath; the last change is noise
+    # (the largest of 101 differences of two independent estimates)
+    assert h[0][0] > 20 * h[0][1]
+    assert h[-1][0] < 8 * h[-1][1]
+    bath = out["bath"]
+    assert np.abs(bath.real).max() < 1e-10           # particle-hole symmetry kept
+    # both dtau ranges extrapolated at the converged bath agree within errors
+    a = P.multigrid_solve(ctx, bath, t * t, U, beta, range_a, seed + 99, n_fine=101, **kw)
+    b = P.multigrid_solve(ctx, bath, t * t, U, beta, range_b, seed + 199, n_fine=101, **kw)
+    # (neighbouring fine-grid points share their grid data: deviations come in
+    # smooth excursions, so the bar is on the largest one and their share)
+    s = np.sqrt(a["g_err"] ** 2 + b["g_err"] ** 2)[1:-1]
+    z = np.abs(a["g"] - b["g"])[1:-1] / s
+    assert z.max() < 4.5 and np.mean(z > 3.0) <= 0.1, (z.max(), np.mean(z > 3.0), np.mean(z))

@@ -67,3 +67,31 @@ def test_atomic_limit_multigrid_within_errors():
     exact = H.atomic_limit_g(U, beta, out["tau"])
     z = np.abs(out["g"] - exact)[1:-1] / out["g_err"][1:-1]
     assert z.max() < 4.0
+
+
+def test_dmft_loop_u0_semicircle_is_fixed_point():
+    # U = 0: every grid returns the bath exactly, the extrapolation and the
+    # reference model are exact, and the semicircle solves the Bethe closure
+    beta, t = 10.0, 1.0
+    bath = B.semicircle_iw(beta, t, 4000)
+    out = MG.dmft_loop(bath, 0.0, beta, t, [0.5, 0.4, 0.25], seed=1, n_iter=2, n_chains=2,
+                       warmup=1, sweeps=2, n_fine=200)
+    assert out["history"][0][0] < 1e-12           # G(tau) is the bath's own G0(tau)
+    assert np.abs(out["bath"] - bath).max() < 1e-10
+    # the second iteration starts from that bath: still self-consistent
+    assert out["history"][1][0] < 1e-10
+
+
+def test_dmft_loop_keeps_particle_hole_symmetry():
+    # the estimator averages both spins, so G(tau) = G(beta - tau) for every
+    # sample; the closure of a symmetric G is a purely imaginary bath
+    beta, U, t = 4.0, 4.0, 1.0
+    bath = B.semicircle_iw(beta, t, 2000)
+    out = MG.dmft_loop(bath, U, beta, t, [0.5, 0.4, 0.25], seed=3, n_iter=1, n_chains=2,
+                       warmup=5, sweeps=40, n_fine=81)
+    g = out["g"]
+    assert np.abs(g - g[::-1]).max() < 1e-10
+    assert np.abs(out["bath"].real).max() < 1e-10
+    assert np.all(out["bath"].imag < 0)
+    # an interacting bath moved away from the semicircle
+    assert np.abs(out["bath"] - bath).max() > 1e-3
