@@ -427,7 +427,8 @@ def main():
     ph = {k: st[k] for k in ("chain_s_sweep", "chain_s_flush", "chain_s_recompute",
                              "chain_s_measure", "chain_s_lu_build", "chain_s_lu_panel",
                              "chain_s_lu_strip", "chain_s_lu_back", "chain_s_lu_gemm",
-                             "chain_s_flush_vectors", "chain_s_flush_gemm")}
+                             "chain_s_flush_vectors", "chain_s_flush_gemm",
+                             "chain_s_window_apply", "chain_s_fold")}
     line = {
         "metric": "HF-QMC sweeps/s (all chains, L=400)",
         "value": value,

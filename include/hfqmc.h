@@ -136,6 +136,9 @@ typedef struct {
   int32_t reserved;
   double chain_s_lu_gemm;   /* recompute breakdown: the reduced form's GEMM (chain-seconds) */
   double chain_s_flush_vectors, chain_s_flush_gemm;  /* flush breakdown: X, Y and G += X Y */
+  /* delayed-update breakdown (chain-seconds, part of chain_s_flush): opening a
+     window with flips pending, and completing T, S and W = T S before a flush */
+  double chain_s_window_apply, chain_s_fold;
 } hfqmc_stats;
 
 /* Fixed-dtau solve: hfqmc_solve(G0(tau), U, beta, dtau, sweeps, seed) -> G(tau).

@@ -662,6 +662,8 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
       gs.chain_s_lu_gemm += s[ST_T_LU_GEMM] * f;
       gs.chain_s_flush_vectors += s[ST_T_FL_VEC] * f;
       gs.chain_s_flush_gemm += s[ST_T_FL_GEMM] * f;
+      gs.chain_s_window_apply += s[ST_T_WAPPLY] * f;
+      gs.chain_s_fold += s[ST_T_FOLD] * f;
       gdrift = std::max(gdrift, cdr[ch]);
       if (!(cdr[ch] == cdr[ch])) gdrift = INFINITY;
       if (opts->flip_count) opts->flip_count[cb + ch] = s[ST_FLIPS];
@@ -696,6 +698,8 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
     tot.chain_s_lu_gemm += gs.chain_s_lu_gemm;
     tot.chain_s_flush_vectors += gs.chain_s_flush_vectors;
     tot.chain_s_flush_gemm += gs.chain_s_flush_gemm;
+    tot.chain_s_window_apply += gs.chain_s_window_apply;
+    tot.chain_s_fold += gs.chain_s_fold;
     max_drift = std::max(max_drift, gdrift);
     const double* gv = call.dev_io ? gcheck.data() : g_tau + goff;
     for (int k = 0; k <= L; ++k)

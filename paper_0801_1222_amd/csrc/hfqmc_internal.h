@@ -27,7 +27,9 @@ enum {
   ST_T_LU_GEMM = 17,   // recompute breakdown: the reduced form's GEMM for the rows outside S
   ST_T_FL_VEC = 18,    // flush breakdown: the full update vectors X, Y
   ST_T_FL_GEMM = 19,   // ... the rank-m product G += X Y
-  NSTAT = 20
+  ST_T_WAPPLY = 20,    // ... opening windows with flips pending (T, S update and window blocks)
+  ST_T_FOLD = 21,      // ... T, S completion and W = T S before a flush
+  NSTAT = 22
 };
 
 enum { MODE_RANK1 = 0, MODE_DELAYED_FP64 = 1, MODE_MIXED = 2 };

@@ -157,6 +157,7 @@ typedef __attribute__((address_space(1))) double gdouble;
 typedef __attribute__((address_space(1))) const double gcdouble;
 
 constexpr int kStatBytes = 256;   // LDS statistics block: NSTAT counters + drift
+static_assert(NSTAT * 8 + 8 <= kStatBytes, "statistics block too small");
 constexpr int kUW = 64;           // acceptance uniforms held in LDS at a time
 
 // Acceptance uniforms u(l, sweep) (stream 0) of slices l0 .. l0 + n - 1 into uw.
@@ -718,7 +719,8 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* red, int* total)
     before += (w < wv) ? r : 0;
     tot += r;
   }
-  *total = tot;
+  // the same in every lane: made uniform for the compiler (scalar control flow)
+  *total = __builtin_amdgcn_readfirstlane(tot);
   return before + x - v;
 }
 
@@ -1260,13 +1262,17 @@ __device__ __forceinline__ Flip propose(double gul, double gdl, int sl, double g
     st[ST_PROPOSED] += 1;
     st[ST_BAD] += bad ? 1 : 0;
   }
+  bool acc;
   if (rlog) {
-    f.accept = k.rep_i < rlen && rlog[k.rep_i] == code;
-    k.rep_i += f.accept ? 1 : 0;
+    acc = k.rep_i < rlen && rlog[k.rep_i] == code;
   } else {
     // Metropolis min(1, R), or heat bath R / (1 + R)
-    f.accept = !bad && (hb ? u < R / (1.0 + R) : u < R);
+    acc = !bad && (hb ? u < R / (1.0 + R) : u < R);
   }
+  // every thread evaluates the same decision from the same values: stating it
+  // as uniform keeps the sweep's control flow (and the counters) scalar
+  f.accept = __builtin_amdgcn_readfirstlane(acc ? 1 : 0) != 0;
+  if (rlog) k.rep_i += f.accept ? 1 : 0;
   return f;
 }
 
@@ -1688,12 +1694,14 @@ __device__ __forceinline__ void flush_fold(double* __restrict__ TSu, double* __r
       const double* TS = sp ? TSd : TSu;
       const int i = ib * 16 + li;          // A row (of T)
       const int j = jb * 16 + li;          // B column (of S)
-#pragma unroll 1
+#pragma unroll 4
       for (int s4 = 0; s4 < ks; ++s4) {
         const int k = 4 * s4 + lq;
-        double a = 0.0, b = 0.0;
-        if (i < m && k < m) a = (k > i) ? TS[i * kKP + k] : (k == i ? 1.0 : 0.0);
-        if (j < m && k < m && k >= j) b = TS[k * kKP + j];
+        // unconditional LDS reads at clamped indices, then masked
+        const int ic = min(i, kMaxK - 1), jc = min(j, kMaxK - 1), kc = min(k, kMaxK - 1);
+        const double ta = TS[ic * kKP + kc], tb = TS[kc * kKP + jc];
+        const double a = (i < m && k < m) ? ((k > i) ? ta : (k == i ? 1.0 : 0.0)) : 0.0;
+        const double b = (j < m && k < m && k >= j) ? tb : 0.0;
         acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[u], 0, 0, 0);
       }
     }
@@ -1768,7 +1776,8 @@ __device__ __forceinline__ void invert_ts(const WinLds& w, int m_inv, int m, int
       for (int j = max(m_inv, 1); j < m; ++j) {
         if (r < j) {
           double acc = UL[r * kKP + j];
-#pragma unroll 1
+          // (unrolled: the LDS reads of several terms are in flight together)
+#pragma unroll 8
           for (int i = r + 1; i < j; ++i) acc = fma(UL[r * kKP + i], UL[i * kKP + j], acc);
           UL[r * kKP + j] = acc;
         }
@@ -1782,7 +1791,7 @@ __device__ __forceinline__ void invert_ts(const WinLds& w, int m_inv, int m, int
       for (int j = max(m_inv, 1); j < m; ++j) {
         if (c < j) {
           double acc = 0.0;
-#pragma unroll 1
+#pragma unroll 8
           for (int i = c; i < j; ++i) acc = fma(UL[j * kKP + i], UL[i * kKP + c], acc);
           UL[j * kKP + c] = cc[j] * acc;
         }
@@ -1820,12 +1829,20 @@ __device__ __forceinline__ void window_apply(const Chain& ch, const WinLds& w, i
       const int rb = e / mb, jb = e - rb * mb;
       const int q = l0 + min(rb * 16 + li, b - 1);
       const int j = jb * 16 + li;
-#pragma unroll 1
-      for (int s4 = 0; s4 < ks; ++s4) {
-        const int i = 4 * s4 + lq;
-        const int fi = w.F[min(i, m - 1)];
+      // every k-step's gathered G value is loaded before the products start
+      // (unconditional loads at clamped, in-bounds indices)
+      double gv[kMaxK / 4];
+#pragma unroll
+      for (int s4 = 0; s4 < kMaxK / 4; ++s4) {
+        const int fi = w.F[min(4 * s4 + lq, m - 1)];
         const double g = G[q * L + fi];
-        const double a = (i < m) ? g - (q == fi ? 1.0 : 0.0) : 0.0;
+        gv[s4] = (s4 < ks) ? g - (q == fi ? 1.0 : 0.0) : 0.0;
+      }
+#pragma unroll
+      for (int s4 = 0; s4 < kMaxK / 4; ++s4) {
+        if (s4 >= ks) break;
+        const int i = 4 * s4 + lq;
+        const double a = (i < m) ? gv[s4] : 0.0;
         const double tv = TS[min(i, kMaxK - 1) * kKP + min(j, kMaxK - 1)];
         const double bv = (i < m && j < m) ? (i < j ? tv : (i == j ? 1.0 : 0.0)) : 0.0;
         acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc, 0, 0, 0);
@@ -1841,13 +1858,19 @@ __device__ __forceinline__ void window_apply(const Chain& ch, const WinLds& w, i
       const int jb = e2 / 4, cb = e2 - jb * 4;
       const int jr = jb * 16 + li;
       const int col = l0 + min(cb * 16 + li, b - 1);
-#pragma unroll 1
-      for (int s4 = 0; s4 < ks; ++s4) {
+      double gv[kMaxK / 4];
+#pragma unroll
+      for (int s4 = 0; s4 < kMaxK / 4; ++s4) {
+        const double g = G[w.F[min(4 * s4 + lq, m - 1)] * L + col];
+        gv[s4] = (s4 < ks) ? g : 0.0;
+      }
+#pragma unroll
+      for (int s4 = 0; s4 < kMaxK / 4; ++s4) {
+        if (s4 >= ks) break;
         const int i = 4 * s4 + lq;
         const double sv = TS[min(jr, kMaxK - 1) * kKP + min(i, kMaxK - 1)];
         const double a = (jr < m && i < m && i <= jr) ? sv : 0.0;
-        const double g = G[w.F[min(i, m - 1)] * L + col];
-        const double bv = (i < m) ? g : 0.0;
+        const double bv = (i < m) ? gv[s4] : 0.0;
         acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc, 0, 0, 0);
       }
 #pragma unroll
@@ -1873,13 +1896,20 @@ __device__ __forceinline__ void window_apply(const Chain& ch, const WinLds& w, i
       acc[r] = (rr < b && col < b) ? G[(l0 + rr) * L + l0 + col] : 0.0;
     }
     const int ar = rb * 16 + li;
-#pragma unroll 1
-    for (int s4 = 0; s4 < ks; ++s4) {
+    double av[kMaxK / 4], bw[kMaxK / 4];
+#pragma unroll
+    for (int s4 = 0; s4 < kMaxK / 4; ++s4) {
       const int i = 4 * s4 + lq;
       const int ic = min(i, kMaxK - 1);
-      const double a = (i < m && ar < b) ? Xrec[(sp * kMaxK + ic) * kWin + min(ar, kWin - 1)] : 0.0;
-      const double bv = (i < m && col < b) ? Yrec[(sp * kMaxK + ic) * kWin + min(col, kWin - 1)] : 0.0;
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc, 0, 0, 0);
+      const double xa = Xrec[(sp * kMaxK + ic) * kWin + min(ar, kWin - 1)];
+      const double yb = Yrec[(sp * kMaxK + ic) * kWin + min(col, kWin - 1)];
+      av[s4] = (i < m && ar < b) ? xa : 0.0;
+      bw[s4] = (i < m && col < b) ? yb : 0.0;
+    }
+#pragma unroll
+    for (int s4 = 0; s4 < kMaxK / 4; ++s4) {
+      if (s4 >= ks) break;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s4], bw[s4], acc, 0, 0, 0);
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -1919,8 +1949,10 @@ __device__ __forceinline__ void flush_pending(const Chain& ch, const WinLds& w, 
   const int L = ch.L;
   T* X = reinterpret_cast<T*>(ch.wbuf + 4 * kMaxK * kWin);   // [2][L][kMaxK]
   T* Y = X + 2LL * L * kMaxK;                                 // [2][kMaxK][L]
-  const long long t1 = wall_clock64();
+  const long long t0 = wall_clock64();
   flush_fold(w.ULu, w.ULd, m, nsp);
+  const long long t1 = wall_clock64();
+  if (threadIdx.x == 0) ch.st[ST_T_FOLD] += t1 - t0;
 #pragma unroll 1
   for (int sp = 0; sp < nsp; ++sp)
     flush_vectors(sp ? ch.Gd : ch.Gu, L, 0, m, w.F, sp ? w.ULd : w.ULu, X + (long long)sp * L * kMaxK,
@@ -1959,7 +1991,11 @@ __device__ __forceinline__ int sweep_window(const SweepParams& p, const Chain& c
       invert_ts(w, m_inv, m, nsp);
       m_inv = m;
       window_apply(ch, w, l0, b, m, nsp);
-      if (t == 0) ch.st[ST_T_FLUSH] += wall_clock64() - t0;
+      if (t == 0) {
+        const long long dt = wall_clock64() - t0;
+        ch.st[ST_T_FLUSH] += dt;
+        ch.st[ST_T_WAPPLY] += dt;
+      }
     } else {
       for (int idx = t; idx < kWin * kWin; idx += kThreads) {
         const int q = idx >> 6, r = idx & 63;
@@ -2010,9 +2046,12 @@ __device__ __forceinline__ int sweep_window(const SweepParams& p, const Chain& c
           w.cD[m] = cd;
         }
         __syncthreads();
+        // only the trailing block (rows and columns after pos) is read again in
+        // this window: later proposals read its diagonal, later flips' vectors
+        // and coefficients read rows / columns beyond their own slice
         for (int idx = t; idx < kWin * kWin; idx += kThreads) {
           const int q = idx >> 6, r = idx & 63;
-          if (q < b && r < b) {
+          if (q > pos && q < b && r > pos && r < b) {
             w.Wu[q * kWP + r] = axpy_nc(w.Wu[q * kWP + r], w.xu[q], w.yu[r]);
             if (!ph) w.Wd[q * kWP + r] = axpy_nc(w.Wd[q * kWP + r], w.xd[q], w.yd[r]);
           }
@@ -2035,6 +2074,7 @@ __device__ __forceinline__ int sweep_window(const SweepParams& p, const Chain& c
     if (m > 0 && (close || l0 >= L)) {
       const long long t0 = wall_clock64();
       invert_ts(w, m_inv, m, nsp);
+      if (t == 0) ch.st[ST_T_FOLD] += wall_clock64() - t0;
       flush_pending<MIXED>(ch, w, m, nsp);
       if (t == 0) {
         ch.st[ST_T_FLUSH] += wall_clock64() - t0;
@@ -2191,7 +2231,7 @@ __global__ void __launch_bounds__(kThreads) k_sweeps(SweepParams p) {
   for (;;) {
     if (threadIdx.x == 0) s_unit = atomicAdd(p.queue, 1);
     __syncthreads();
-    const int unit = s_unit;
+    const int unit = __builtin_amdgcn_readfirstlane(s_unit);   // uniform: scalar loads, branches
     __syncthreads();
     if (unit >= p.n_units) break;
     const int code = p.units[unit];
