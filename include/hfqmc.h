@@ -69,8 +69,10 @@ enum {
 
 /* Option bits (hfqmc_opts.flags). */
 enum {
-  HFQMC_FLAG_EAGER = 1,      /* launch the kernels one by one instead of replaying a captured
-                                HIP graph of the launch sequence (results are identical) */
+  HFQMC_FLAG_EAGER = 1,      /* launch the set-up kernels (bath matrices, fills, references)
+                                one by one instead of replaying them as a captured HIP graph
+                                (results are identical); the sweep kernel and the chain
+                                reduction follow as two launches either way */
   HFQMC_FLAG_HEAT_BATH = 2,  /* heat-bath acceptance u < R/(1+R) instead of Metropolis u < R */
   HFQMC_FLAG_DIRECT_RECOMPUTE = 4, /* recompute with the full L x L LU of [M | G0] instead of the
                                       reduced system against the uniform-field references */
@@ -128,7 +130,7 @@ typedef struct {
   int32_t recompute_every;  /* recompute interval actually used */
   int32_t n_workgroups;     /* persistent workgroups launched */
   int32_t lu_panel;         /* LU panel width of the recompute */
-  int32_t graph;            /* 1 if the launch sequence ran as a captured HIP graph */
+  int32_t graph;            /* 1 if the set-up launches ran as a captured HIP graph */
   int32_t autotuned;        /* 1 if k and the panel width came from the autotuner */
   double seconds_autotune;  /* time spent in trial launches during this call (0 on a cache hit) */
   int64_t n_reduced_rows;   /* sum over reduced-form recomputes of the system size |S| */
@@ -139,6 +141,9 @@ typedef struct {
   /* delayed-update breakdown (chain-seconds, part of chain_s_flush): opening a
      window with flips pending, and completing T, S and W = T S before a flush */
   double chain_s_window_apply, chain_s_fold;
+  double seconds_sweep_kernel;  /* HIP-event time of the persistent sweep kernel alone (the
+                                   launch sequence of seconds_kernel also builds the bath
+                                   matrices and references and reduces the chains) */
 } hfqmc_stats;
 
 /* Fixed-dtau solve: hfqmc_solve(G0(tau), U, beta, dtau, sweeps, seed) -> G(tau).

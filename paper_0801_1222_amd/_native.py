@@ -51,7 +51,7 @@ class Stats(C.Structure):
         ("graph", _i32), ("autotuned", _i32), ("seconds_autotune", _f64),
         ("n_reduced_rows", _i64), ("recompute_reduced", _i32), ("reserved", _i32),
         ("chain_s_lu_gemm", _f64), ("chain_s_flush_vectors", _f64), ("chain_s_flush_gemm", _f64),
-        ("chain_s_window_apply", _f64), ("chain_s_fold", _f64),
+        ("chain_s_window_apply", _f64), ("chain_s_fold", _f64), ("seconds_sweep_kernel", _f64),
     ]
 
     def as_dict(self):
