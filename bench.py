@@ -251,7 +251,7 @@ def calib_copy():
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--mode", default="mixed", choices=["rank1", "delayed", "mixed"])
     ap.add_argument("--delay-k", type=int, default=0,
@@ -263,7 +263,7 @@ def main():
     ap.add_argument("--rank1-sweeps", type=int, default=40,
                     help="sweeps per chain of the plain FP64 rank-1 comparison solve (0 = skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sweeps", type=int, default=100)
+    ap.add_argument("--cpu-sweeps", type=int, default=300)
     ap.add_argument("--calib-copy", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the peak probes and the small-L / three-grid workloads")
@@ -330,8 +330,12 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     stats = []
+    step_s = []
     for i in range(args.steps):
+        ts = time.perf_counter()
         stats.append(solve_dev())
+        torch.cuda.synchronize()
+        step_s.append(time.perf_counter() - ts)
         progress("timed step %d done, kernel %.2f s" % (i, stats[-1]["seconds_kernel"]))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -441,6 +445,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": elapsed / args.steps * 1e3,
+        "step_ms": [x * 1e3 for x in step_s],
+        "median_step_sweeps_per_s": chain_sweeps / float(np.median(step_s)),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
