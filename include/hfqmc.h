@@ -216,11 +216,14 @@ int hfqmc_measure_peaks(hfqmc_ctx *ctx, hfqmc_peaks *out);
  * then fitted per tau_j by weighted least squares c0 + c1 dtau^2 + c2 dtau^4.
  * Outputs: g_fine[n_fine], g_fine_err[n_fine] (or NULL); g_grids (or NULL)
  * concatenated raw grid estimates, sum (L_i+1) values; per_grid[n_grids]
- * stats (or NULL). */
+ * stats (or NULL); docc_grids[2 n_grids] (or NULL) each grid's double
+ * occupancy and its error; docc[2] (or NULL) the double occupancy
+ * extrapolated to dtau -> 0 by the same weighted quadratic fit in dtau^2
+ * (the D(dtau^2) analysis of Figs. 3 and 4) and its error. */
 int multigrid_solve(hfqmc_ctx *ctx, const double *bath_iw, int32_t n_iw, double bath_m3,
                     double U, double beta, const double *dtaus, int32_t n_grids, uint64_t seed,
                     const hfqmc_opts *opts, int32_t n_fine, double *g_fine, double *g_fine_err,
-                    double *g_grids, hfqmc_stats *per_grid);
+                    double *g_grids, hfqmc_stats *per_grid, double *docc_grids, double *docc);
 
 /* One Bethe-lattice DMFT self-consistency step (host only, no device):
  * G(i w) = G_ref(i w) - int_0^beta e^{i w tau} S(tau) d tau, S the natural
@@ -240,9 +243,10 @@ int dmft_bethe_step(const double *g_fine, int32_t n_fine, const double *bath_iw_
  * the U = 0 solution) and the last bath on return; its 1/(i w)^3 moment is t^2
  * throughout (the Bethe closure keeps it).  g_fine[n_fine] (and g_fine_err,
  * or NULL) is the last iteration's extrapolated G(tau_j), tau_j =
- * j beta/(n_fine-1).  history[2 n_iter] (or NULL): per iteration, the largest
+ * j beta/(n_fine-1).  history[4 n_iter] (or NULL): per iteration, the largest
  * |g_fine - g_fine of the previous iteration| (for the first, against the
- * starting bath's G0(tau_j)) and the largest error bar of g_fine.  Each
+ * starting bath's G0(tau_j)), the largest error bar of g_fine, and the
+ * extrapolated double occupancy with its error (see multigrid_solve).  Each
  * iteration draws fresh Philox streams.  Errors as multigrid_solve; EINVAL for
  * n_iter < 1, mixing outside [0, 1), t <= 0. */
 int dmft_solve(hfqmc_ctx *ctx, double U, double beta, double t, const double *dtaus,

@@ -103,8 +103,13 @@ def multigrid_solve(bath_iw, m3, U, beta, dtaus, seed, n_chains, warmup, sweeps,
         ei.append(e_f)
         per.append(r)
     c0, err = extrapolate(dts, np.array(gi), np.array(ei))
+    # the double occupancy D(dtau^2) of each grid (the quantity of Figs. 3 and 4),
+    # extrapolated by the same weighted quadratic fit
+    d_g = np.array([[r["D"]] for r in per])
+    d_e = np.array([[r["D_err"]] for r in per])
+    d0, d0e = extrapolate(dts, d_g, d_e)
     return dict(g=c0, g_err=err, tau=tau_f, grids=per, g_interp=np.array(gi),
-                e_interp=np.array(ei), Ls=Ls, dtaus=dts)
+                e_interp=np.array(ei), Ls=Ls, dtaus=dts, D=float(d0[0]), D_err=float(d0e[0]))
 
 
 def spline_fourier(tau, values, beta, n_iw):
@@ -154,8 +159,9 @@ def dmft_loop(bath_iw, U, beta, t, dtaus, seed, n_iter, n_chains, warmup, sweeps
     impurity solve at the current bath (fresh random streams per iteration: the
     seed moves by 2^32), then the closure Bath_new = 1/(i w - t^2 G(i w)), mixed
     as mixing * old + (1 - mixing) * new.  The bath's 1/(i w)^3 moment stays t^2.
-    history[it] = (max |g - g_prev|, max g_err), g_prev of the first iteration
-    being the starting bath's own G0(tau_j)."""
+    history[it] = (max |g - g_prev|, max g_err, D, D_err), g_prev of the first
+    iteration being the starting bath's own G0(tau_j), D the extrapolated double
+    occupancy."""
     m3 = t * t
     bath = np.asarray(bath_iw, dtype=np.complex128).copy()
     tau_f = fine_grid(beta, n_fine)
@@ -165,7 +171,8 @@ def dmft_loop(bath_iw, U, beta, t, dtaus, seed, n_iter, n_chains, warmup, sweeps
     for it in range(n_iter):
         r = multigrid_solve(bath, m3, U, beta, dtaus, seed + (it << 32), n_chains, warmup, sweeps,
                             n_rec=n_rec, n_fine=n_fine)
-        hist.append((float(np.abs(r["g"] - prev).max()), float(r["g_err"].max())))
+        hist.append((float(np.abs(r["g"] - prev).max()), float(r["g_err"].max()), r["D"],
+                     r["D_err"]))
         prev = r["g"]
         new = dmft_bethe_step(r["g"], r["tau"], bath, m3, U, beta, t)
         bath = mixing * bath + (1.0 - mixing) * new

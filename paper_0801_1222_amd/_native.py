@@ -86,7 +86,7 @@ lib.hfqmc_solve_grids.argtypes = [_ctx_p, _i32, _pi32, _pd, _f64, _f64, _u64, C.
                                   _pd, _pd, _pd, C.POINTER(Stats)]
 lib.hfqmc_solve_grids.restype = C.c_int
 lib.multigrid_solve.argtypes = [_ctx_p, _pd, _i32, _f64, _f64, _f64, _pd, _i32, _u64,
-                                C.POINTER(Opts), _i32, _pd, _pd, _pd, C.POINTER(Stats)]
+                                C.POINTER(Opts), _i32, _pd, _pd, _pd, C.POINTER(Stats), _pd, _pd]
 lib.multigrid_solve.restype = C.c_int
 lib.dmft_bethe_step.argtypes = [_pd, _i32, _pd, _i32, _f64, _f64, _f64, _f64, _pd]
 lib.dmft_bethe_step.restype = C.c_int

@@ -251,16 +251,20 @@ def multigrid_solve(ctx, bath_iw, bath_m3, U, beta, dtaus, seed, n_fine=200, n_c
     ef = np.zeros(n_fine)
     gg = np.zeros(sum(L + 1 for L in Ls))
     st = (N.Stats * len(Ls))()
+    dg = np.zeros(2 * len(Ls))
+    dx = np.zeros(2)
     rc = N.lib.multigrid_solve(ctx.handle, N.ptr(b), n_iw, float(bath_m3), float(U), float(beta),
                                N.ptr(dt), len(Ls), int(seed), C.byref(o), int(n_fine), N.ptr(gf),
-                               N.ptr(ef), N.ptr(gg), st)
+                               N.ptr(ef), N.ptr(gg), st, N.ptr(dg), N.ptr(dx))
     N.check(rc, "multigrid_solve")
     grids, off = [], 0
     for L in Ls:
         grids.append(gg[off:off + L + 1].copy())
         off += L + 1
     return dict(g=gf, g_err=ef, tau=np.arange(n_fine) * (beta / (n_fine - 1)), Ls=Ls,
-                g_grids=grids, stats=[st[i].as_dict() for i in range(len(Ls))])
+                g_grids=grids, stats=[st[i].as_dict() for i in range(len(Ls))],
+                D_grids=dg[0::2].copy(), D_err_grids=dg[1::2].copy(), D=float(dx[0]),
+                D_err=float(dx[1]))
 
 
 def dmft_solve(ctx, U, beta, t, dtaus, seed, n_iter, bath_iw=None, n_iw=4096, n_fine=200,
@@ -269,7 +273,8 @@ def dmft_solve(ctx, U, beta, t, dtaus, seed, n_iter, bath_iw=None, n_iw=4096, n_
                ph=False):
     """Multigrid DMFT cycle on the Bethe lattice; starts from bath_iw (default:
     the U = 0 semicircle).  Returns dict(bath, g, g_err, tau, history) with
-    history[it] = (max |g - g_prev|, max g_err)."""
+    history[it] = (max |g - g_prev|, max g_err, D, D_err), D the extrapolated
+    double occupancy."""
     if bath_iw is None:
         bath_iw = bethe_semicircle_bath(beta, t, n_iw)
     b = np.ascontiguousarray(np.asarray(bath_iw, dtype=np.complex128)).copy().view(np.float64)
@@ -279,13 +284,13 @@ def dmft_solve(ctx, U, beta, t, dtaus, seed, n_iter, bath_iw=None, n_iw=4096, n_
               _flags(eager, heat_bath, direct, ph))
     gf = np.zeros(n_fine)
     ef = np.zeros(n_fine)
-    hist = np.zeros(2 * int(n_iter))
+    hist = np.zeros(4 * int(n_iter))
     rc = N.lib.dmft_solve(ctx.handle, float(U), float(beta), float(t), N.ptr(dt), dt.shape[0],
                           int(seed), C.byref(o), int(n_fine), n_iw, int(n_iter), float(mixing),
                           N.ptr(b), N.ptr(gf), N.ptr(ef), N.ptr(hist))
     N.check(rc, "dmft_solve")
     return dict(bath=b.view(np.complex128), g=gf, g_err=ef,
-                tau=np.arange(n_fine) * (beta / (n_fine - 1)), history=hist.reshape(-1, 2))
+                tau=np.arange(n_fine) * (beta / (n_fine - 1)), history=hist.reshape(-1, 4))
 
 
 def dmft_bethe_step(g_fine, bath_iw_prev, bath_m3, U, beta, t):

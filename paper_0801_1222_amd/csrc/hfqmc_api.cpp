@@ -854,7 +854,7 @@ extern "C" int multigrid_solve(hfqmc_ctx* c, const double* bath_iw, int32_t n_iw
                                double U, double beta, const double* dtaus, int32_t n_grids,
                                uint64_t seed, const hfqmc_opts* opts, int32_t n_fine,
                                double* g_fine, double* g_fine_err, double* g_grids,
-                               hfqmc_stats* per_grid) {
+                               hfqmc_stats* per_grid, double* docc_grids, double* docc) {
   if (!bath_iw || !dtaus || !g_fine) return fail(HFQMC_EINVAL, "multigrid_solve: null pointer");
   if (n_grids < 3) return fail(HFQMC_EINVAL, "multigrid_solve: n_grids=%d < 3", n_grids);
   if (n_fine < 4) return fail(HFQMC_EINVAL, "multigrid_solve: n_fine=%d < 4", n_fine);
@@ -870,7 +870,7 @@ extern "C" int multigrid_solve(hfqmc_ctx* c, const double* bath_iw, int32_t n_iw
     Lsum += Ls[i];
     Psum += Ls[i] + 1;
   }
-  std::vector<double> g0(Lsum), gg(Psum), ge(Psum);
+  std::vector<double> g0(Lsum), gg(Psum), ge(Psum), dd(2 * (size_t)n_grids);
   long long off = 0;
   for (int i = 0; i < n_grids; ++i) {
     int rc = bath_to_tau(bath_iw, n_iw, bath_m3, beta, Ls[i], g0.data() + off);
@@ -878,7 +878,7 @@ extern "C" int multigrid_solve(hfqmc_ctx* c, const double* bath_iw, int32_t n_iw
     off += Ls[i];
   }
   int rc = solve_grids_impl(c, n_grids, Ls.data(), g0.data(), U, beta, seed, opts, gg.data(),
-                            ge.data(), nullptr, per_grid, Call());
+                            ge.data(), dd.data(), per_grid, Call());
   if (rc) return rc;
   // (i) interpolation onto the fine grid with the reference model
   std::vector<double> tf(n_fine), gref_f(n_fine);
@@ -910,6 +910,16 @@ extern "C" int multigrid_solve(hfqmc_ctx* c, const double* bath_iw, int32_t n_iw
   host::extrapolate(dts.data(), n_grids, gi.data(), ei.data(), n_fine, g_fine, err.data());
   if (g_fine_err) std::memcpy(g_fine_err, err.data(), sizeof(double) * n_fine);
   if (g_grids) std::memcpy(g_grids, gg.data(), sizeof(double) * Psum);
+  // the double occupancy of each grid and its dtau -> 0 extrapolation
+  if (docc_grids) std::memcpy(docc_grids, dd.data(), sizeof(double) * 2 * n_grids);
+  if (docc) {
+    std::vector<double> dv(n_grids), de(n_grids);
+    for (int i = 0; i < n_grids; ++i) {
+      dv[i] = dd[2 * i];
+      de[i] = dd[2 * i + 1];
+    }
+    host::extrapolate(dts.data(), n_grids, dv.data(), de.data(), 1, &docc[0], &docc[1]);
+  }
   return HFQMC_OK;
 }
 
@@ -946,8 +956,9 @@ extern "C" int dmft_solve(hfqmc_ctx* c, double U, double beta, double t, const d
     // independent Philox streams per iteration: the seed moves by 2^32 (chain keys
     // are seed + chain with fewer than 2^20 chains)
     const uint64_t s_it = seed + ((uint64_t)it << 32);
+    double dx[2] = {0.0, 0.0};
     int rc = multigrid_solve(c, bath_iw, n_iw, m3, U, beta, dtaus, n_grids, s_it, opts, n_fine,
-                             g_fine, err.data(), nullptr, nullptr);
+                             g_fine, err.data(), nullptr, nullptr, nullptr, dx);
     if (rc) return rc;
     double dmax = 0.0, emax = 0.0;
     for (int j = 0; j < n_fine; ++j) {
@@ -956,8 +967,10 @@ extern "C" int dmft_solve(hfqmc_ctx* c, double U, double beta, double t, const d
       prev[j] = g_fine[j];
     }
     if (history) {
-      history[2 * it] = dmax;
-      history[2 * it + 1] = emax;
+      history[4 * it] = dmax;
+      history[4 * it + 1] = emax;
+      history[4 * it + 2] = dx[0];
+      history[4 * it + 3] = dx[1];
     }
     rc = host::bethe_step(g_fine, n_fine, bath_iw, n_iw, m3, U, beta, t, nb.data());
     if (rc) return fail(rc, "dmft_solve: Bethe step failed in iteration %d", it);

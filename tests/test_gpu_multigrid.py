@@ -41,8 +41,12 @@ def test_multigrid_matches_oracle_grid_by_grid(ctx):
     assert out["Ls"] == [50, 60, 70, 80, 100, 120, 160]
     for i in range(len(dtaus)):
         assert np.abs(out["g_grids"][i] - ref["grids"][i]["g"]).max() < 1e-10
+        assert abs(out["D_grids"][i] - ref["grids"][i]["D"]) < 1e-10
+        assert abs(out["D_err_grids"][i] - ref["grids"][i]["D_err"]) < 1e-10
     assert np.abs(out["g"] - ref["g"]).max() < 1e-9
     assert np.abs(out["g_err"] - ref["g_err"]).max() < 1e-9
+    # the double occupancy extrapolated in dtau^2
+    assert abs(out["D"] - ref["D"]) < 1e-9 and abs(out["D_err"] - ref["D_err"]) < 1e-9
 
 
 def test_multigrid_u0_is_exact(ctx):
@@ -65,6 +69,7 @@ def test_multigrid_atomic_limit(ctx):
     exact = OH.atomic_limit_g(U, beta, out["tau"])
     z = np.abs(out["g"] - exact)[1:-1] / out["g_err"][1:-1]
     assert z.max() < 4.5
+    assert abs(out["D"] - OH.atomic_limit_d(U, beta)) < 4.5 * out["D_err"]
 
 
 def test_bethe_cycle_at_u0_is_a_fixed_point(ctx):

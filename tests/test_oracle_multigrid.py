@@ -67,6 +67,17 @@ def test_atomic_limit_multigrid_within_errors():
     exact = H.atomic_limit_g(U, beta, out["tau"])
     z = np.abs(out["g"] - exact)[1:-1] / out["g_err"][1:-1]
     assert z.max() < 4.0
+    # the extrapolated double occupancy as well (every grid is Trotter-exact)
+    assert abs(out["D"] - H.atomic_limit_d(U, beta)) < 4.0 * out["D_err"]
+
+
+def test_u0_double_occupancy_is_a_quarter():
+    # U = 0: D = <n_up><n_dn> = 1/4 exactly on every grid and after the fit
+    beta = 10.0
+    bath = B.semicircle_iw(beta, 1.0, 4000)
+    out = MG.multigrid_solve(bath, 1.0, 0.0, beta, [0.5, 0.4, 0.25], seed=0,
+                             n_chains=2, warmup=1, sweeps=2, n_fine=60)
+    assert abs(out["D"] - 0.25) < 1e-12
 
 
 def test_dmft_loop_u0_semicircle_is_fixed_point():
