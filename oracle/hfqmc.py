@@ -347,3 +347,31 @@ def atomic_limit_g(U, beta, tau):
 def atomic_limit_d(U, beta):
     """Half-filled Hubbard atom: D = 1 / (2 (1 + e^{beta U / 2}))."""
     return 1.0 / (2.0 * (1.0 + np.exp(0.5 * beta * U)))
+
+
+# ------------------------------------------ an atomic level at any filling ----
+# The bath of an isolated level eps0 (chemical potential -eps0) and the exact
+# Green function and double occupancy of the Hubbard atom built on it.  The
+# interaction is the decoupled U (n_up n_dn - (n_up + n_dn)/2); the four states
+# have energies 0, E1 = eps0 - U/2 (twice), E2 = 2 eps0.  HF-QMC is
+# Trotter-exact here for every L (everything is diagonal in the occupations).
+
+def atomic_level_bath(eps0, beta, tau):
+    """G0(tau) = e^{-eps0 tau} / (1 + e^{-beta eps0}), 0 <= tau < beta (positive convention)."""
+    tau = np.asarray(tau, dtype=np.float64)
+    return np.exp(-eps0 * tau) / (1.0 + np.exp(-beta * eps0))
+
+
+def atomic_level_g(eps0, U, beta, tau):
+    """G(tau) = [e^{-tau E1} + e^{-beta E1} e^{-tau (E2 - E1)}] / Z, Z = 1 + 2 e^{-beta E1} + e^{-beta E2}."""
+    tau = np.asarray(tau, dtype=np.float64)
+    e1, e2 = eps0 - 0.5 * U, 2.0 * eps0
+    z = 1.0 + 2.0 * np.exp(-beta * e1) + np.exp(-beta * e2)
+    return (np.exp(-tau * e1) + np.exp(-beta * e1) * np.exp(-tau * (e2 - e1))) / z
+
+
+def atomic_level_d(eps0, U, beta):
+    """D = e^{-beta E2} / Z."""
+    e1, e2 = eps0 - 0.5 * U, 2.0 * eps0
+    z = 1.0 + 2.0 * np.exp(-beta * e1) + np.exp(-beta * e2)
+    return np.exp(-beta * e2) / z

@@ -196,3 +196,28 @@ def test_replay_of_own_flips_is_identical():
     r2 = H.run_chain(g, U, beta, seed=9, warmup=1, sweeps=10, replay=set(r1["flips"]))
     assert r1["flips"] == r2["flips"]
     assert np.array_equal(r1["bins_g"], r2["bins_g"])
+
+
+def test_atomic_level_reduces_to_half_filled_atom():
+    beta, U = 4.0, 3.0
+    tau = np.linspace(0.0, beta, 9)
+    assert np.abs(H.atomic_level_g(0.0, U, beta, tau) - H.atomic_limit_g(U, beta, tau)).max() < 1e-14
+    assert abs(H.atomic_level_d(0.0, U, beta) - H.atomic_limit_d(U, beta)) < 1e-15
+    assert np.abs(H.atomic_level_bath(0.0, beta, tau[:-1]) - 0.5).max() == 0.0
+    # U = 0: the interacting atom is its own bath
+    assert np.abs(H.atomic_level_g(-0.6, 0.0, beta, tau[:-1])
+                  - H.atomic_level_bath(-0.6, beta, tau[:-1])).max() < 1e-14
+
+
+@pytest.mark.parametrize("eps0,L", [(-0.7, 8), (0.45, 10)])
+def test_brute_force_atomic_level_away_from_half_filling(eps0, L):
+    # general filling: exact enumeration of the HS field equals the closed form
+    beta, U = 4.0, 4.0
+    tau = np.arange(L) * beta / L
+    g_tau = H.atomic_level_bath(eps0, beta, tau)
+    g, d, wmin = H.brute_force(g_tau, U, beta)
+    exact = H.atomic_level_g(eps0, U, beta, np.arange(L + 1) * beta / L)
+    exact[L] = 1.0 - exact[0]
+    assert wmin > 0
+    assert np.abs(g - exact).max() < 1e-11
+    assert abs(d - H.atomic_level_d(eps0, U, beta)) < 1e-12
