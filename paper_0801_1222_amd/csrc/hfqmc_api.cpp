@@ -266,8 +266,11 @@ int autotune(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double* g0_tau,
   }
   int nb_widest = 0, scratch = 0;
   const int direct = (opts->flags & HFQMC_FLAG_DIRECT_RECOMPUTE) ? 1 : 0;
-  if (lds_bytes(Lmax, opts->mode, 0, direct, &nb_widest, &scratch) < 0)
-    (void)lds_bytes(Lmax, opts->mode, 0, 1, &nb_widest, &scratch);
+  for (int i = 0; i < n_grids; ++i) {
+    int nb = 0;
+    (void)lds_bytes(Lmax, Ls[i], opts->mode, 0, direct, &nb, &scratch);
+    nb_widest = std::max(nb_widest, nb);
+  }
   std::vector<int> nbs = {nb_widest};
   if (nb_widest == 32) nbs.push_back(16);
   hfqmc_opts to;
@@ -353,19 +356,28 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
 
   // ---- device memory layout (two passes: size, then assign)
   // ---- launch shape (LDS, LU panel width) and the recompute form
-  int lu_nb = 0, scratch = 0;
-  int direct = (opts->flags & HFQMC_FLAG_DIRECT_RECOMPUTE) ? 1 : 0;
-  int lds = lds_bytes(Lmax, r.mode, nb_max, direct, &lu_nb, &scratch);
-  if (lds < 0) {
-    // the reduced system's LDS staging does not fit: full-size recompute
-    direct = 1;
-    lds = lds_bytes(Lmax, r.mode, nb_max, 1, &lu_nb, &scratch);
+  // per grid: the recompute form and its LU panel width; the launch's LDS
+  // covers the largest need (the head and update buffers are sized for Lmax)
+  const int direct = (opts->flags & HFQMC_FLAG_DIRECT_RECOMPUTE) ? 1 : 0;
+  std::vector<int> g_nb(n_grids);
+  int lu_nb = 0, scratch = 0, lds = 0;
+  for (int i = 0; i < n_grids; ++i) {
+    int sc = 0;
+    const int l = lds_bytes(Lmax, Ls[i], r.mode, nb_max, direct, &g_nb[i], &sc);
+    lds = std::max(lds, l);
+    scratch = std::max(scratch, sc);
+    lu_nb = std::max(lu_nb, g_nb[i]);
   }
   if (lds + 1024 > c->lds_max)
     return fail(HFQMC_EUNSUPPORTED, "L=%d needs %d bytes of LDS, device allows %d", Lmax, lds, c->lds_max);
-  int ref_nb = 0, ref_scratch = 0, ref_lds = 0;
+  std::vector<int> g_ref_nb(n_grids, 0);
+  int ref_scratch = 0, ref_lds = 0;
   if (!direct) {
-    ref_lds = lds_bytes(Lmax, -1, 0, 1, &ref_nb, &ref_scratch);
+    for (int i = 0; i < n_grids; ++i) {
+      int sc = 0;
+      ref_lds = std::max(ref_lds, lds_bytes(Lmax, Ls[i], -1, 0, 1, &g_ref_nb[i], &sc));
+      ref_scratch = std::max(ref_scratch, sc);
+    }
     if (ref_lds + 1024 > c->lds_max)
       return fail(HFQMC_EUNSUPPORTED, "L=%d: reference solve needs %d bytes of LDS", Lmax, ref_lds);
   }
@@ -424,6 +436,9 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
     g.n_chains = nch;
     g.grid_id = i;
     g.unit_base = i * nch;
+    g.lu_nb = g_nb[i];
+    g.direct = direct;
+    g.ref_nb = g_ref_nb[i];
     g.gp = std::expm1(2.0 * lam);
     g.gm = std::expm1(-2.0 * lam);
     g.ep = std::expm1(lam);
@@ -533,7 +548,7 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
       e = launch_zero(g.cdrift, nch, s);
       if (e == hipSuccess && !direct) e = launch_zero_i32(g.ref_sing, 4, s);
     }
-    if (e == hipSuccess && !direct) e = launch_reference(p, ref_nb, ref_lds, ref_scratch, s);
+    if (e == hipSuccess && !direct) e = launch_reference(p, ref_lds, ref_scratch, s);
     if (e == hipSuccess) e = launch_zero_i32(d_queue, 64, s);
     return e;
   };

@@ -42,6 +42,9 @@ struct GridDev {
   const double* refQ[2];  // L x L, Q_r = M_r^{-1} (1 - G0) for the uniform references
   const double* refH[2];  //   r = 0: D = e^{lambda} - 1, r = 1: D = e^{-lambda} - 1; H_r = M_r^{-1} G0
   int* ref_sing;          // set when a reference solve met a zero pivot
+  int lu_nb;              // LU panel width of this grid's recomputes
+  int direct;             // 1: full-size recompute (no references), 0: reduced form
+  int ref_nb;             // LU panel width of this grid's reference solves
   int unit_base;          // index of chain 0 of this grid in the per-launch chain arrays
   double gp, gm;          // e^{2 lambda} - 1, e^{-2 lambda} - 1  (flip factors gamma)
   double ep, em;          // e^{lambda} - 1,   e^{-lambda} - 1    (Dyson matrix diagonal)
@@ -73,7 +76,7 @@ struct SweepParams {
   int delay_k;            // max pending flips (delayed modes)
   int window_b;           // max slices per window (delayed modes)
   int n_bins;
-  int lu_nb;              // LU panel width
+  int lu_nb;              // widest LU panel of the launch (per grid: GridDev::lu_nb)
   long long flip_cap, replay_cap;
   double* work;           // per-workgroup workspace
   long long work_stride;  // doubles per workgroup
@@ -90,11 +93,13 @@ constexpr int kMaxK = 64;       // largest delayed rank
 
 // Workspace (doubles) needed per workgroup for chains of length up to Lmax.
 long long workspace_doubles(int Lmax, int kmax);
-// Dynamic LDS bytes of the persistent kernel and the LU panel width for Lmax
-// (the widest that fits the LDS budget, at most nb_max).  direct = 0 sizes the
-// LU for the reduced system (at most Lmax/2) and returns -1 if that form does
-// not fit; the reference kernel uses direct = 1.
-int lds_bytes(int Lmax, int mode, int nb_max, int direct, int* lu_nb, int* scratch_bytes);
+// Dynamic LDS bytes of the persistent kernel for a grid of L slices in a launch
+// whose longest grid has Lmax (the head and the update buffers are sized for
+// Lmax), and that grid's LU panel width (the widest that fits the LDS budget,
+// at most nb_max).  direct = 0 sizes the LU for the reduced system (at most
+// L/2 rows; the reduced form's product streams G[S,:] through LDS in slabs
+// that fit); the reference kernel uses direct = 1.
+int lds_bytes(int Lmax, int L, int mode, int nb_max, int direct, int* lu_nb, int* scratch_bytes);
 // Sets the kernel's dynamic-LDS limit (needed above 64 KiB); call before a
 // launch or a stream capture.
 hipError_t prepare_sweeps(int lds);
@@ -106,9 +111,10 @@ hipError_t launch_zero_i64(long long* p, long long n, hipStream_t s);
 hipError_t launch_zero_i32(int* p, long long n, hipStream_t s);
 hipError_t launch_sweeps(const SweepParams& p, int n_wg, int lds, hipStream_t s);
 // Uniform-field reference matrices (Q_r, H_r, r = 0, 1) of every grid: 4
-// workgroups per grid, direct LU with panel width nb, workspace slots 0..4 n_grids-1.
+// workgroups per grid, direct LU with the grid's panel width ref_nb,
+// workspace slots 0..4 n_grids-1.
 hipError_t prepare_reference(int lds);
-hipError_t launch_reference(const SweepParams& p, int nb, int lds, int scratch, hipStream_t s);
+hipError_t launch_reference(const SweepParams& p, int lds, int scratch, hipStream_t s);
 hipError_t launch_reduce(const GridDev* grids, int n_grids, int n_bins, hipStream_t s);
 
 // Achievable-peak probes (hfqmc_peaks.hip).  Copy / read: n16 16-byte

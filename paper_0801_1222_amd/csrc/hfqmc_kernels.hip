@@ -193,6 +193,8 @@ struct Chain {
   int* sr;         // LDS [L] at the start of the scratch during a reduced solve: S, then R
   const double* refQ[2];
   const double* refH[2];
+  int lu_nb;       // LU panel width of this grid
+  bool reduced;    // recompute against the uniform-field references
 };
 
 // Control state every thread keeps (uniform); the statistics live in LDS.
@@ -1064,95 +1066,115 @@ __device__ __forceinline__ double dyson_solve(const Chain& ch, int sigma, double
         }
       }
     }
-    int zw = 64;                                        // chunk width
+    // chunks of zw columns of G[S,:] staged in LDS; where a chunk of all kr
+    // rows does not fit (large L), K is split into slabs of kc rows and the
+    // partial sums of G[R,:] go through the workspace (after Aq)
+    int zw = 64;
     while (zw > 16 && (long long)kr * (zw + 2) * 8 > lu_scr_bytes) zw >>= 1;
+    int kc = kr;
+    if ((long long)kr * (zw + 2) * 8 > lu_scr_bytes)
+      kc = max(8, (int)((lu_scr_bytes / ((zw + 2) * 8)) & ~7LL));
     const int zs = zw + 2;
     double* Zl = reinterpret_cast<double*>(lu_scr);
+    double* __restrict__ Pq = A + (long long)nR * kr;   // [nR][L] partial sums (kc < kr only)
     const int li = lane & 15, lq = lane >> 4;
     const int nrb = (nR + 15) >> 4;
     for (int c0 = 0; c0 < L; c0 += zw) {
-      __syncthreads();
-      // a wave per row, four rows in flight; lanes along the chunk
-      for (int i0 = wv; i0 < kr; i0 += 4 * (kThreads / 64)) {
-        for (int j = lane; j < zw; j += 64) {
-          double v[4];
+      for (int k0 = 0; k0 < kr; k0 += kc) {
+        const int kcl = min(kc, kr - k0);                // rows of this slab (8 | kcl)
+        const int kcs = kcl >> 2;                        // K steps of this slab (even)
+        const bool first = k0 == 0, last = k0 + kcl >= kr;
+        __syncthreads();
+        // a wave per row, four rows in flight; lanes along the chunk
+        for (int i0 = wv; i0 < kcl; i0 += 4 * (kThreads / 64)) {
+          for (int j = lane; j < zw; j += 64) {
+            double v[4];
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int i = i0 + u * (kThreads / 64);
-            const int gi = sr[min(i, ns - 1)];
-            v[u] = (i < ns && c0 + j < L) ? Gs[gi * L + c0 + j] : 0.0;
-          }
+            for (int u = 0; u < 4; ++u) {
+              const int i = k0 + i0 + u * (kThreads / 64);
+              const int gi = sr[min(i, ns - 1)];
+              const double g = Gs[gi * L + min(c0 + j, L - 1)];   // clamped: in bounds
+              v[u] = (i < ns && c0 + j < L) ? g : 0.0;
+            }
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            const int i = i0 + u * (kThreads / 64);
-            if (i < kr) Zl[i * zs + j] = v[u];
-          }
-        }
-      }
-      __syncthreads();
-      const int ntile = (min(zw, L - c0) + 15) >> 4;   // 16-column tiles in this chunk (<= 4)
-      for (int rb = wv; rb < nrb; rb += kThreads / 64) {
-        // one 16-row block of R against every tile of the chunk; the A operand
-        // is prefetched a batch of kGB steps ahead (two register batches in turn)
-        constexpr int kGB = 16;
-        const int arow = min(rb * 16 + li, nR - 1);
-        const double2* arow2 = reinterpret_cast<const double2*>(Aq + (long long)arow * kr + lq * ks);
-        int orow[4], oR[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          orow[r] = rb * 16 + 4 * r + lq;
-          oR[r] = Rl[min(orow[r], nR - 1)];
-        }
-        doublex4 acc[4];
-        double gold[4][4];
-#pragma unroll
-        for (int tt = 0; tt < 4; ++tt) {
-          const int col = min(c0 + 16 * tt + li, L - 1);
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            acc[tt][r] = (tt < ntile) ? Hr[oR[r] * L + col] : 0.0;
-            gold[tt][r] = (tt < ntile) ? Gs[oR[r] * L + col] : 0.0;
-          }
-        }
-        // steps q0.. of this lane's K range (clamped, in bounds: ks is even)
-        auto load_a = [&](int q0, double2 (&av)[kGB / 2]) {
-#pragma unroll
-          for (int u = 0; u < kGB / 2; ++u) av[u] = arow2[min(q0 / 2 + u, ks / 2 - 1)];
-        };
-        auto mma = [&](int q0, const double2 (&av)[kGB / 2]) {
-#pragma unroll
-          for (int u = 0; u < kGB; ++u) {
-            if (q0 + u < ks) {
-              const double a = (u & 1) ? av[u >> 1].y : av[u >> 1].x;
-              const double* zb = Zl + (lq * ks + q0 + u) * zs + li;
-#pragma unroll
-              for (int tt = 0; tt < 4; ++tt)
-                if (tt < ntile)
-                  acc[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, zb[16 * tt], acc[tt], 0, 0, 0);
+            for (int u = 0; u < 4; ++u) {
+              const int i = i0 + u * (kThreads / 64);
+              if (i < kcl) Zl[i * zs + j] = v[u];
             }
           }
-        };
-        double2 a0[kGB / 2], a1[kGB / 2];
-        load_a(0, a0);
-#pragma unroll 1
-        for (int q0 = 0; q0 < ks; q0 += 2 * kGB) {
-          if (q0 + kGB < ks) load_a(q0 + kGB, a1);
-          mma(q0, a0);
-          if (q0 + kGB >= ks) break;
-          if (q0 + 2 * kGB < ks) load_a(q0 + 2 * kGB, a0);
-          mma(q0 + kGB, a1);
         }
+        __syncthreads();
+        const int ntile = (min(zw, L - c0) + 15) >> 4;   // 16-column tiles in this chunk (<= 4)
+        for (int rb = wv; rb < nrb; rb += kThreads / 64) {
+          // one 16-row block of R against every tile of the chunk; the A operand
+          // is prefetched a batch of kGB steps ahead (two register batches in turn)
+          constexpr int kGB = 16;
+          const int arow = min(rb * 16 + li, nR - 1);
+          const double2* arow2 =
+              reinterpret_cast<const double2*>(Aq + (long long)arow * kr + k0 + lq * kcs);
+          int orow[4], oR[4];
 #pragma unroll
-        for (int tt = 0; tt < 4; ++tt) {
-          const int col = c0 + 16 * tt + li;
-          if (tt < ntile && col < L && col < c0 + zw) {
+          for (int r = 0; r < 4; ++r) {
+            orow[r] = rb * 16 + 4 * r + lq;
+            oR[r] = Rl[min(orow[r], nR - 1)];
+          }
+          doublex4 acc[4];
+          double gold[4][4];   // the updated G the final rows replace (for the drift)
+#pragma unroll
+          for (int tt = 0; tt < 4; ++tt) {
+            const int col = min(c0 + 16 * tt + li, L - 1);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-              if (orow[r] < nR) {
-                const double x = acc[tt][r];
-                dmax = fmax(dmax, fabs(x - gold[tt][r]));
-                if (!(fabs(x) < INFINITY)) dmax = INFINITY;
-                Gs[oR[r] * L + col] = x;
+              acc[tt][r] = (tt < ntile) ? (first ? Hr[oR[r] * L + col]
+                                                 : Pq[(long long)min(orow[r], nR - 1) * L + col])
+                                        : 0.0;
+              gold[tt][r] = (tt < ntile && last) ? Gs[oR[r] * L + col] : 0.0;
+            }
+          }
+          // steps q0.. of this lane's K range (clamped, in bounds: kcs is even)
+          auto load_a = [&](int q0, double2 (&av)[kGB / 2]) {
+#pragma unroll
+            for (int u = 0; u < kGB / 2; ++u) av[u] = arow2[min(q0 / 2 + u, kcs / 2 - 1)];
+          };
+          auto mma = [&](int q0, const double2 (&av)[kGB / 2]) {
+#pragma unroll
+            for (int u = 0; u < kGB; ++u) {
+              if (q0 + u < kcs) {
+                const double a = (u & 1) ? av[u >> 1].y : av[u >> 1].x;
+                const double* zb = Zl + (lq * kcs + q0 + u) * zs + li;
+#pragma unroll
+                for (int tt = 0; tt < 4; ++tt)
+                  if (tt < ntile)
+                    acc[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, zb[16 * tt], acc[tt], 0, 0, 0);
+              }
+            }
+          };
+          double2 a0[kGB / 2], a1[kGB / 2];
+          load_a(0, a0);
+#pragma unroll 1
+          for (int q0 = 0; q0 < kcs; q0 += 2 * kGB) {
+            if (q0 + kGB < kcs) load_a(q0 + kGB, a1);
+            mma(q0, a0);
+            if (q0 + kGB >= kcs) break;
+            if (q0 + 2 * kGB < kcs) load_a(q0 + 2 * kGB, a0);
+            mma(q0 + kGB, a1);
+          }
+#pragma unroll
+          for (int tt = 0; tt < 4; ++tt) {
+            const int col = c0 + 16 * tt + li;
+            if (tt < ntile && col < L && col < c0 + zw) {
+#pragma unroll
+              for (int r = 0; r < 4; ++r) {
+                if (orow[r] < nR) {
+                  const double x = acc[tt][r];
+                  if (last) {
+                    dmax = fmax(dmax, fabs(x - gold[tt][r]));
+                    if (!(fabs(x) < INFINITY)) dmax = INFINITY;
+                    Gs[oR[r] * L + col] = x;
+                  } else {
+                    Pq[(long long)orow[r] * L + col] = x;
+                  }
+                }
               }
             }
           }
@@ -1303,7 +1325,7 @@ __device__ __forceinline__ void recompute_both(const SweepParams& p, const Chain
   const int nsp = p.ph ? 1 : 2;
 #pragma unroll 1
   for (int sp = 0; sp < nsp; ++sp)
-    d = fmax(d, dyson_solve(ch, sp ? -1 : +1, sp ? ch.Gd : ch.Gu, p.lu_nb, p.direct == 0, false));
+    d = fmax(d, dyson_solve(ch, sp ? -1 : +1, sp ? ch.Gd : ch.Gu, ch.lu_nb, ch.reduced, false));
   if (counted && threadIdx.x == 0) {
     *ch.drift = fmax(*ch.drift, d);
     ch.st[ST_RECOMPUTES] += 1;
@@ -2106,15 +2128,20 @@ __device__ __forceinline__ void setup_chain(Chain& ch, const SweepParams& p, con
   ch.refQ[1] = gd->refQ[1];
   ch.refH[0] = gd->refH[0];
   ch.refH[1] = gd->refH[1];
+  ch.lu_nb = lu_nb;
+  ch.reduced = gd->direct == 0;
   const int L = ch.L;
   const long long L2 = (long long)L * L;
   ch.Gu = ws;
   ch.Gd = ws + L2;
   ch.A = ws + 2 * L2;
   {
-    const long long np = (L + lu_nb - 1) / lu_nb * lu_nb;
-    ch.Ui = ch.A + 2 * np * np;    // after the padded L x 2L LU workspace
-    ch.wbuf = ch.Ui + np * kNBMax;
+    // LU workspace for any panel width: 2 (L + kNBMax)^2 doubles (the padded
+    // L x 2L system, or the reduced one with its product's operands), then the
+    // U11^{-1} blocks
+    const long long lp = L + kNBMax;
+    ch.Ui = ch.A + 2 * lp * lp;
+    ch.wbuf = ch.Ui + lp * kNBMax;
   }
   ch.grid = gd->grid_id;
   ch.s = reinterpret_cast<int8_t*>(lds);
@@ -2131,7 +2158,7 @@ __device__ __forceinline__ void setup_chain(Chain& ch, const SweepParams& p, con
 __device__ __forceinline__ void run_chain(const SweepParams& p, const GridDev* gd, int chain, double* ws,
                           char* lds) {
   Chain ch;
-  setup_chain(ch, p, gd, chain, ws, lds, p.lu_nb, p.lds_scratch_bytes);
+  setup_chain(ch, p, gd, chain, ws, lds, gd->lu_nb, p.lds_scratch_bytes);
   const int L = ch.L;
   const long long L2 = (long long)L * L;
 
@@ -2244,10 +2271,12 @@ __global__ void __launch_bounds__(kThreads) k_sweeps(SweepParams p) {
 // M_r X = G0 (kind 0, X = H_r) or M_r X = 1 - G0 (kind 1, X = Q_r) with the
 // direct LU, M_r = 1 + d_r (1 - G0), d_0 = e^{lambda} - 1, d_1 = e^{-lambda} - 1
 // (the field s = +1 everywhere, spin up for r = 0 and down for r = 1).
-__global__ void __launch_bounds__(kThreads) k_reference(SweepParams p, int nb, int scratch_bytes) {
+__global__ void __launch_bounds__(kThreads) k_reference(SweepParams p, int scratch_bytes) {
   extern __shared__ __align__(16) char lds[];
   const int gi = blockIdx.x >> 2, r = (blockIdx.x >> 1) & 1, kind = blockIdx.x & 1;
   const GridDev* gd = p.grids + gi;
+  if (gd->direct) return;   // grids recomputed in full size need no references
+  const int nb = gd->ref_nb;
   Chain ch;
   setup_chain(ch, p, gd, 0, p.work + (long long)blockIdx.x * p.work_stride, lds, nb, scratch_bytes);
   for (int l = threadIdx.x; l < ch.L; l += kThreads) ch.s[l] = 1;
@@ -2323,11 +2352,11 @@ static int lu_panel(int Lmax, long long budget, int nb_max) {
   return 4;
 }
 
-int lds_bytes(int Lmax, int mode, int nb_max, int direct, int* lu_nb, int* scratch_bytes) {
+int lds_bytes(int Lmax, int L, int mode, int nb_max, int direct, int* lu_nb, int* scratch_bytes) {
   const long long head = ((Lmax + 15) & ~15) + kUW * 8 + 64 * 8 + kStatBytes;
-  const long long srb = direct ? 0 : ((4LL * Lmax + 15) & ~15);   // reduced form's slice lists
+  const long long srb = direct ? 0 : ((4LL * L + 15) & ~15);   // reduced form's slice lists
   const long long budget = 150 * 1024 - head - srb;
-  const int nsys = direct ? Lmax : (Lmax / 2 > 0 ? Lmax / 2 : 1);
+  const int nsys = direct ? L : (L / 2 > 0 ? L / 2 : 1);
   const int nb = lu_panel(nsys, budget, nb_max > 0 ? nb_max : kNBMax);
   *lu_nb = nb;
   const long long np = (nsys + nb - 1) / nb * nb;
@@ -2338,26 +2367,27 @@ int lds_bytes(int Lmax, int mode, int nb_max, int direct, int* lu_nb, int* scrat
     sc = sc > r1 ? sc : r1;
   } else if (mode == MODE_DELAYED_FP64 || mode == MODE_MIXED) {
     const long long win = kSmall + (2LL * kWin * kWP + 4LL * kWin + 2LL * kMaxK * kKP) * 8;
-    const long long ul = win;
     // flush GEMM: at least one kCW-wide FP64 panel of Y
     const long long yp = kSmall + 1LL * kCW * kYK * 8;
-    long long w = win > ul ? win : ul;
-    w = w > yp ? w : yp;
+    const long long w = win > yp ? win : yp;
     sc = sc > w ? sc : w;
   }
   if (!direct) {
-    // reduced form: G[S,:] staged in LDS 64 columns wide where that fits, at least 16
+    // reduced form: G[S,:] staged 64 columns wide where all its rows fit, else
+    // narrower; where even 16 columns of all rows do not fit, the product
+    // streams K in slabs through whatever the scratch holds (at least 8 rows)
     const long long kr = (nsys + 7LL) & ~7LL;
+    long long z = srb + 8LL * (16 + 2) * 8;
     for (int zw = 64; zw >= 16; zw >>= 1) {
-      const long long z = srb + kr * (zw + 2) * 8;
-      if (head + (sc > z ? sc : z) <= 150 * 1024 || zw == 16) {
-        sc = sc > z ? sc : z;
+      const long long zf = srb + kr * (zw + 2) * 8;
+      if (head + (sc > zf ? sc : zf) <= 150 * 1024) {
+        z = zf;
         break;
       }
     }
+    sc = sc > z ? sc : z;
   }
   sc = (sc + 15) & ~15LL;
-  if (!direct && head + sc > 150 * 1024) return -1;
   *scratch_bytes = (int)sc;
   return (int)(head + sc);
 }
@@ -2417,8 +2447,8 @@ hipError_t prepare_reference(int lds) {
   return hipFuncSetAttribute((const void*)k_reference, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
 }
 
-hipError_t launch_reference(const SweepParams& p, int nb, int lds, int scratch, hipStream_t s) {
-  hipLaunchKernelGGL(k_reference, dim3(4 * p.n_grids), dim3(kThreads), lds, s, p, nb, scratch);
+hipError_t launch_reference(const SweepParams& p, int lds, int scratch, hipStream_t s) {
+  hipLaunchKernelGGL(k_reference, dim3(4 * p.n_grids), dim3(kThreads), lds, s, p, scratch);
   return hipGetLastError();
 }
 
