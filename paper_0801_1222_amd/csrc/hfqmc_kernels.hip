@@ -726,6 +726,132 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* red, int* total)
   return before + x - v;
 }
 
+// The reduced form's product G[R,:] = H_r[R,:] - c Q_r[R,S] G[S,:] for systems
+// whose G[S,:] does not fit LDS even 16 columns wide (L beyond about 1000): K
+// is streamed in slabs of kc rows through LDS (Zl), the partial sums of G[R,:]
+// kept in the workspace Pq.  Kept light in registers (short operand batches,
+// the drift's old values read at the store) so that it adds no pressure to
+// the sweep kernel; returns this thread's largest drift (the caller reduces it).
+__device__ __forceinline__ double reduced_product_slabs(
+    const double* __restrict__ Aq, double* __restrict__ Pq, double* __restrict__ Zl,
+    double* __restrict__ Gs_, const double* __restrict__ Hr_, const int* __restrict__ sr, int ns,
+    int nR, int kr, int L, long long lu_scr_bytes) {
+  gdouble* __restrict__ Gs = (gdouble*)Gs_;
+  gcdouble* __restrict__ Hr = (gcdouble*)Hr_;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int* Rl = sr + ns;
+  double dmax = 0.0;
+  int zw = 64;
+  while (zw > 16 && (long long)kr * (zw + 2) * 8 > lu_scr_bytes) zw >>= 1;
+  int kc = kr;
+  if ((long long)kr * (zw + 2) * 8 > lu_scr_bytes)
+    kc = max(8, (int)((lu_scr_bytes / ((zw + 2) * 8)) & ~7LL));
+  const int zs = zw + 2;
+  const int li = lane & 15, lq = lane >> 4;
+  const int nrb = (nR + 15) >> 4;
+  for (int c0 = 0; c0 < L; c0 += zw) {
+    for (int k0 = 0; k0 < kr; k0 += kc) {
+      const int kcl = min(kc, kr - k0);                // rows of this slab (8 | kcl)
+      const int kcs = kcl >> 2;                        // K steps of this slab (even)
+      const bool first = k0 == 0, last = k0 + kcl >= kr;
+      __syncthreads();
+      // a wave per row, four rows in flight; lanes along the chunk
+      for (int i0 = wv; i0 < kcl; i0 += 4 * (kThreads / 64)) {
+        for (int j = lane; j < zw; j += 64) {
+          double v[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int i = k0 + i0 + u * (kThreads / 64);
+            const int gi = sr[min(i, ns - 1)];
+            const double g = Gs[gi * L + min(c0 + j, L - 1)];   // clamped: in bounds
+            v[u] = (i < ns && c0 + j < L) ? g : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int i = i0 + u * (kThreads / 64);
+            if (i < kcl) Zl[i * zs + j] = v[u];
+          }
+        }
+      }
+      __syncthreads();
+      const int ntile = (min(zw, L - c0) + 15) >> 4;   // 16-column tiles in this chunk (<= 4)
+      for (int rb = wv; rb < nrb; rb += kThreads / 64) {
+        // one 16-row block of R against every tile of the chunk; the A operand
+        // is prefetched a batch of kGB steps ahead (two register batches in turn)
+        constexpr int kGB = 4;
+        const int arow = min(rb * 16 + li, nR - 1);
+        const double2* arow2 =
+            reinterpret_cast<const double2*>(Aq + (long long)arow * kr + k0 + lq * kcs);
+        int orow[4], oR[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          orow[r] = rb * 16 + 4 * r + lq;
+          oR[r] = Rl[min(orow[r], nR - 1)];
+        }
+        doublex4 acc[4];
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt) {
+          const int col = min(c0 + 16 * tt + li, L - 1);
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            acc[tt][r] = (tt < ntile) ? (first ? Hr[oR[r] * L + col]
+                                               : Pq[(long long)min(orow[r], nR - 1) * L + col])
+                                      : 0.0;
+        }
+        // steps q0.. of this lane's K range (clamped, in bounds: kcs is even)
+        auto load_a = [&](int q0, double2 (&av)[kGB / 2]) {
+#pragma unroll
+          for (int u = 0; u < kGB / 2; ++u) av[u] = arow2[min(q0 / 2 + u, kcs / 2 - 1)];
+        };
+        auto mma = [&](int q0, const double2 (&av)[kGB / 2]) {
+#pragma unroll
+          for (int u = 0; u < kGB; ++u) {
+            if (q0 + u < kcs) {
+              const double a = (u & 1) ? av[u >> 1].y : av[u >> 1].x;
+              const double* zb = Zl + (lq * kcs + q0 + u) * zs + li;
+#pragma unroll
+              for (int tt = 0; tt < 4; ++tt)
+                if (tt < ntile)
+                  acc[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, zb[16 * tt], acc[tt], 0, 0, 0);
+            }
+          }
+        };
+        double2 a0[kGB / 2], a1[kGB / 2];
+        load_a(0, a0);
+#pragma unroll 1
+        for (int q0 = 0; q0 < kcs; q0 += 2 * kGB) {
+          if (q0 + kGB < kcs) load_a(q0 + kGB, a1);
+          mma(q0, a0);
+          if (q0 + kGB >= kcs) break;
+          if (q0 + 2 * kGB < kcs) load_a(q0 + 2 * kGB, a0);
+          mma(q0 + kGB, a1);
+        }
+#pragma unroll
+        for (int tt = 0; tt < 4; ++tt) {
+          const int col = c0 + 16 * tt + li;
+          if (tt < ntile && col < L && col < c0 + zw) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              if (orow[r] < nR) {
+                const double x = acc[tt][r];
+                if (last) {
+                  // the drift against the updated G the final rows replace
+                  dmax = fmax(dmax, fabs(x - Gs[oR[r] * L + col]));
+                  if (!(fabs(x) < INFINITY)) dmax = INFINITY;
+                  Gs[oR[r] * L + col] = x;
+                } else {
+                  Pq[(long long)orow[r] * L + col] = x;
+                }
+              }
+            }
+          }
+        }
+      }
+    }
+  }
+  return dmax;
+}
+
 // ---------------------------------------------------- the Dyson solve ----
 //
 // Direct form: G_sigma = M^{-1} G0 with M = 1 + K D, K = 1 - G0,
@@ -1066,40 +1192,34 @@ __device__ __forceinline__ double dyson_solve(const Chain& ch, int sigma, double
         }
       }
     }
-    // chunks of zw columns of G[S,:] staged in LDS; where a chunk of all kr
-    // rows does not fit (large L), K is split into slabs of kc rows and the
-    // partial sums of G[R,:] go through the workspace (after Aq)
-    int zw = 64;
-    while (zw > 16 && (long long)kr * (zw + 2) * 8 > lu_scr_bytes) zw >>= 1;
-    int kc = kr;
-    if ((long long)kr * (zw + 2) * 8 > lu_scr_bytes)
-      kc = max(8, (int)((lu_scr_bytes / ((zw + 2) * 8)) & ~7LL));
-    const int zs = zw + 2;
-    double* Zl = reinterpret_cast<double*>(lu_scr);
-    double* __restrict__ Pq = A + (long long)nR * kr;   // [nR][L] partial sums (kc < kr only)
-    const int li = lane & 15, lq = lane >> 4;
-    const int nrb = (nR + 15) >> 4;
-    for (int c0 = 0; c0 < L; c0 += zw) {
-      for (int k0 = 0; k0 < kr; k0 += kc) {
-        const int kcl = min(kc, kr - k0);                // rows of this slab (8 | kcl)
-        const int kcs = kcl >> 2;                        // K steps of this slab (even)
-        const bool first = k0 == 0, last = k0 + kcl >= kr;
+    if ((long long)kr * (16 + 2) * 8 > lu_scr_bytes) {
+      // G[S,:] does not fit LDS 16 columns wide: K in slabs (large L)
+      dmax = fmax(dmax, reduced_product_slabs(Aq, A + (long long)nR * kr,
+                                              reinterpret_cast<double*>(lu_scr), Gs_,
+                                              (const double*)Hr, sr, ns, nR, kr, L, lu_scr_bytes));
+    } else {
+      int zw = 64;                                        // chunk width
+      while (zw > 16 && (long long)kr * (zw + 2) * 8 > lu_scr_bytes) zw >>= 1;
+      const int zs = zw + 2;
+      double* Zl = reinterpret_cast<double*>(lu_scr);
+      const int li = lane & 15, lq = lane >> 4;
+      const int nrb = (nR + 15) >> 4;
+      for (int c0 = 0; c0 < L; c0 += zw) {
         __syncthreads();
         // a wave per row, four rows in flight; lanes along the chunk
-        for (int i0 = wv; i0 < kcl; i0 += 4 * (kThreads / 64)) {
+        for (int i0 = wv; i0 < kr; i0 += 4 * (kThreads / 64)) {
           for (int j = lane; j < zw; j += 64) {
             double v[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-              const int i = k0 + i0 + u * (kThreads / 64);
-              const int gi = sr[min(i, ns - 1)];
-              const double g = Gs[gi * L + min(c0 + j, L - 1)];   // clamped: in bounds
-              v[u] = (i < ns && c0 + j < L) ? g : 0.0;
-            }
-#pragma unroll
+  #pragma unroll
             for (int u = 0; u < 4; ++u) {
               const int i = i0 + u * (kThreads / 64);
-              if (i < kcl) Zl[i * zs + j] = v[u];
+              const int gi = sr[min(i, ns - 1)];
+              v[u] = (i < ns && c0 + j < L) ? Gs[gi * L + c0 + j] : 0.0;
+            }
+  #pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              const int i = i0 + u * (kThreads / 64);
+              if (i < kr) Zl[i * zs + j] = v[u];
             }
           }
         }
@@ -1110,39 +1230,36 @@ __device__ __forceinline__ double dyson_solve(const Chain& ch, int sigma, double
           // is prefetched a batch of kGB steps ahead (two register batches in turn)
           constexpr int kGB = 16;
           const int arow = min(rb * 16 + li, nR - 1);
-          const double2* arow2 =
-              reinterpret_cast<const double2*>(Aq + (long long)arow * kr + k0 + lq * kcs);
+          const double2* arow2 = reinterpret_cast<const double2*>(Aq + (long long)arow * kr + lq * ks);
           int orow[4], oR[4];
-#pragma unroll
+  #pragma unroll
           for (int r = 0; r < 4; ++r) {
             orow[r] = rb * 16 + 4 * r + lq;
             oR[r] = Rl[min(orow[r], nR - 1)];
           }
           doublex4 acc[4];
-          double gold[4][4];   // the updated G the final rows replace (for the drift)
-#pragma unroll
+          double gold[4][4];
+  #pragma unroll
           for (int tt = 0; tt < 4; ++tt) {
             const int col = min(c0 + 16 * tt + li, L - 1);
-#pragma unroll
+  #pragma unroll
             for (int r = 0; r < 4; ++r) {
-              acc[tt][r] = (tt < ntile) ? (first ? Hr[oR[r] * L + col]
-                                                 : Pq[(long long)min(orow[r], nR - 1) * L + col])
-                                        : 0.0;
-              gold[tt][r] = (tt < ntile && last) ? Gs[oR[r] * L + col] : 0.0;
+              acc[tt][r] = (tt < ntile) ? Hr[oR[r] * L + col] : 0.0;
+              gold[tt][r] = (tt < ntile) ? Gs[oR[r] * L + col] : 0.0;
             }
           }
-          // steps q0.. of this lane's K range (clamped, in bounds: kcs is even)
+          // steps q0.. of this lane's K range (clamped, in bounds: ks is even)
           auto load_a = [&](int q0, double2 (&av)[kGB / 2]) {
-#pragma unroll
-            for (int u = 0; u < kGB / 2; ++u) av[u] = arow2[min(q0 / 2 + u, kcs / 2 - 1)];
+  #pragma unroll
+            for (int u = 0; u < kGB / 2; ++u) av[u] = arow2[min(q0 / 2 + u, ks / 2 - 1)];
           };
           auto mma = [&](int q0, const double2 (&av)[kGB / 2]) {
-#pragma unroll
+  #pragma unroll
             for (int u = 0; u < kGB; ++u) {
-              if (q0 + u < kcs) {
+              if (q0 + u < ks) {
                 const double a = (u & 1) ? av[u >> 1].y : av[u >> 1].x;
-                const double* zb = Zl + (lq * kcs + q0 + u) * zs + li;
-#pragma unroll
+                const double* zb = Zl + (lq * ks + q0 + u) * zs + li;
+  #pragma unroll
                 for (int tt = 0; tt < 4; ++tt)
                   if (tt < ntile)
                     acc[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, zb[16 * tt], acc[tt], 0, 0, 0);
@@ -1151,29 +1268,25 @@ __device__ __forceinline__ double dyson_solve(const Chain& ch, int sigma, double
           };
           double2 a0[kGB / 2], a1[kGB / 2];
           load_a(0, a0);
-#pragma unroll 1
-          for (int q0 = 0; q0 < kcs; q0 += 2 * kGB) {
-            if (q0 + kGB < kcs) load_a(q0 + kGB, a1);
+  #pragma unroll 1
+          for (int q0 = 0; q0 < ks; q0 += 2 * kGB) {
+            if (q0 + kGB < ks) load_a(q0 + kGB, a1);
             mma(q0, a0);
-            if (q0 + kGB >= kcs) break;
-            if (q0 + 2 * kGB < kcs) load_a(q0 + 2 * kGB, a0);
+            if (q0 + kGB >= ks) break;
+            if (q0 + 2 * kGB < ks) load_a(q0 + 2 * kGB, a0);
             mma(q0 + kGB, a1);
           }
-#pragma unroll
+  #pragma unroll
           for (int tt = 0; tt < 4; ++tt) {
             const int col = c0 + 16 * tt + li;
             if (tt < ntile && col < L && col < c0 + zw) {
-#pragma unroll
+  #pragma unroll
               for (int r = 0; r < 4; ++r) {
                 if (orow[r] < nR) {
                   const double x = acc[tt][r];
-                  if (last) {
-                    dmax = fmax(dmax, fabs(x - gold[tt][r]));
-                    if (!(fabs(x) < INFINITY)) dmax = INFINITY;
-                    Gs[oR[r] * L + col] = x;
-                  } else {
-                    Pq[(long long)orow[r] * L + col] = x;
-                  }
+                  dmax = fmax(dmax, fabs(x - gold[tt][r]));
+                  if (!(fabs(x) < INFINITY)) dmax = INFINITY;
+                  Gs[oR[r] * L + col] = x;
                 }
               }
             }
