@@ -247,7 +247,9 @@ int dmft_bethe_step(const double *g_fine, int32_t n_fine, const double *bath_iw_
  * |g_fine - g_fine of the previous iteration| (for the first, against the
  * starting bath's G0(tau_j)), the largest error bar of g_fine, and the
  * extrapolated double occupancy with its error (see multigrid_solve).  Each
- * iteration draws fresh Philox streams.  Errors as multigrid_solve; EINVAL for
+ * iteration draws fresh Philox streams.  With HFQMC_FLAG_PH_SYMMETRIC the new
+ * bath keeps only its imaginary part (exact for the symmetric G(tau) that flag
+ * implies; the real part is rounding).  Errors as multigrid_solve; EINVAL for
  * n_iter < 1, mixing outside [0, 1), t <= 0. */
 int dmft_solve(hfqmc_ctx *ctx, double U, double beta, double t, const double *dtaus,
                int32_t n_grids, uint64_t seed, const hfqmc_opts *opts, int32_t n_fine,
@@ -256,6 +258,14 @@ int dmft_solve(hfqmc_ctx *ctx, double U, double beta, double t, const double *dt
 
 /* U = 0 starting bath: Bethe-lattice local Green function, half-bandwidth 2t. */
 int bethe_semicircle_bath(double beta, double t, int32_t n_iw, double *bath_iw);
+
+/* Insulating starting bath (Benchmark results section, Fig. 3: the insulating
+ * solution where metal and insulator coexist): the Bethe closure of the
+ * half-filled Hubbard atom, bath_iw = 1/(i w - t^2 G_at(i w)) with
+ * G_at(i w) = (1/(i w - U/2) + 1/(i w + U/2))/2, on w_n, n = 0..n_iw-1.  Its
+ * 1/(i w)^3 moment is t^2, as for bethe_semicircle_bath.  EINVAL for a null
+ * pointer, beta <= 0, t <= 0, U < 0 or n_iw < 1. */
+int bethe_atomic_bath(double beta, double t, double U, int32_t n_iw, double *bath_iw);
 
 /* Bath on a Trotter grid: g_tau[k] = G(k beta/L), k = 0..L-1, by the
  * Matsubara sum with the 1/(i w) + m3/(i w)^3 tail handled in closed form. */

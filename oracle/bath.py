@@ -90,3 +90,18 @@ def bethe_step_iw(g_iw, beta, t):
     """Bethe-lattice closure of the DMFT cycle: new bath 1/(i w - t^2 G(i w))."""
     w = matsubara(beta, g_iw.shape[0])
     return 1.0 / (1j * w - t * t * np.asarray(g_iw))
+
+
+def atomic_seed_iw(beta, t, U, n_iw):
+    """Insulating starting bath: the Bethe closure applied to the half-filled
+    Hubbard atom, 1/(i w - t^2 G_at(i w)) with
+    G_at(i w) = (1/(i w - U/2) + 1/(i w + U/2)) / 2.
+
+    The atomic Green function has a Mott gap of width U; seeding the DMFT
+    cycle with it leads to the insulating solution where metal and insulator
+    coexist (Benchmark results section, Fig. 3).  Its 1/(i w)^3 moment is t^2,
+    like that of the semicircle.  At U = 0 it is the bath of a bare level.
+    """
+    iw = 1j * matsubara(beta, n_iw)
+    g_at = 0.5 * (1.0 / (iw - 0.5 * U) + 1.0 / (iw + 0.5 * U))
+    return bethe_step_iw(g_at, beta, t)

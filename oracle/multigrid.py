@@ -154,14 +154,17 @@ def dmft_bethe_step(g_fine, tau_fine, bath_iw, m3, U, beta, t):
 
 
 def dmft_loop(bath_iw, U, beta, t, dtaus, seed, n_iter, n_chains, warmup, sweeps, n_rec=100,
-              n_fine=200, mixing=0.0):
+              n_fine=200, mixing=0.0, ph=False):
     """The DMFT cycle of Fig. 1(c) on the Bethe lattice, n_iter times: a multigrid
     impurity solve at the current bath (fresh random streams per iteration: the
     seed moves by 2^32), then the closure Bath_new = 1/(i w - t^2 G(i w)), mixed
     as mixing * old + (1 - mixing) * new.  The bath's 1/(i w)^3 moment stays t^2.
     history[it] = (max |g - g_prev|, max g_err, D, D_err), g_prev of the first
     iteration being the starting bath's own G0(tau_j), D the extrapolated double
-    occupancy."""
+    occupancy.  With ph (a particle-hole symmetric cycle) the new bath keeps
+    only its imaginary part: the transform of a symmetric G(tau) has none, and
+    the rounding left there is magnified by an insulating bath's pole near
+    zero frequency."""
     m3 = t * t
     bath = np.asarray(bath_iw, dtype=np.complex128).copy()
     tau_f = fine_grid(beta, n_fine)
@@ -175,5 +178,7 @@ def dmft_loop(bath_iw, U, beta, t, dtaus, seed, n_iter, n_chains, warmup, sweeps
                      r["D_err"]))
         prev = r["g"]
         new = dmft_bethe_step(r["g"], r["tau"], bath, m3, U, beta, t)
+        if ph:
+            new = 1j * new.imag
         bath = mixing * bath + (1.0 - mixing) * new
     return dict(bath=bath, g=r["g"], g_err=r["g_err"], tau=tau_f, history=np.array(hist))

@@ -3,7 +3,8 @@
 The compute lives in libhfqmc.so (HIP kernels for gfx950 behind a C ABI,
 declared in include/hfqmc.h); this package is its thin Python binding.
 """
-from .api import (Context, HFQMCError, bath_to_tau, bethe_semicircle_bath,  # noqa: F401
+from .api import (Context, HFQMCError, bath_to_tau, bethe_atomic_bath,  # noqa: F401
+                  bethe_semicircle_bath,
                   dmft_bethe_step, dmft_solve, hfqmc_measure_peaks, hfqmc_solve, hfqmc_solve_dev,
                   hfqmc_solve_grids,
                   multigrid_solve)

@@ -92,6 +92,8 @@ lib.dmft_bethe_step.argtypes = [_pd, _i32, _pd, _i32, _f64, _f64, _f64, _f64, _p
 lib.dmft_bethe_step.restype = C.c_int
 lib.bethe_semicircle_bath.argtypes = [_f64, _f64, _i32, _pd]
 lib.bethe_semicircle_bath.restype = C.c_int
+lib.bethe_atomic_bath.argtypes = [_f64, _f64, _f64, _i32, _pd]
+lib.bethe_atomic_bath.restype = C.c_int
 lib.bath_to_tau.argtypes = [_pd, _i32, _f64, _f64, _i32, _pd]
 lib.bath_to_tau.restype = C.c_int
 lib.dmft_solve.argtypes = [_ctx_p, _f64, _f64, _f64, _pd, _i32, _u64, C.POINTER(Opts), _i32, _i32,
@@ -107,7 +109,7 @@ FLAG_PH_SYMMETRIC = 8      # particle-hole symmetric bath: only G_up stored (G_d
 
 EXPORTED = ["hfqmc_create", "hfqmc_destroy", "hfqmc_set_stream", "hfqmc_last_error",
             "hfqmc_solve", "hfqmc_solve_dev", "hfqmc_solve_grids", "multigrid_solve", "dmft_bethe_step",
-            "bethe_semicircle_bath", "bath_to_tau", "hfqmc_measure_peaks", "dmft_solve"]
+            "bethe_semicircle_bath", "bethe_atomic_bath", "bath_to_tau", "hfqmc_measure_peaks", "dmft_solve"]
 
 
 def ptr(a, ctype=C.c_double):

@@ -312,6 +312,13 @@ def bethe_semicircle_bath(beta, t, n_iw):
     return out.view(np.complex128)
 
 
+def bethe_atomic_bath(beta, t, U, n_iw):
+    out = np.zeros(2 * int(n_iw))
+    N.check(N.lib.bethe_atomic_bath(float(beta), float(t), float(U), int(n_iw), N.ptr(out)),
+            "bethe_atomic_bath")
+    return out.view(np.complex128)
+
+
 def bath_to_tau(bath_iw, m3, beta, L):
     b = np.ascontiguousarray(np.asarray(bath_iw, dtype=np.complex128)).view(np.float64)
     out = np.zeros(int(L))

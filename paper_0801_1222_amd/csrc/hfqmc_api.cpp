@@ -856,6 +856,13 @@ extern "C" int bethe_semicircle_bath(double beta, double t, int32_t n_iw, double
   return HFQMC_OK;
 }
 
+extern "C" int bethe_atomic_bath(double beta, double t, double U, int32_t n_iw, double* bath_iw) {
+  if (!bath_iw || !(beta > 0) || !(t > 0) || !(U >= 0) || n_iw < 1)
+    return fail(HFQMC_EINVAL, "bethe_atomic_bath: bad argument");
+  host::atomic_seed(beta, t, U, n_iw, bath_iw);
+  return HFQMC_OK;
+}
+
 extern "C" int bath_to_tau(const double* bath_iw, int32_t n_iw, double m3, double beta, int32_t L,
                            double* g_tau) {
   if (!bath_iw || !g_tau || n_iw < 16 || L < 2 || !(beta > 0)) return fail(HFQMC_EINVAL, "bath_to_tau: bad argument");
@@ -989,6 +996,12 @@ extern "C" int dmft_solve(hfqmc_ctx* c, double U, double beta, double t, const d
     }
     rc = host::bethe_step(g_fine, n_fine, bath_iw, n_iw, m3, U, beta, t, nb.data());
     if (rc) return fail(rc, "dmft_solve: Bethe step failed in iteration %d", it);
+    if (opts->flags & HFQMC_FLAG_PH_SYMMETRIC) {
+      // a symmetric G(tau) transforms to a purely imaginary G(i w); the rounding
+      // left in the real part is magnified by an insulating bath's pole near
+      // zero frequency, so it is dropped
+      for (int n = 0; n < n_iw; ++n) nb[2 * n] = 0.0;
+    }
     for (size_t q = 0; q < nb.size(); ++q) bath_iw[q] = mixing * bath_iw[q] + (1.0 - mixing) * nb[q];
   }
   if (g_fine_err) std::memcpy(g_fine_err, err.data(), sizeof(double) * n_fine);

@@ -31,6 +31,18 @@ void semicircle(double beta, double t, int n_iw, double* out) {
   }
 }
 
+// Bethe closure of the half-filled Hubbard atom, 1/(i w - t^2 G_at(i w)):
+// G_at(i w) = i w / ((i w)^2 - U^2/4) = -i w / (w^2 + U^2/4), so the bath is
+// -i / (w (1 + t^2 / (w^2 + U^2/4))), purely imaginary like the semicircle.
+void atomic_seed(double beta, double t, double U, int n_iw, double* out) {
+  const double a = 0.25 * U * U;
+  for (int n = 0; n < n_iw; ++n) {
+    const double w = matsubara(beta, n);
+    out[2 * n] = 0.0;
+    out[2 * n + 1] = -1.0 / (w * (1.0 + t * t / (w * w + a)));
+  }
+}
+
 // Positive-convention G(tau) from Matsubara data with the tail
 // 1/(i w) + m3/(i w)^3 summed in closed form:
 //   G_std(tau) = -1/2 + m3 tau (beta - tau)/4 + (2/beta) sum_n Re[e^{-i w tau} rem_n]

@@ -9,6 +9,7 @@ constexpr double kSigmaFloor = 1e-14;
 
 double matsubara(double beta, int n);
 void semicircle(double beta, double t, int n_iw, double* out);
+void atomic_seed(double beta, double t, double U, int n_iw, double* out);
 void iw_to_tau(const double* f_iw, int n_iw, double m3, double beta, const double* tau, int n_tau,
                double* out);
 void reference_iw(const double* bath_iw, int n_iw, double U, double beta, double* out);

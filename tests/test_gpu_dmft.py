@@ -46,7 +46,7 @@ def test_dmft_cycle_matches_oracle(ctx, ph):
     out = P.dmft_solve(ctx, U, beta, t, dtaus, seed, 2, bath_iw=bath, n_fine=81, n_chains=3,
                        warmup=5, sweeps=40, mode="rank1", ph=ph)
     ref = OM.dmft_loop(bath, U, beta, t, dtaus, seed, 2, n_chains=3, warmup=5, sweeps=40,
-                       n_fine=81)
+                       n_fine=81, ph=ph)
     assert np.abs(out["g"] - ref["g"]).max() < 1e-9
     assert np.abs(out["g_err"] - ref["g_err"]).max() < 1e-9
     assert np.abs(out["bath"] - ref["bath"]).max() < 1e-9

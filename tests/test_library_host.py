@@ -50,6 +50,13 @@ def test_semicircle_and_bath_transform_match_oracle():
         assert np.abs(g - go).max() < 1e-12
 
 
+def test_atomic_seed_matches_oracle():
+    import paper_0801_1222_amd as P
+    for beta, U in [(45.0, 5.0), (10.0, 0.0), (100.0, 4.8)]:
+        b = P.bethe_atomic_bath(beta, 1.0, U, 6000)
+        assert np.abs(b - OB.atomic_seed_iw(beta, 1.0, U, 6000)).max() < 1e-15
+
+
 def test_bethe_step_matches_oracle_and_fixed_point():
     import paper_0801_1222_amd as P
     beta, t = 10.0, 1.0
@@ -71,3 +78,5 @@ def test_host_argument_errors():
         P.bath_to_tau(np.zeros(4, dtype=complex), 1.0, 10.0, 20)   # n_iw < 16
     with pytest.raises(P.HFQMCError):
         P.dmft_bethe_step(np.zeros(3), np.zeros(100, dtype=complex), 1.0, 0.0, 10.0, 1.0)
+    with pytest.raises(P.HFQMCError):
+        P.bethe_atomic_bath(10.0, 1.0, -1.0, 100)                  # U < 0

@@ -6,6 +6,8 @@
 * The semicircle is a fixed point of the Bethe closure at U = 0.
 * The reference model reduces to the closed-form Hubbard atom.
 * Spline Fourier integral converges to a closed-form G(i w).
+* The insulating seed (Bethe closure of the Hubbard atom) against its
+  imaginary-time closed form from a partial-fraction expansion.
 """
 import numpy as np
 import pytest
@@ -64,3 +66,22 @@ def test_spline_fourier_converges_to_closed_form():
         errs.append(np.abs(giw - b0).max())
     assert errs[-1] < 2e-7
     assert errs[0] / errs[1] > 6 and errs[1] / errs[2] > 6
+
+
+@pytest.mark.parametrize("beta,U,L", [(45.0, 5.0, 90), (10.0, 0.0, 40), (20.0, 3.0, 57)])
+def test_atomic_seed_matches_partial_fractions(beta, U, L):
+    # 1/(z - t^2 z/(z^2 - a)) = (z^2 - a)/(z (z^2 - E^2)), a = U^2/4, E^2 = a + t^2:
+    # poles 0 (weight a/E^2) and +-E (weight t^2/(2 E^2) each); a pole at e
+    # contributes w e^{-tau e}/(1 + e^{-beta e}) to the positive-convention G(tau)
+    t = 1.0
+    b = B.atomic_seed_iw(beta, t, U, 20000)
+    g = B.bath_to_tau(b, t * t, beta, L)
+    tau = np.arange(L) * beta / L
+    a = U * U / 4.0
+    E = np.sqrt(a + t * t)
+    exact = (a / E ** 2) / 2.0 + t * t / (2.0 * E * E) * (
+        np.exp(-tau * E) + np.exp(-(beta - tau) * E)) / (1.0 + np.exp(-beta * E))
+    assert np.abs(g - exact).max() < 1e-12
+    # high-frequency moment t^2 (the same tail as the semicircle)
+    w = B.matsubara(beta, 20000)[-1]
+    assert abs((b[-1] - 1.0 / (1j * w)) * (1j * w) ** 3 - t * t) < 1e-6
