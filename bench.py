@@ -265,6 +265,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=300)
     ap.add_argument("--calib-copy", action="store_true")
+    ap.add_argument("--g-fp32", action="store_true",
+                    help="time the mixed path with G stored in FP32 between recomputes")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the peak probes and the small-L / three-grid workloads")
     args = ap.parse_args()
@@ -300,7 +302,8 @@ def main():
         # host-pointer entry (bath and results cross PCIe; used for the warm-up step)
         return P.hfqmc_solve(ctx, g0, w["U"], w["beta"], w["dtau"], w["seed"],
                              n_chains=w["n_chains"], warmup=warmup, sweeps=sweeps, mode=mode,
-                             delay_k=args.delay_k if mode != "rank1" else 0)
+                             delay_k=args.delay_k if mode != "rank1" else 0,
+                             g_fp32=args.g_fp32 and mode == "mixed")
 
     # device-resident input and outputs for the timed steps
     g0_d = torch.tensor(g0, dtype=torch.float64, device="cuda")
@@ -313,7 +316,8 @@ def main():
                                  g_d.data_ptr(), e_d.data_ptr(), d_d.data_ptr(),
                                  n_chains=w["n_chains"], warmup=w["warmup"], sweeps=w["sweeps"],
                                  mode=args.mode,
-                                 delay_k=args.delay_k if args.mode != "rank1" else 0)
+                                 delay_k=args.delay_k if args.mode != "rank1" else 0,
+                                 g_fp32=args.g_fp32)
 
     chain_sweeps = w["n_chains"] * (w["warmup"] + w["sweeps"])
     host_rate = None
@@ -414,6 +418,26 @@ def main():
                   note="same chains and sweeps; only G_up stored (G_dn = 1 - G_up^T holds for "
                        "a particle-hole symmetric bath); not the headline value")
         progress("single-matrix (particle-hole symmetric) form: %.0f sweeps/s" % phv["sweeps_per_s"])
+    g32 = None
+    if not args.no_extra and args.mode == "mixed" and not args.g_fp32:
+        # the same workload with G stored in FP32 between recomputes
+        s32 = P.hfqmc_solve_dev(ctx, g0_d.data_ptr(), L, w["U"], w["beta"], w["dtau"], w["seed"],
+                                g_d.data_ptr(), e_d.data_ptr(), d_d.data_ptr(),
+                                n_chains=w["n_chains"], warmup=w["warmup"], sweeps=w["sweeps"],
+                                mode="mixed", delay_k=args.delay_k, g_fp32=True)
+        torch.cuda.synchronize()
+        r32 = roofline(L, s32, w["n_chains"], w["sweeps"], "mixed", s32["seconds_sweep_kernel"])
+        g32_ = g_d.cpu().numpy()
+        g32 = dict(sweeps_per_s=chain_sweeps / s32["seconds_kernel"], kernel_s=s32["seconds_kernel"],
+                   speedup_vs_fp64_stored=t_launch / s32["seconds_kernel"], delay_k=s32["delay_k"],
+                   lu_panel=s32["lu_panel"], acc_rate=s32["acc_rate"], max_drift=s32["max_drift"],
+                   docc=float(d_d.cpu().numpy()[0]),
+                   max_abs_dg_vs_fp64_stored=float(np.abs(g32_ - g).max()),
+                   flop_roofline={k_: r32[k_] for k_ in ("bound", "achieved", "peak", "unit",
+                                                          "frac")},
+                   note="same chains and sweeps; G stored in FP32 between the FP64 recomputes "
+                        "(half the G traffic); not the headline value")
+        progress("FP32-stored G: %.0f sweeps/s" % g32["sweeps_per_s"])
     rank1 = None
     if args.rank1_sweeps > 0 and args.mode != "rank1":
         r = solve("rank1", 0, args.rank1_sweeps)
@@ -458,7 +482,8 @@ def main():
                    "mode": args.mode, "delay_k": st["delay_k"],
                    "recompute_every": st["recompute_every"], "n_chains": w["n_chains"], "L": L,
                    "workgroups": st["n_workgroups"], "lu_panel": st["lu_panel"],
-                   "graph": bool(st["graph"]), "autotuned": bool(st["autotuned"])},
+                   "graph": bool(st["graph"]), "autotuned": bool(st["autotuned"]),
+                   "g_fp32": bool(args.g_fp32)},
         "autotune": tune,
         "host_entry_sweeps_per_s": host_rate,
         "roofline": rf,
@@ -470,6 +495,7 @@ def main():
         "kernel_sweeps_per_s": chain_sweeps / t_launch,
         "measured_peaks": peaks,
         "ph_single_matrix": phv,
+        "fp32_stored_g": g32,
         "other_workloads": extra or None,
     }
     print(json.dumps(line), flush=True)

@@ -81,7 +81,14 @@ enum {
                                   1 - G_up^T for every field (V_dn = -V_up); R_dn, the
                                   estimators and final_green use that identity.  Halves the
                                   update, recompute and measurement work.  EINVAL unless every
-                                  bath satisfies the symmetry to 1e-9 */
+                                  bath satisfies the symmetry to 1e-9 */,
+  HFQMC_FLAG_G_FP32 = 16     /* mixed mode only (EINVAL otherwise): the Green matrices are
+                                stored in FP32 between recomputes, halving their HBM traffic.
+                                Ratios, window blocks, acceptance, estimators and the LU
+                                recompute still compute in FP64, from the FP32-stored values;
+                                each flush and each recompute rounds its result to FP32 when
+                                storing it (the reduced recompute's product reads the solved
+                                rows back in that form) */
 };
 
 typedef struct {

@@ -106,6 +106,7 @@ FLAG_EAGER = 1       # launch kernels one by one (no captured graph)
 FLAG_HEAT_BATH = 2   # heat-bath acceptance u < R/(1+R)
 FLAG_DIRECT_RECOMPUTE = 4  # full-size LU recompute instead of the reduced system
 FLAG_PH_SYMMETRIC = 8      # particle-hole symmetric bath: only G_up stored (G_dn = 1 - G_up^T)
+FLAG_G_FP32 = 16           # mixed mode: G stored in FP32 between recomputes
 
 EXPORTED = ["hfqmc_create", "hfqmc_destroy", "hfqmc_set_stream", "hfqmc_last_error",
             "hfqmc_solve", "hfqmc_solve_dev", "hfqmc_solve_grids", "multigrid_solve", "dmft_bethe_step",

@@ -61,10 +61,10 @@ class Context:
             pass
 
 
-def _flags(eager=False, heat_bath=False, direct=False, ph=False):
+def _flags(eager=False, heat_bath=False, direct=False, ph=False, g_fp32=False):
     return ((N.FLAG_EAGER if eager else 0) | (N.FLAG_HEAT_BATH if heat_bath else 0)
             | (N.FLAG_DIRECT_RECOMPUTE if direct else 0)
-            | (N.FLAG_PH_SYMMETRIC if ph else 0))
+            | (N.FLAG_PH_SYMMETRIC if ph else 0) | (N.FLAG_G_FP32 if g_fp32 else 0))
 
 
 def _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drift_limit, flags=0):
@@ -151,12 +151,12 @@ class _Hooks:
 def hfqmc_solve(ctx, g0_tau, U, beta, dtau, seed, n_chains=1, warmup=0, sweeps=1,
                 mode="rank1", recompute_every=0, delay_k=0, n_bins=0, drift_limit=0.0,
                 flip_cap=0, replay=None, want_chain=False, want_green=False, eager=False,
-                heat_bath=False, direct=False, ph=False):
+                heat_bath=False, direct=False, ph=False, g_fp32=False):
     """Fixed-dtau solve; returns dict(g, g_err, D, D_err, stats, [hooks])."""
     g0 = np.ascontiguousarray(g0_tau, dtype=np.float64)
     L = g0.shape[0]
     o = _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drift_limit,
-              _flags(eager, heat_bath, direct, ph))
+              _flags(eager, heat_bath, direct, ph, g_fp32))
     hk = _Hooks(o, 1, n_chains, [L], n_bins, flip_cap,
                 [replay] if replay is not None else None, want_chain, want_green)
     g = np.zeros(L + 1)
@@ -181,11 +181,11 @@ def hfqmc_solve(ctx, g0_tau, U, beta, dtau, seed, n_chains=1, warmup=0, sweeps=1
 def hfqmc_solve_dev(ctx, g0_tau, L, U, beta, dtau, seed, g_tau, g_err=None, docc=None,
                     n_chains=1, warmup=0, sweeps=1, mode="rank1", recompute_every=0, delay_k=0,
                     n_bins=0, drift_limit=0.0, eager=False, heat_bath=False, direct=False,
-                    ph=False):
+                    ph=False, g_fp32=False):
     """hfqmc_solve on device buffers (raw device addresses as ints, e.g. a torch
     tensor's data_ptr(), on the context's device and stream); returns the stats."""
     o = _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drift_limit,
-              _flags(eager, heat_bath, direct, ph))
+              _flags(eager, heat_bath, direct, ph, g_fp32))
     st = N.Stats()
     rc = N.lib.hfqmc_solve_dev(ctx.handle, C.c_void_p(int(g0_tau)), int(L), float(U), float(beta),
                                float(dtau), int(seed), C.byref(o), C.c_void_p(int(g_tau)),
@@ -206,7 +206,7 @@ def hfqmc_measure_peaks(ctx):
 def hfqmc_solve_grids(ctx, Ls, g0_taus, U, beta, seed, n_chains=1, warmup=0, sweeps=1,
                       mode="rank1", recompute_every=0, delay_k=0, n_bins=0, drift_limit=0.0,
                       flip_cap=0, replay=None, want_chain=False, eager=False, heat_bath=False,
-                      direct=False, ph=False):
+                      direct=False, ph=False, g_fp32=False):
     """Several grids in one persistent launch; per-grid lists in the result."""
     Ls = [int(L) for L in Ls]
     n = len(Ls)
@@ -214,7 +214,7 @@ def hfqmc_solve_grids(ctx, Ls, g0_taus, U, beta, seed, n_chains=1, warmup=0, swe
     g0 = np.ascontiguousarray(np.concatenate([np.asarray(x, dtype=np.float64) for x in g0_taus]))
     assert g0.shape[0] == sum(Ls)
     o = _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drift_limit,
-              _flags(eager, heat_bath, direct, ph))
+              _flags(eager, heat_bath, direct, ph, g_fp32))
     hk = _Hooks(o, n, n_chains, Ls, n_bins, flip_cap, replay, want_chain, False)
     P = sum(L + 1 for L in Ls)
     g = np.zeros(P)
@@ -239,13 +239,13 @@ def hfqmc_solve_grids(ctx, Ls, g0_taus, U, beta, seed, n_chains=1, warmup=0, swe
 def multigrid_solve(ctx, bath_iw, bath_m3, U, beta, dtaus, seed, n_fine=200, n_chains=1,
                     warmup=0, sweeps=1, mode="rank1", recompute_every=0, delay_k=0, n_bins=0,
                     drift_limit=0.0, eager=False, heat_bath=False, direct=False,
-                    ph=False):
+                    ph=False, g_fp32=False):
     """dtau -> 0 extrapolated G(tau_j), tau_j = j beta/(n_fine-1)."""
     b = np.ascontiguousarray(np.asarray(bath_iw, dtype=np.complex128)).view(np.float64)
     n_iw = b.shape[0] // 2
     dt = np.ascontiguousarray(dtaus, dtype=np.float64)
     o = _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drift_limit,
-              _flags(eager, heat_bath, direct, ph))
+              _flags(eager, heat_bath, direct, ph, g_fp32))
     Ls = [int(round(beta / x)) for x in dt]
     gf = np.zeros(n_fine)
     ef = np.zeros(n_fine)
@@ -270,7 +270,7 @@ def multigrid_solve(ctx, bath_iw, bath_m3, U, beta, dtaus, seed, n_fine=200, n_c
 def dmft_solve(ctx, U, beta, t, dtaus, seed, n_iter, bath_iw=None, n_iw=4096, n_fine=200,
                mixing=0.0, n_chains=1, warmup=0, sweeps=1, mode="rank1", recompute_every=0,
                delay_k=0, n_bins=0, drift_limit=0.0, eager=False, heat_bath=False, direct=False,
-               ph=False):
+               ph=False, g_fp32=False):
     """Multigrid DMFT cycle on the Bethe lattice; starts from bath_iw (default:
     the U = 0 semicircle).  Returns dict(bath, g, g_err, tau, history) with
     history[it] = (max |g - g_prev|, max g_err, D, D_err), D the extrapolated
@@ -281,7 +281,7 @@ def dmft_solve(ctx, U, beta, t, dtaus, seed, n_iter, bath_iw=None, n_iw=4096, n_
     n_iw = b.shape[0] // 2
     dt = np.ascontiguousarray(dtaus, dtype=np.float64)
     o = _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drift_limit,
-              _flags(eager, heat_bath, direct, ph))
+              _flags(eager, heat_bath, direct, ph, g_fp32))
     gf = np.zeros(n_fine)
     ef = np.zeros(n_fine)
     hist = np.zeros(4 * int(n_iter))

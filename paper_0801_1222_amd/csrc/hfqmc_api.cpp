@@ -193,8 +193,10 @@ int resolve_opts(const hfqmc_opts* o, Resolved* r) {
   r->warmup = o->warmup;
   r->sweeps = o->sweeps;
   if (o->flags & ~(HFQMC_FLAG_EAGER | HFQMC_FLAG_HEAT_BATH | HFQMC_FLAG_DIRECT_RECOMPUTE |
-                   HFQMC_FLAG_PH_SYMMETRIC))
+                   HFQMC_FLAG_PH_SYMMETRIC | HFQMC_FLAG_G_FP32))
     return fail(HFQMC_EINVAL, "flags=0x%x", o->flags);
+  if ((o->flags & HFQMC_FLAG_G_FP32) && o->mode != MODE_MIXED)
+    return fail(HFQMC_EINVAL, "HFQMC_FLAG_G_FP32 needs the mixed mode (mode=%d)", o->mode);
   if (o->mode == MODE_RANK1) {
     r->delay_k = 1;
     r->window_b = 1;
@@ -235,7 +237,8 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
 int autotune(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double* g0_tau, bool dev_io,
              double U, double beta, uint64_t seed, const hfqmc_opts* opts, int Lmax,
              TuneChoice* out, double* seconds) {
-  std::vector<int> key = {opts->mode, opts->n_chains, opts->flags & HFQMC_FLAG_PH_SYMMETRIC};
+  std::vector<int> key = {opts->mode, opts->n_chains,
+                          opts->flags & (HFQMC_FLAG_PH_SYMMETRIC | HFQMC_FLAG_G_FP32)};
   long long Lsum = 0;
   for (int i = 0; i < n_grids; ++i) {
     key.push_back(Ls[i]);
@@ -282,7 +285,7 @@ int autotune(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double* g0_tau,
   to.recompute_every = opts->recompute_every;
   to.n_bins = 1;
   to.flags = (opts->flags & (HFQMC_FLAG_HEAT_BATH | HFQMC_FLAG_DIRECT_RECOMPUTE |
-                             HFQMC_FLAG_PH_SYMMETRIC)) | HFQMC_FLAG_EAGER;
+                             HFQMC_FLAG_PH_SYMMETRIC | HFQMC_FLAG_G_FP32)) | HFQMC_FLAG_EAGER;
   long long P = 0;
   for (int i = 0; i < n_grids; ++i) P += Ls[i] + 1;
   std::vector<double> gs(P), es(P), ds(2 * n_grids);
@@ -512,7 +515,7 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
   p.warmup = r.warmup;
   p.sweeps = r.sweeps;
   p.n_rec = r.n_rec;
-  p.mode = r.mode;
+  p.mode = (opts->flags & HFQMC_FLAG_G_FP32) ? MODE_MIXED_G32 : r.mode;
   p.delay_k = r.delay_k;
   p.window_b = r.window_b;
   p.n_bins = nbin;

@@ -32,7 +32,8 @@ enum {
   NSTAT = 22
 };
 
-enum { MODE_RANK1 = 0, MODE_DELAYED_FP64 = 1, MODE_MIXED = 2 };
+enum { MODE_RANK1 = 0, MODE_DELAYED_FP64 = 1, MODE_MIXED = 2,
+       MODE_MIXED_G32 = 3 /* mixed with G stored in FP32 (the sweep kernel's mode only) */ };
 
 // One Trotter grid of a (possibly batched) launch.  All pointers are device pointers.
 struct GridDev {

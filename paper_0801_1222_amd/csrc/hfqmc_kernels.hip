@@ -155,6 +155,12 @@ __global__ void k_zero(T* p, long long n) {
 // count against the LDS wait counter.
 typedef __attribute__((address_space(1))) double gdouble;
 typedef __attribute__((address_space(1))) const double gcdouble;
+typedef __attribute__((address_space(1))) float gfloat;
+// global element type of the stored Green matrices: FP64, or FP32 where G is
+// kept in single precision between recomputes
+template <typename GT> struct GlobalOf;
+template <> struct GlobalOf<double> { typedef gdouble type; };
+template <> struct GlobalOf<float> { typedef gfloat type; };
 
 constexpr int kStatBytes = 256;   // LDS statistics block: NSTAT counters + drift
 static_assert(NSTAT * 8 + 8 <= kStatBytes, "statistics block too small");
@@ -426,12 +432,13 @@ __device__ __forceinline__ void lu_strip_forward_mfma(double* __restrict__ A, in
 
 // Backward, block at kb: X_b = U11^{-1} Y_b (Li = U11^{-1}), then
 // Y[0:kb] -= U01 X_b with U01 = P rows 0..kb-1.
-template <int NB>
+template <int NB, typename GT>
 __device__ __forceinline__ void lu_strip_backward_mfma(double* __restrict__ A, int lda, int kb,
                                                        int np, int cend16,
                                                        const double* __restrict__ P, int ps,
                                                        const double* __restrict__ Li, int ls,
-                                                       gdouble* __restrict__ Gs, int ns, int L,
+                                                       typename GlobalOf<GT>::type* __restrict__ Gs,
+                                                       int ns, int L,
                                                        const int* __restrict__ rowmap,
                                                        double& dmax,
                                                        const int* __restrict__ perm) {
@@ -732,11 +739,12 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* red, int* total)
 // kept in the workspace Pq.  Kept light in registers (short operand batches,
 // the drift's old values read at the store) so that it adds no pressure to
 // the sweep kernel; returns this thread's largest drift (the caller reduces it).
+template <typename GT>
 __device__ __forceinline__ double reduced_product_slabs(
     const double* __restrict__ Aq, double* __restrict__ Pq, double* __restrict__ Zl,
-    double* __restrict__ Gs_, const double* __restrict__ Hr_, const int* __restrict__ sr, int ns,
+    GT* __restrict__ Gs_, const double* __restrict__ Hr_, const int* __restrict__ sr, int ns,
     int nR, int kr, int L, long long lu_scr_bytes) {
-  gdouble* __restrict__ Gs = (gdouble*)Gs_;
+  typename GlobalOf<GT>::type* __restrict__ Gs = (typename GlobalOf<GT>::type*)Gs_;
   gcdouble* __restrict__ Hr = (gcdouble*)Hr_;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int* Rl = sr + ns;
@@ -873,14 +881,15 @@ __device__ __forceinline__ double reduced_product_slabs(
 //
 // rhs_k (direct form only): right-hand side K = 1 - G0 instead of G0 (the
 // reference matrices Q_r).
-__device__ __forceinline__ double dyson_solve(const Chain& ch, int sigma, double* Gs_,
+template <typename GT>
+__device__ __forceinline__ double dyson_solve(const Chain& ch, int sigma, GT* Gs_,
                                               int NB, bool reduced, bool rhs_k) {
   const int L = ch.L;
   const int t = threadIdx.x;
   const int lane = t & 63, wv = t >> 6;
   const double ep = ch.ep, em = ch.em;
   const int8_t* s = ch.s;
-  gdouble* __restrict__ Gs = (gdouble*)Gs_;
+  typename GlobalOf<GT>::type* __restrict__ Gs = (typename GlobalOf<GT>::type*)Gs_;
   gcdouble* __restrict__ G0 = (gcdouble*)ch.G0;
   double* __restrict__ A = ch.A;
   int* sr = ch.sr;                                       // reduced form only
@@ -1137,11 +1146,11 @@ __device__ __forceinline__ double dyson_solve(const Chain& ch, int sigma, double
     __syncthreads();
     if (NB >= 16) {
       if (NB == 32)
-        lu_strip_backward_mfma<32>(A, lda, kb, np, cend16, P, ps, Li, ls, Gs, ns, L, rowmap, dmax,
-                                   perm);
+        lu_strip_backward_mfma<32, GT>(A, lda, kb, np, cend16, P, ps, Li, ls, Gs, ns, L, rowmap,
+                                       dmax, perm);
       else
-        lu_strip_backward_mfma<16>(A, lda, kb, np, cend16, P, ps, Li, ls, Gs, ns, L, rowmap, dmax,
-                                   perm);
+        lu_strip_backward_mfma<16, GT>(A, lda, kb, np, cend16, P, ps, Li, ls, Gs, ns, L, rowmap,
+                                       dmax, perm);
     } else {
       switch (NB) {
         case 8: lu_strip_backward<8>(A, lda, kb, np, cend, P, ps); break;
@@ -1312,9 +1321,12 @@ __device__ __forceinline__ double dyson_solve(const Chain& ch, int sigma, double
 // spin-down sum over i becomes, with j = (i - k) mod L,
 //   sum_i sgn G_dn(i, j) = L delta_k0 - sum_j sgn' G_up(j, (j + k) mod L),
 // sgn' = -1 where j + k wraps: again one contiguous stretch of a row per step.
+template <typename GT>
 __device__ __forceinline__ void measure(const Chain& ch, int bin, bool ph) {
   const int L = ch.L;
   double* accg = ch.accg;
+  const GT* Gup = reinterpret_cast<const GT*>(ch.Gu);
+  const GT* Gdn = reinterpret_cast<const GT*>(ch.Gd);
   for (int k = threadIdx.x; k < L; k += kThreads) {
     // step i: every thread of a wave reads row i (one contiguous stretch):
     // G(i, i - k), with sign - where i - k wraps
@@ -1329,8 +1341,8 @@ __device__ __forceinline__ void measure(const Chain& ch, int bin, bool ph) {
           sg = -1.0;
         }
         const long long o = (long long)i * L + j;
-        up += sg * ch.Gu[o];
-        dn += sg * ch.Gd[o];
+        up += sg * Gup[o];
+        dn += sg * Gdn[o];
       }
     } else {
       // and G_up(i, i + k), with sign - where i + k wraps, for the spin-down term
@@ -1347,7 +1359,7 @@ __device__ __forceinline__ void measure(const Chain& ch, int bin, bool ph) {
           j2 -= L;
           sg2 = -1.0;
         }
-        const double* row = ch.Gu + (long long)i * L;
+        const GT* row = Gup + (long long)i * L;
         up += sg * row[j];
         tr += sg2 * row[j2];
       }
@@ -1361,8 +1373,8 @@ __device__ __forceinline__ void measure(const Chain& ch, int bin, bool ph) {
   double dsum = 0.0;
   for (int l = threadIdx.x; l < L; l += kThreads) {
     const long long o = (long long)l * L + l;
-    const double gu = ch.Gu[o];
-    dsum += (1.0 - gu) * (ph ? gu : 1.0 - ch.Gd[o]);
+    const double gu = Gup[o];
+    dsum += (1.0 - gu) * (ph ? gu : 1.0 - Gdn[o]);
   }
   dsum = block_sum(dsum, ch.red);
   if (threadIdx.x == 0) {
@@ -1431,6 +1443,7 @@ __device__ __forceinline__ void log_flip(const ChainIO& io, long long* st, long 
 
 // Dyson recompute of both spins (the kernel's only call site of the LU, so it
 // is inlined once).  The initial recompute of a chain is not counted as one.
+template <typename GT>
 __device__ __forceinline__ void recompute_both(const SweepParams& p, const Chain& ch, Counters& k,
                                                bool counted) {
   const long long t0 = wall_clock64();
@@ -1438,7 +1451,8 @@ __device__ __forceinline__ void recompute_both(const SweepParams& p, const Chain
   const int nsp = p.ph ? 1 : 2;
 #pragma unroll 1
   for (int sp = 0; sp < nsp; ++sp)
-    d = fmax(d, dyson_solve(ch, sp ? -1 : +1, sp ? ch.Gd : ch.Gu, ch.lu_nb, ch.reduced, false));
+    d = fmax(d, dyson_solve(ch, sp ? -1 : +1, reinterpret_cast<GT*>(sp ? ch.Gd : ch.Gu), ch.lu_nb,
+                            ch.reduced, false));
   if (counted && threadIdx.x == 0) {
     *ch.drift = fmax(*ch.drift, d);
     ch.st[ST_RECOMPUTES] += 1;
@@ -1607,9 +1621,9 @@ constexpr int kCW = 64;          // columns per work item (4 output tiles)
 constexpr int kCT = kCW / 16;
 constexpr int kYK = kMaxK + 4;   // LDS stride of a staged Y column
 
-template <bool MIXED>
+template <bool MIXED, typename GT>
 __device__ __forceinline__ void flush_gemm(
-    double* __restrict__ G, const typename std::conditional<MIXED, float, double>::type* __restrict__ X,
+    GT* __restrict__ G, const typename std::conditional<MIXED, float, double>::type* __restrict__ X,
     const typename std::conditional<MIXED, float, double>::type* __restrict__ Y, int L, int m,
     char* __restrict__ ybuf, int ybytes) {
   typedef typename std::conditional<MIXED, float, double>::type T;
@@ -1656,21 +1670,22 @@ __device__ __forceinline__ void flush_gemm(
     const int hi = (int)((long long)items * (wv + 1) / (kThreads / 64));
     if (lo >= hi) continue;
     // G of item `it` for this lane: 4 rows x kCT tiles (clamped, in bounds)
-    auto load_g = [&](int it, double (&g)[kCT][4]) {
+    auto load_g = [&](int it, GT (&g)[kCT][4]) {
       const int st = it / nchunk, chk = it - st * nchunk;
 #pragma unroll
       for (int ct = 0; ct < kCT; ++ct) {
         const int col = min(c0 + chk * kCW + 16 * ct + li, L - 1);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const unsigned o = (unsigned)(min(16 * st + orow_off[r], L - 1) * L + col) << 3;
-          g[ct][r] = *reinterpret_cast<const double*>(Gc + o);
+          const unsigned o = (unsigned)(min(16 * st + orow_off[r], L - 1) * L + col)
+                             << (sizeof(GT) == 8 ? 3 : 2);
+          g[ct][r] = *reinterpret_cast<const GT*>(Gc + o);
         }
       }
     };
     T a[KS];
     int cur_strip = -1;
-    auto process = [&](int it, const double (&gcur)[kCT][4]) {
+    auto process = [&](int it, const GT (&gcur)[kCT][4]) {
       const int st = it / nchunk, chk = it - st * nchunk;
       if (st != cur_strip) {
         cur_strip = st;
@@ -1707,13 +1722,13 @@ __device__ __forceinline__ void flush_gemm(
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int row = 16 * st + orow_off[r];
-          if (cok && row < L) G[row * L + col] = gcur[ct][r] + (double)acc[ct][r];
+          if (cok && row < L) G[row * L + col] = (GT)((double)gcur[ct][r] + (double)acc[ct][r]);
         }
       }
     };
     // three G buffers in turn: the loads of the next two items are in flight
     // while one item runs on the matrix cores
-    double g0[kCT][4], g1[kCT][4], g2[kCT][4];
+    GT g0[kCT][4], g1[kCT][4], g2[kCT][4];
     load_g(lo, g0);
     if (lo + 1 < hi) load_g(lo + 1, g1);
 #pragma unroll 1
@@ -1737,8 +1752,8 @@ __device__ __forceinline__ void flush_gemm(
 // Y on the matrix cores (FP64) in wave-independent 16 x 16 tiles whose G rows
 // are loaded one tile ahead.  X and Y are stored in the product's operand
 // type T (FP32 in the mixed path: the product rounds them to FP32 anyway).
-template <typename T>
-__device__ __forceinline__ void flush_vectors(const double* __restrict__ G, int L, int l0, int m,
+template <typename T, typename GT>
+__device__ __forceinline__ void flush_vectors(const GT* __restrict__ G, int L, int l0, int m,
                                               const int* __restrict__ F,
                                               const double* __restrict__ W,
                                               T* __restrict__ X, T* __restrict__ Y) {
@@ -1942,6 +1957,7 @@ __device__ __forceinline__ void invert_ts(const WinLds& w, int m_inv, int m, int
 //   Xrec[i][r] = X(l0 + r, i) = sum_{i'} C0(l0 + r, i') T[i'][i],
 //   Yrec[i][c] = Y(i, l0 + c) = sum_{i'} S[i][i'] G(f_i', l0 + c),
 // then the window blocks W = G(B,B) + X(B,:) Y(:,B), all FP64 on the matrix cores.
+template <typename GT>
 __device__ __forceinline__ void window_apply(const Chain& ch, const WinLds& w, int l0, int b, int m,
                                              int nsp) {
   const int L = ch.L;
@@ -1956,7 +1972,7 @@ __device__ __forceinline__ void window_apply(const Chain& ch, const WinLds& w, i
   for (int tile = wv; tile < ntile; tile += kThreads / 64) {
     const int sp = tile >= 2 * nx;
     const int e = tile - sp * 2 * nx;
-    const double* G = sp ? ch.Gd : ch.Gu;
+    const GT* G = reinterpret_cast<const GT*>(sp ? ch.Gd : ch.Gu);
     const double* TS = sp ? w.ULd : w.ULu;
     doublex4 acc = {0.0, 0.0, 0.0, 0.0};
     if (e < nx) {
@@ -2021,7 +2037,7 @@ __device__ __forceinline__ void window_apply(const Chain& ch, const WinLds& w, i
   for (int tile = wv; tile < 16 * nsp; tile += kThreads / 64) {
     const int sp = tile >> 4, e = tile & 15;
     const int rb = e >> 2, cb = e & 3;
-    const double* G = sp ? ch.Gd : ch.Gu;
+    const GT* G = reinterpret_cast<const GT*>(sp ? ch.Gd : ch.Gu);
     double* W = sp ? w.Wd : w.Wu;
     const int col = cb * 16 + li;
     doublex4 acc;
@@ -2078,7 +2094,7 @@ __device__ __forceinline__ void capture_coefficients(const Chain& ch, const WinL
 
 // Applies the m pending flips (T, S complete up to m) to G_up and G_dn (nsp = 2)
 // or to G_up alone (nsp = 1).
-template <bool MIXED>
+template <bool MIXED, typename GT>
 __device__ __forceinline__ void flush_pending(const Chain& ch, const WinLds& w, int m, int nsp) {
   typedef typename std::conditional<MIXED, float, double>::type T;
   const int L = ch.L;
@@ -2090,15 +2106,16 @@ __device__ __forceinline__ void flush_pending(const Chain& ch, const WinLds& w, 
   if (threadIdx.x == 0) ch.st[ST_T_FOLD] += t1 - t0;
 #pragma unroll 1
   for (int sp = 0; sp < nsp; ++sp)
-    flush_vectors(sp ? ch.Gd : ch.Gu, L, 0, m, w.F, sp ? w.ULd : w.ULu, X + (long long)sp * L * kMaxK,
-                  Y + (long long)sp * kMaxK * L);
+    flush_vectors<T, GT>(reinterpret_cast<const GT*>(sp ? ch.Gd : ch.Gu), L, 0, m, w.F,
+                         sp ? w.ULd : w.ULu, X + (long long)sp * L * kMaxK,
+                         Y + (long long)sp * kMaxK * L);
   __syncthreads();
   const long long t2 = wall_clock64();
   char* un = ch.scratch + kSmall;
 #pragma unroll 1
   for (int sp = 0; sp < nsp; ++sp)
-    flush_gemm<MIXED>(sp ? ch.Gd : ch.Gu, X + (long long)sp * L * kMaxK,
-                      Y + (long long)sp * kMaxK * L, L, m, un, ch.scratch_bytes - kSmall);
+    flush_gemm<MIXED, GT>(reinterpret_cast<GT*>(sp ? ch.Gd : ch.Gu), X + (long long)sp * L * kMaxK,
+                          Y + (long long)sp * kMaxK * L, L, m, un, ch.scratch_bytes - kSmall);
   __syncthreads();
   if (threadIdx.x == 0) {
     ch.st[ST_T_FL_VEC] += t2 - t1;
@@ -2106,7 +2123,7 @@ __device__ __forceinline__ void flush_pending(const Chain& ch, const WinLds& w, 
   }
 }
 
-template <bool MIXED>
+template <bool MIXED, typename GT>
 __device__ __forceinline__ int sweep_window(const SweepParams& p, const Chain& ch, long long sw,
                                             Counters& k, const ChainIO& io, int l_begin) {
   const int L = ch.L;
@@ -2125,7 +2142,7 @@ __device__ __forceinline__ int sweep_window(const SweepParams& p, const Chain& c
       const long long t0 = wall_clock64();
       invert_ts(w, m_inv, m, nsp);
       m_inv = m;
-      window_apply(ch, w, l0, b, m, nsp);
+      window_apply<GT>(ch, w, l0, b, m, nsp);
       if (t == 0) {
         const long long dt = wall_clock64() - t0;
         ch.st[ST_T_FLUSH] += dt;
@@ -2136,8 +2153,8 @@ __device__ __forceinline__ int sweep_window(const SweepParams& p, const Chain& c
         const int q = idx >> 6, r = idx & 63;
         if (q < b && r < b) {
           const long long o = (long long)(l0 + q) * L + l0 + r;
-          w.Wu[q * kWP + r] = ch.Gu[o];
-          if (!ph) w.Wd[q * kWP + r] = ch.Gd[o];
+          w.Wu[q * kWP + r] = reinterpret_cast<const GT*>(ch.Gu)[o];
+          if (!ph) w.Wd[q * kWP + r] = reinterpret_cast<const GT*>(ch.Gd)[o];
         }
       }
       __syncthreads();
@@ -2210,7 +2227,7 @@ __device__ __forceinline__ int sweep_window(const SweepParams& p, const Chain& c
       const long long t0 = wall_clock64();
       invert_ts(w, m_inv, m, nsp);
       if (t == 0) ch.st[ST_T_FOLD] += wall_clock64() - t0;
-      flush_pending<MIXED>(ch, w, m, nsp);
+      flush_pending<MIXED, GT>(ch, w, m, nsp);
       if (t == 0) {
         ch.st[ST_T_FLUSH] += wall_clock64() - t0;
         ch.st[ST_FLUSHES] += 1;
@@ -2268,8 +2285,10 @@ __device__ __forceinline__ void setup_chain(Chain& ch, const SweepParams& p, con
   ch.scratch_bytes = scratch_bytes;
 }
 
+template <bool G32>
 __device__ __forceinline__ void run_chain(const SweepParams& p, const GridDev* gd, int chain, double* ws,
                           char* lds) {
+  typedef typename std::conditional<G32, float, double>::type GT;   // stored G
   Chain ch;
   setup_chain(ch, p, gd, chain, ws, lds, gd->lu_nb, p.lds_scratch_bytes);
   const int L = ch.L;
@@ -2310,7 +2329,7 @@ __device__ __forceinline__ void run_chain(const SweepParams& p, const GridDev* g
   bool need_rec = true, first = true;
   for (;;) {
     if (need_rec) {
-      recompute_both(p, ch, k, !first);
+      recompute_both<GT>(p, ch, k, !first);
       first = false;
       need_rec = false;
     }
@@ -2319,7 +2338,7 @@ __device__ __forceinline__ void run_chain(const SweepParams& p, const GridDev* g
         const long long t1 = wall_clock64();
         const long long msw = sw - p.warmup;
         const int bin = (int)((msw * nb) / p.sweeps);
-        measure(ch, bin, p.ph != 0);
+        measure<GT>(ch, bin, p.ph != 0);
         stat_add(ch.st, ST_T_MEAS, wall_clock64() - t1);
       }
       __syncthreads();
@@ -2330,12 +2349,16 @@ __device__ __forceinline__ void run_chain(const SweepParams& p, const GridDev* g
     const long long t0 = wall_clock64();
     const long long f0 = threadIdx.x == 0 ? ch.st[ST_T_FLUSH] : 0;
     int nl;
-    if (p.mode == MODE_RANK1)
-      nl = sweep_rank1(p, ch, sw, k, io, l);
-    else if (p.mode == MODE_MIXED)
-      nl = sweep_window<true>(p, ch, sw, k, io, l);
-    else
-      nl = sweep_window<false>(p, ch, sw, k, io, l);
+    if constexpr (G32) {
+      nl = sweep_window<true, float>(p, ch, sw, k, io, l);
+    } else {
+      if (p.mode == MODE_RANK1)
+        nl = sweep_rank1(p, ch, sw, k, io, l);
+      else if (p.mode == MODE_MIXED)
+        nl = sweep_window<true, double>(p, ch, sw, k, io, l);
+      else
+        nl = sweep_window<false, double>(p, ch, sw, k, io, l);
+    }
     if (threadIdx.x == 0) ch.st[ST_T_SWEEP] += (wall_clock64() - t0) - (ch.st[ST_T_FLUSH] - f0);
     need_rec = (k.acc_since == p.n_rec);
     l = nl;
@@ -2349,13 +2372,15 @@ __device__ __forceinline__ void run_chain(const SweepParams& p, const GridDev* g
   }
   if (gd->g_final) {
     double* out = gd->g_final + (long long)chain * 2 * L2;
+    const GT* Gup = reinterpret_cast<const GT*>(ch.Gu);
+    const GT* Gdn = reinterpret_cast<const GT*>(ch.Gd);
     for (long long idx = threadIdx.x; idx < L2; idx += kThreads) {
-      out[idx] = ch.Gu[idx];
+      out[idx] = Gup[idx];
       if (p.ph) {
         const long long i = idx / L, j = idx - i * L;   // G_dn(i, j) = delta_ij - G_up(j, i)
-        out[L2 + idx] = (i == j ? 1.0 : 0.0) - ch.Gu[j * L + i];
+        out[L2 + idx] = (i == j ? 1.0 : 0.0) - Gup[j * L + i];
       } else {
-        out[L2 + idx] = ch.Gd[idx];
+        out[L2 + idx] = Gdn[idx];
       }
     }
   }
@@ -2364,6 +2389,9 @@ __device__ __forceinline__ void run_chain(const SweepParams& p, const GridDev* g
 
 // ------------------------------------------------- persistent kernel ----
 
+// G32: the mixed update with G stored in FP32 (a kernel of its own; the other
+// modes share one kernel and choose their sweep at run time)
+template <bool G32>
 __global__ void __launch_bounds__(kThreads) k_sweeps(SweepParams p) {
   extern __shared__ __align__(16) char lds[];
   __shared__ int s_unit;
@@ -2376,7 +2404,7 @@ __global__ void __launch_bounds__(kThreads) k_sweeps(SweepParams p) {
     if (unit >= p.n_units) break;
     const int code = p.units[unit];
     const int gi = code >> 20, c = code & 0xFFFFF;
-    run_chain(p, p.grids + gi, c, ws, lds);
+    run_chain<G32>(p, p.grids + gi, c, ws, lds);
   }
 }
 
@@ -2547,11 +2575,18 @@ hipError_t launch_zero_i32(int* p, long long n, hipStream_t s) {
 
 hipError_t prepare_sweeps(int lds) {
   if (lds <= 64 * 1024) return hipSuccess;
-  return hipFuncSetAttribute((const void*)k_sweeps, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  const hipError_t e = hipFuncSetAttribute((const void*)k_sweeps<false>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_sweeps<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             lds);
 }
 
 hipError_t launch_sweeps(const SweepParams& p, int n_wg, int lds, hipStream_t s) {
-  hipLaunchKernelGGL(k_sweeps, dim3(n_wg), dim3(kThreads), lds, s, p);
+  if (p.mode == MODE_MIXED_G32)
+    hipLaunchKernelGGL(k_sweeps<true>, dim3(n_wg), dim3(kThreads), lds, s, p);
+  else
+    hipLaunchKernelGGL(k_sweeps<false>, dim3(n_wg), dim3(kThreads), lds, s, p);
   return hipGetLastError();
 }
 
