@@ -272,8 +272,9 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU; --gpus %d is not supported "
-              "(independent chains shard across GPUs; see the design notes)" % args.gpus,
+        print("bench.py: the library runs on one GPU; --gpus %d is not supported "
+              "(independent chains would shard across GPUs with one all-reduce of the "
+              "accumulators per multigrid step)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
     if args.calib_copy:
