@@ -63,10 +63,24 @@ def dyson_matrix(G0, s, lam, sigma):
     return eye + (eye - G0) * potential_factors(s, lam, sigma)[None, :]
 
 
+def spin_baths(g_tau):
+    """(G0_up(tau_k), G0_dn(tau_k)): a pair as given, or one bath for both spins."""
+    if isinstance(g_tau, (tuple, list)) and len(g_tau) == 2 and np.ndim(g_tau[0]) == 1:
+        up = np.asarray(g_tau[0], dtype=np.float64)
+        dn = np.asarray(g_tau[1], dtype=np.float64)
+        if up.shape != dn.shape:
+            raise ValueError("spin baths of different lengths")
+        return up, dn
+    g = np.asarray(g_tau, dtype=np.float64)
+    return g, g
+
+
 def green_from_field(G0, s, lam):
-    """Exact G_up, G_dn for field s: solve M_sigma G_sigma = G0 (LU, partial pivoting)."""
-    Gu = np.linalg.solve(dyson_matrix(G0, s, lam, +1), G0)
-    Gd = np.linalg.solve(dyson_matrix(G0, s, lam, -1), G0)
+    """Exact G_up, G_dn for field s: solve M_sigma G_sigma = G0_sigma (LU, partial
+    pivoting).  G0 is one bath matrix for both spins or a pair (up, down)."""
+    G0u, G0d = G0 if isinstance(G0, tuple) else (G0, G0)
+    Gu = np.linalg.solve(dyson_matrix(G0u, s, lam, +1), G0u)
+    Gd = np.linalg.solve(dyson_matrix(G0d, s, lam, -1), G0d)
     return Gu, Gd
 
 
@@ -112,6 +126,23 @@ def measure(Gu, Gd):
     return out, D
 
 
+def measure_spins(Gu, Gd):
+    """Spin-resolved estimator: G_sigma(tau_k) = 1/L sum_l sgn G_sigma[(l+k) mod L, l],
+    G_sigma(beta-) = 1 - G_sigma(0+) = n_sigma.  Returns [2, L+1] (up, down); their
+    mean is the estimator of ``measure``."""
+    L = Gu.shape[0]
+    out = np.empty((2, L + 1))
+    l = np.arange(L)
+    for k in range(L):
+        r = l + k
+        sgn = np.where(r < L, 1.0, -1.0)
+        rr = np.mod(r, L)
+        out[0, k] = np.sum(sgn * Gu[rr, l]) / L
+        out[1, k] = np.sum(sgn * Gd[rr, l]) / L
+    out[:, L] = 1.0 - out[:, 0]
+    return out
+
+
 # -------------------------------------------------------------- chains ----
 
 def run_chain(g_tau, U, beta, seed, chain=0, grid_id=0, warmup=0, sweeps=1,
@@ -134,18 +165,23 @@ def run_chain(g_tau, U, beta, seed, chain=0, grid_id=0, warmup=0, sweeps=1,
     ``flush_fp32`` performs that flush as float32 A B^T with float32
     accumulation added to the float64 G (mixed-precision emulation).
 
+    ``g_tau``: one bath for both spins, or a pair (up, down) of spin-dependent
+    baths (a magnetic field, magnetic phases); ``bins_gs`` holds the
+    spin-resolved sums of ``measure_spins`` either way.
+
     Returns a dict with the accumulated estimators and bookkeeping.
     """
-    g_tau = np.asarray(g_tau, dtype=np.float64)
-    L = g_tau.shape[0]
+    g_up, g_dn = spin_baths(g_tau)
+    L = g_up.shape[0]
     dtau = beta / L
     lam = hs_lambda(U, dtau)
     gp, gm = flip_gammas(lam)
-    G0 = g0_matrix(g_tau)
+    G0 = (g0_matrix(g_up), g0_matrix(g_dn))
     s = philox.initial_field(seed, chain, grid_id, L).astype(np.int64)
     Gu, Gd = green_from_field(G0, s, lam)
 
     bins_g = np.zeros((n_bins, L + 1))
+    bins_gs = np.zeros((n_bins, 2, L + 1))
     bins_d = np.zeros(n_bins)
     bins_n = np.zeros(n_bins, dtype=np.int64)
     flips = []
@@ -228,11 +264,12 @@ def run_chain(g_tau, U, beta, seed, chain=0, grid_id=0, warmup=0, sweeps=1,
             meas = sw - warmup
             b = (meas * n_bins) // sweeps
             bins_g[b] += g
+            bins_gs[b] += measure_spins(Gu, Gd)
             bins_d[b] += D
             bins_n[b] += 1
             if keep_trace:
                 trace.append((g, D))
-    return dict(L=L, lam=lam, bins_g=bins_g, bins_d=bins_d, bins_n=bins_n,
+    return dict(L=L, lam=lam, bins_g=bins_g, bins_gs=bins_gs, bins_d=bins_d, bins_n=bins_n,
                 flips=flips, n_proposed=n_prop, n_accepted=n_acc, n_bad=n_bad,
                 n_recomputes=n_recs, max_drift=max_drift, field=s.copy(),
                 Gu=Gu, Gd=Gd, trace=trace)
@@ -281,18 +318,19 @@ def solve(g_tau, U, beta, seed, n_chains=1, warmup=0, sweeps=1, n_rec=100,
 
 # --------------------------------------------------------- brute force ----
 
-def brute_force(g_tau, U, beta, batch=4096):
+def brute_force(g_tau, U, beta, batch=4096, spins=False):
     """Exact fixed-dtau expectation by enumerating all 2^L fields.
 
     Weight w(s) = det M_up(s) det M_dn(s) (the HS weight up to an s-independent
-    factor); returns (G(tau_k) [L+1], D, min weight / max weight).
+    factor); returns (G(tau_k) [L+1], D, min weight / max weight), with
+    ``spins`` the spin-resolved G_sigma(tau_k) [2, L+1] in place of G.  g_tau:
+    one bath or a pair (up, down) as in ``run_chain``.
     """
-    g_tau = np.asarray(g_tau, dtype=np.float64)
-    L = g_tau.shape[0]
+    g_up, g_dn = spin_baths(g_tau)
+    L = g_up.shape[0]
     lam = hs_lambda(U, beta / L)
-    G0 = g0_matrix(g_tau)
+    G0s = (g0_matrix(g_up), g0_matrix(g_dn))
     eye = np.eye(L)
-    K = eye - G0
     n_conf = 1 << L
     logw_all = []
     g_all = []
@@ -304,9 +342,9 @@ def brute_force(g_tau, U, beta, batch=4096):
         sign_tot = np.ones(idx.shape[0])
         logw = np.zeros(idx.shape[0])
         Gs = []
-        for sigma in (+1, -1):
+        for sigma, G0 in ((+1, G0s[0]), (-1, G0s[1])):
             f = np.expm1(lam * sigma * s)
-            M = eye[None] + K[None] * f[:, None, :]
+            M = eye[None] + (eye - G0)[None] * f[:, None, :]
             sg, ld = np.linalg.slogdet(M)
             sign_tot *= sg
             logw += ld
@@ -316,14 +354,14 @@ def brute_force(g_tau, U, beta, batch=4096):
         logw_all.append(logw)
         # the estimator of ``measure`` evaluated for the whole batch at once
         l = np.arange(L)
-        gb = np.empty((idx.shape[0], L + 1))
+        gb = np.empty((idx.shape[0], 2, L + 1))
         for k in range(L):
             r = l + k
             sgn = np.where(r < L, 1.0, -1.0)
             rr = np.mod(r, L)
-            gb[:, k] = ((Gs[0][:, rr, l] * sgn).sum(axis=1)
-                        + (Gs[1][:, rr, l] * sgn).sum(axis=1)) / (2.0 * L)
-        gb[:, L] = 1.0 - gb[:, 0]
+            gb[:, 0, k] = (Gs[0][:, rr, l] * sgn).sum(axis=1) / L
+            gb[:, 1, k] = (Gs[1][:, rr, l] * sgn).sum(axis=1) / L
+        gb[:, :, L] = 1.0 - gb[:, :, 0]
         du = np.diagonal(Gs[0], axis1=1, axis2=2)
         dd = np.diagonal(Gs[1], axis1=1, axis2=2)
         g_all.append(gb)
@@ -333,7 +371,8 @@ def brute_force(g_tau, U, beta, batch=4096):
     g_all = np.concatenate(g_all)
     d_all = np.concatenate(d_all)
     Z = w.sum()
-    return (w[:, None] * g_all).sum(axis=0) / Z, float((w * d_all).sum() / Z), float(w.min())
+    gs = np.tensordot(w, g_all, axes=(0, 0)) / Z
+    return (gs if spins else gs.mean(axis=0)), float((w * d_all).sum() / Z), float(w.min())
 
 
 # ---------------------------------------------------------- closed forms ----
@@ -374,4 +413,27 @@ def atomic_level_d(eps0, U, beta):
     """D = e^{-beta E2} / Z."""
     e1, e2 = eps0 - 0.5 * U, 2.0 * eps0
     z = 1.0 + 2.0 * np.exp(-beta * e1) + np.exp(-beta * e2)
+    return np.exp(-beta * e2) / z
+
+
+# ------------------------------------------- the atom in a magnetic field ----
+# Spin-dependent levels eps_up, eps_dn (a Zeeman splitting): the four states
+# have energies 0, E_up = eps_up - U/2, E_dn = eps_dn - U/2, E2 = eps_up + eps_dn;
+# again Trotter-exact for every L.
+
+def atomic_field_g(eps_up, eps_dn, U, beta, tau):
+    """(G_up(tau), G_dn(tau)): G_sigma = [e^{-tau E_sigma} + e^{-beta E_-sigma}
+    e^{-tau (E2 - E_-sigma)}] / Z, Z = 1 + e^{-beta E_up} + e^{-beta E_dn} + e^{-beta E2}."""
+    tau = np.asarray(tau, dtype=np.float64)
+    eu, ed, e2 = eps_up - 0.5 * U, eps_dn - 0.5 * U, eps_up + eps_dn
+    z = 1.0 + np.exp(-beta * eu) + np.exp(-beta * ed) + np.exp(-beta * e2)
+    gu = (np.exp(-tau * eu) + np.exp(-beta * ed) * np.exp(-tau * (e2 - ed))) / z
+    gd = (np.exp(-tau * ed) + np.exp(-beta * eu) * np.exp(-tau * (e2 - eu))) / z
+    return gu, gd
+
+
+def atomic_field_d(eps_up, eps_dn, U, beta):
+    """D = e^{-beta E2} / Z."""
+    eu, ed, e2 = eps_up - 0.5 * U, eps_dn - 0.5 * U, eps_up + eps_dn
+    z = 1.0 + np.exp(-beta * eu) + np.exp(-beta * ed) + np.exp(-beta * e2)
     return np.exp(-beta * e2) / z

@@ -11,6 +11,9 @@ Each check is tied to something other than the oracle itself:
   * Particle-hole symmetry at half filling: G_dn = 1 - G_up^T per field.
   * Monte Carlo vs exact enumeration within statistical error (L <= 12).
   * Delayed updates reproduce the rank-1 sequence.
+  * Spin-dependent baths (an atom in a Zeeman field): enumeration equals the
+    closed form per spin; U = 0 returns each spin's own bath; one bath given
+    twice reproduces the single-bath chain.
 """
 import numpy as np
 import pytest
@@ -221,3 +224,45 @@ def test_brute_force_atomic_level_away_from_half_filling(eps0, L):
     assert wmin > 0
     assert np.abs(g - exact).max() < 1e-11
     assert abs(d - H.atomic_level_d(eps0, U, beta)) < 1e-12
+
+
+def test_atomic_field_reduces_to_atomic_level_and_swaps_spins():
+    beta, U = 4.0, 3.0
+    tau = np.linspace(0.0, beta, 9)
+    gu, gd = H.atomic_field_g(-0.4, -0.4, U, beta, tau)
+    assert np.abs(gu - H.atomic_level_g(-0.4, U, beta, tau)).max() < 1e-14
+    assert np.abs(gd - gu).max() == 0.0
+    assert abs(H.atomic_field_d(-0.4, -0.4, U, beta) - H.atomic_level_d(-0.4, U, beta)) < 1e-15
+    a, b = H.atomic_field_g(0.3, -0.5, U, beta, tau)
+    c, d = H.atomic_field_g(-0.5, 0.3, U, beta, tau)
+    assert np.abs(a - d).max() < 1e-15 and np.abs(b - c).max() < 1e-15
+
+
+@pytest.mark.parametrize("eu,ed,L", [(-0.7, 0.3, 8), (0.5, -0.2, 10)])
+def test_brute_force_spin_dependent_baths_match_closed_form(eu, ed, L):
+    beta, U = 4.0, 4.0
+    tau = np.arange(L) * beta / L
+    baths = (H.atomic_level_bath(eu, beta, tau), H.atomic_level_bath(ed, beta, tau))
+    gs, d, wmin = H.brute_force(baths, U, beta, spins=True)
+    ex = np.array(H.atomic_field_g(eu, ed, U, beta, np.arange(L + 1) * beta / L))
+    ex[:, L] = 1.0 - ex[:, 0]
+    assert wmin > 0
+    assert np.abs(gs - ex).max() < 1e-11
+    assert abs(d - H.atomic_field_d(eu, ed, U, beta)) < 1e-12
+
+
+def test_spin_dependent_chain_u0_and_equal_baths():
+    beta, L = 5.0, 10
+    tau = np.arange(L) * beta / L
+    bu, bd = H.atomic_level_bath(-0.6, beta, tau), B.bath_to_tau(B.semicircle_iw(beta, 1.0, 8000), 1.0, beta, L)
+    r = H.run_chain((bu, bd), 0.0, beta, 3, warmup=1, sweeps=4)
+    assert np.abs(r["Gu"] - H.g0_matrix(bu)).max() < 1e-14
+    assert np.abs(r["Gd"] - H.g0_matrix(bd)).max() < 1e-14
+    m = r["bins_gs"][0] / r["bins_n"][0]
+    assert np.abs(m[0, :L] - bu).max() < 1e-14 and np.abs(m[1, :L] - bd).max() < 1e-14
+    # one bath given for both spins: the same chain as the single-bath call
+    r1 = H.run_chain(bd, 4.0, beta, 5, warmup=1, sweeps=6)
+    r2 = H.run_chain((bd, bd), 4.0, beta, 5, warmup=1, sweeps=6)
+    assert r1["flips"] == r2["flips"]
+    assert np.array_equal(r1["bins_g"], r2["bins_g"])
+    assert np.abs(r2["bins_gs"][0].mean(axis=0) - r2["bins_g"][0]).max() < 1e-13
