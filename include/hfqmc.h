@@ -184,6 +184,19 @@ int hfqmc_solve_dev(hfqmc_ctx *ctx, const double *g0_tau, int32_t L, double U, d
                     double dtau, uint64_t seed, const hfqmc_opts *opts,
                     double *g_tau, double *g_err, double *docc, hfqmc_stats *stats);
 
+/* hfqmc_solve with spin-dependent baths (a magnetic field, magnetic phases;
+ * the paper's closing remarks on the method's generality): spin up sees the
+ * bath g0_up[L], spin down g0_dn[L], both G0_sigma(k dtau) in the positive
+ * convention; M_sigma = 1 + (1 - G0_sigma)(e^{V_sigma} - 1).  Outputs are
+ * spin-resolved: g_tau[2 (L+1)] = G_up(tau_k), k = 0..L, then G_dn(tau_k)
+ * (G_sigma(beta-) = n_sigma); g_err likewise or NULL; docc as hfqmc_solve.
+ * opts.chain_g, when given, holds [n_chains][n_bins][2][L+1].  All update
+ * modes; EINVAL with HFQMC_FLAG_PH_SYMMETRIC or HFQMC_FLAG_G_FP32, for a null
+ * g0_dn and as hfqmc_solve otherwise.  Host buffers only. */
+int hfqmc_solve_spin(hfqmc_ctx *ctx, const double *g0_up, const double *g0_dn, int32_t L,
+                     double U, double beta, double dtau, uint64_t seed, const hfqmc_opts *opts,
+                     double *g_tau, double *g_err, double *docc, hfqmc_stats *stats);
+
 /* Batched solve of several grids in ONE persistent launch (the data-parallel
  * core of a multigrid step): grid i has L[i] slices, bath g0_tau (concatenated,
  * sum L[i] values), dtau_i = beta / L[i], Philox grid key i.  opts.n_chains

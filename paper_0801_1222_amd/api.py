@@ -84,9 +84,11 @@ def _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drif
 class _Hooks:
     """Host buffers of the optional test hooks, kept alive for the call."""
 
-    def __init__(self, o, n_grids, n_chains, Ls, n_bins, flip_cap, replay, want_chain, want_green):
+    def __init__(self, o, n_grids, n_chains, Ls, n_bins, flip_cap, replay, want_chain, want_green,
+                 spins=1):
         self.keep = []
         self.n_grids, self.n_chains, self.Ls = n_grids, n_chains, list(Ls)
+        self.spins = spins   # 2: spin-resolved estimators, [..][2][L+1] per sample
         nb = n_bins if n_bins > 0 else (20 if n_chains == 1 else 1)
         self.n_bins = nb
         self.flip_log = self.flip_count = None
@@ -111,7 +113,7 @@ class _Hooks:
             o.replay_cap = cap
         self.chain_g = self.chain_d = self.chain_n = self.chain_drift = None
         if want_chain:
-            tot = sum(L + 1 for L in Ls)
+            tot = sum(spins * (L + 1) for L in Ls)
             self.chain_g = np.zeros(n_chains * nb * tot)
             self.chain_d = np.zeros((n_grids, n_chains, nb))
             self.chain_n = np.zeros((n_grids, n_chains, nb), dtype=np.int64)
@@ -136,8 +138,10 @@ class _Hooks:
             per = []
             off = 0
             for L in self.Ls:
-                n = self.n_chains * self.n_bins * (L + 1)
-                per.append(self.chain_g[off:off + n].reshape(self.n_chains, self.n_bins, L + 1).copy())
+                n = self.n_chains * self.n_bins * self.spins * (L + 1)
+                shape = ((self.n_chains, self.n_bins, L + 1) if self.spins == 1
+                         else (self.n_chains, self.n_bins, 2, L + 1))
+                per.append(self.chain_g[off:off + n].reshape(shape).copy())
                 off += n
             out["chain_g"] = per
             out["chain_d"] = self.chain_d.copy()
@@ -172,6 +176,39 @@ def hfqmc_solve(ctx, g0_tau, U, beta, dtau, seed, n_chains=1, warmup=0, sweeps=1
         if k in r:
             r[k] = r[k][0]
     for k in ("flip_count", "chain_d", "chain_n", "chain_drift"):
+        if k in r:
+            r[k] = r[k][0]
+    out.update(r)
+    return out
+
+
+def hfqmc_solve_spin(ctx, g0_up, g0_dn, U, beta, dtau, seed, n_chains=1, warmup=0, sweeps=1,
+                     mode="rank1", recompute_every=0, delay_k=0, n_bins=0, drift_limit=0.0,
+                     flip_cap=0, replay=None, want_chain=False, want_green=False, eager=False,
+                     heat_bath=False, direct=False):
+    """Fixed-dtau solve with spin-dependent baths; returns dict(g_up, g_dn,
+    err_up, err_dn, D, D_err, stats, [hooks]); chain_g is [n_chains][n_bins][2][L+1]."""
+    gu = np.ascontiguousarray(g0_up, dtype=np.float64)
+    gd = np.ascontiguousarray(g0_dn, dtype=np.float64)
+    if gu.shape != gd.shape:
+        raise ValueError("g0_up and g0_dn differ in length")
+    L = gu.shape[0]
+    o = _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drift_limit,
+              _flags(eager, heat_bath, direct))
+    hk = _Hooks(o, 1, n_chains, [L], n_bins, flip_cap,
+                [replay] if replay is not None else None, want_chain, want_green, spins=2)
+    g = np.zeros(2 * (L + 1))
+    ge = np.zeros(2 * (L + 1))
+    d = np.zeros(2)
+    st = N.Stats()
+    rc = N.lib.hfqmc_solve_spin(ctx.handle, N.ptr(gu), N.ptr(gd), L, float(U), float(beta),
+                                float(dtau), int(seed), C.byref(o), N.ptr(g), N.ptr(ge), N.ptr(d),
+                                C.byref(st))
+    N.check(rc, "hfqmc_solve_spin")
+    out = dict(g_up=g[:L + 1].copy(), g_dn=g[L + 1:].copy(), err_up=ge[:L + 1].copy(),
+               err_dn=ge[L + 1:].copy(), D=d[0], D_err=d[1], stats=st.as_dict())
+    r = hk.results()
+    for k in ("flips", "chain_g", "flip_count", "chain_d", "chain_n", "chain_drift"):
         if k in r:
             r[k] = r[k][0]
     out.update(r)

@@ -224,6 +224,7 @@ struct Call {
   bool dev_io = false;
   int nb_max = 0;
   bool trial = false;
+  const double* g0_dn = nullptr;   // spin-down baths (host, like g0_tau): spin-dependent solve
 };
 
 int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double* g0_tau, double U,
@@ -338,6 +339,14 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
   if (!call.dev_io)
     for (long long q = 0; q < Lsum; ++q)
       if (!std::isfinite(g0_tau[q])) return fail(HFQMC_EINVAL, "g0_tau[%lld] not finite", q);
+  const bool spin = call.g0_dn != nullptr;
+  if (spin) {
+    if (call.dev_io) return fail(HFQMC_EINVAL, "spin-dependent baths: host buffers only");
+    if (opts->flags & (HFQMC_FLAG_PH_SYMMETRIC | HFQMC_FLAG_G_FP32))
+      return fail(HFQMC_EINVAL, "spin-dependent baths exclude HFQMC_FLAG_PH_SYMMETRIC and HFQMC_FLAG_G_FP32");
+    for (long long q = 0; q < Lsum; ++q)
+      if (!std::isfinite(call.g0_dn[q])) return fail(HFQMC_EINVAL, "g0_dn[%lld] not finite", q);
+  }
 
   HIPCHK(hipSetDevice(c->device));
   hipStream_t st = c->stream;
@@ -390,16 +399,20 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
   int* d_queue = nullptr;
   GridDev* d_grids = nullptr;
   double* d_gtau = nullptr;
+  double* d_gtau_dn = nullptr;
   auto layout = [&](Bump& b) {
     d_grids = b.take<GridDev>(n_grids);
     d_units = b.take<int>((size_t)n_grids * nch);
     d_queue = b.take<int>(64);
     d_gtau = b.take<double>(Lsum);
+    d_gtau_dn = spin ? b.take<double>(Lsum) : nullptr;
     for (int i = 0; i < n_grids; ++i) {
       const int L = Ls[i];
+      const int ng = spin ? 2 * (L + 1) : L + 1;
       GridDev& g = gd[i];
       g.G0 = b.take<double>((size_t)L * L);
-      g.acc_g = b.take<double>((size_t)nch * nbin * (L + 1));
+      g.G0d = spin ? b.take<double>((size_t)L * L) : g.G0;
+      g.acc_g = b.take<double>((size_t)nch * nbin * ng);
       g.acc_d = b.take<double>((size_t)nch * nbin);
       g.acc_n = b.take<long long>((size_t)nch * nbin);
       g.cstats = b.take<long long>((size_t)nch * NSTAT);
@@ -408,13 +421,16 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
       g.replay = opts->replay_log ? b.take<long long>((size_t)nch * opts->replay_cap) : nullptr;
       g.replay_n = opts->replay_log ? b.take<long long>(nch) : nullptr;
       g.g_final = opts->final_green ? b.take<double>((size_t)nch * 2 * L * L) : nullptr;
-      g.g_out = b.take<double>(L + 1);
-      g.g_err = b.take<double>(L + 1);
+      g.g_out = b.take<double>(ng);
+      g.g_err = b.take<double>(ng);
       g.d_out = b.take<double>(2);
       for (int q = 0; q < 2; ++q) {
         g.refQ[q] = direct ? nullptr : b.take<double>((size_t)L * L);
         g.refH[q] = direct ? nullptr : b.take<double>((size_t)L * L);
+        g.refQd[q] = (spin && !direct) ? b.take<double>((size_t)L * L) : g.refQ[q];
+        g.refHd[q] = (spin && !direct) ? b.take<double>((size_t)L * L) : g.refH[q];
       }
+      g.spin = spin ? 1 : 0;
       g.ref_sing = direct ? nullptr : b.take<int>(4);
     }
   };
@@ -455,6 +471,8 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
     HIPCHK(launch_copy(g0_tau, d_gtau, Lsum, st));
   else
     HIPCHK(hipMemcpyAsync(d_gtau, g0_tau, sizeof(double) * Lsum, hipMemcpyHostToDevice, st));
+  if (spin)
+    HIPCHK(hipMemcpyAsync(d_gtau_dn, call.g0_dn, sizeof(double) * Lsum, hipMemcpyHostToDevice, st));
   if (opts->flags & HFQMC_FLAG_PH_SYMMETRIC) {
     // G_dn = 1 - G_up^T needs G0 = 1 - G0^T: G0(0+) = 1/2 and G0(tau) = G0(beta - tau)
     std::vector<double> gh_tau;
@@ -529,6 +547,7 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
   p.heat_bath = (opts->flags & HFQMC_FLAG_HEAT_BATH) ? 1 : 0;
   p.direct = direct;
   p.ph = (opts->flags & HFQMC_FLAG_PH_SYMMETRIC) ? 1 : 0;
+  p.spin = spin ? 1 : 0;
 
   // ---- the device launch sequence: bath matrices, zeroed accumulators and
   // counters (fill kernels), the persistent sweep kernel, the chain reduction
@@ -544,14 +563,20 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
       const int L = Ls[i];
       const GridDev& g = gd[i];
       if ((e = launch_build_g0(d_gtau + goff0[i], L, const_cast<double*>(g.G0), s)) != hipSuccess) break;
-      if ((e = launch_zero(g.acc_g, (long long)nch * nbin * (L + 1), s)) != hipSuccess) break;
+      if (spin &&
+          (e = launch_build_g0(d_gtau_dn + goff0[i], L, const_cast<double*>(g.G0d), s)) != hipSuccess)
+        break;
+      if ((e = launch_zero(g.acc_g, (long long)nch * nbin * (spin ? 2 * (L + 1) : L + 1), s)) !=
+          hipSuccess)
+        break;
       if ((e = launch_zero(g.acc_d, (long long)nch * nbin, s)) != hipSuccess) break;
       if ((e = launch_zero_i64(g.acc_n, (long long)nch * nbin, s)) != hipSuccess) break;
       if ((e = launch_zero_i64(g.cstats, (long long)nch * NSTAT, s)) != hipSuccess) break;
       e = launch_zero(g.cdrift, nch, s);
       if (e == hipSuccess && !direct) e = launch_zero_i32(g.ref_sing, 4, s);
     }
-    if (e == hipSuccess && !direct) e = launch_reference(p, ref_lds, ref_scratch, s);
+    if (e == hipSuccess && !direct) e = launch_reference(p, ref_lds, ref_scratch, 0, s);
+    if (e == hipSuccess && !direct && spin) e = launch_reference(p, ref_lds, ref_scratch, 1, s);
     if (e == hipSuccess) e = launch_zero_i32(d_queue, 64, s);
     return e;
   };
@@ -643,9 +668,10 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
   std::memset(&tot, 0, sizeof tot);
   for (int i = 0; i < n_grids; ++i) {
     const int L = Ls[i];
+    const int ng = spin ? 2 * (L + 1) : L + 1;
     const GridDev& g = gd[i];
-    HIPCHK(out_copy(g_tau + goff, g.g_out, L + 1));
-    if (g_err) HIPCHK(out_copy(g_err + goff, g.g_err, L + 1));
+    HIPCHK(out_copy(g_tau + goff, g.g_out, ng));
+    if (g_err) HIPCHK(out_copy(g_err + goff, g.g_err, ng));
     if (docc) HIPCHK(out_copy(docc + 2 * i, g.d_out, 2));
     if (call.dev_io) {
       gcheck.resize(L + 1);
@@ -662,7 +688,7 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
     }
     if (opts->chain_g)
       HIPCHK(hipMemcpyAsync(opts->chain_g + (size_t)nch * nbin * (goff), g.acc_g,
-                            sizeof(double) * nch * nbin * (L + 1), hipMemcpyDeviceToHost, st));
+                            sizeof(double) * nch * nbin * ng, hipMemcpyDeviceToHost, st));
     if (opts->chain_d)
       HIPCHK(hipMemcpyAsync(opts->chain_d + cb * nbin, g.acc_d, sizeof(double) * nch * nbin, hipMemcpyDeviceToHost, st));
     if (opts->chain_n)
@@ -735,9 +761,9 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
     tot.chain_s_fold += gs.chain_s_fold;
     max_drift = std::max(max_drift, gdrift);
     const double* gv = call.dev_io ? gcheck.data() : g_tau + goff;
-    for (int k = 0; k <= L; ++k)
+    for (int k = 0; k < (call.dev_io ? L + 1 : ng); ++k)
       if (!std::isfinite(gv[k])) numeric_bad = true;
-    goff += L + 1;
+    goff += ng;
   }
   float ms = 0.f, ms_k = 0.f;
   HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
@@ -785,6 +811,19 @@ extern "C" int hfqmc_solve(hfqmc_ctx* c, const double* g0_tau, int32_t L, double
   if (std::fabs(beta / dtau - L) > 1e-9 * L) return fail(HFQMC_EINVAL, "beta/dtau=%.12g != L=%d", beta / dtau, L);
   const int32_t Ls[1] = {L};
   return solve_grids_impl(c, 1, Ls, g0_tau, U, beta, seed, opts, g_tau, g_err, docc, stats, Call());
+}
+
+extern "C" int hfqmc_solve_spin(hfqmc_ctx* c, const double* g0_up, const double* g0_dn, int32_t L,
+                                double U, double beta, double dtau, uint64_t seed,
+                                const hfqmc_opts* opts, double* g_tau, double* g_err, double* docc,
+                                hfqmc_stats* stats) {
+  if (!g0_dn) return fail(HFQMC_EINVAL, "hfqmc_solve_spin: g0_dn is null");
+  if (!(dtau > 0.0) || !(beta > 0.0)) return fail(HFQMC_EINVAL, "dtau=%g beta=%g", dtau, beta);
+  if (std::fabs(beta / dtau - L) > 1e-9 * L) return fail(HFQMC_EINVAL, "beta/dtau=%.12g != L=%d", beta / dtau, L);
+  const int32_t Ls[1] = {L};
+  Call call;
+  call.g0_dn = g0_dn;
+  return solve_grids_impl(c, 1, Ls, g0_up, U, beta, seed, opts, g_tau, g_err, docc, stats, call);
 }
 
 extern "C" int hfqmc_solve_dev(hfqmc_ctx* c, const double* g0_tau, int32_t L, double U, double beta,

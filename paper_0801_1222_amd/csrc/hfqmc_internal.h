@@ -62,6 +62,11 @@ struct GridDev {
   double* g_out;          // [L+1] chain-reduced G(tau)
   double* g_err;          // [L+1]
   double* d_out;          // [2] D and its error
+  const double* G0d;      // spin-down bath matrix (G0 itself unless the baths are spin-dependent)
+  const double* refQd[2]; // spin-down references (refQ, refH themselves unless spin-dependent)
+  const double* refHd[2];
+  int spin;               // 1: spin-dependent baths; accumulators and outputs per spin,
+                          //    [..][2][L+1] (up, down) in place of [..][L+1]
 };
 
 struct SweepParams {
@@ -86,6 +91,7 @@ struct SweepParams {
   int heat_bath;          // 1: accept iff u < R/(1+R); 0: Metropolis, u < R
   int direct;             // 1: recompute with the full L x L system (no reference reduction)
   int ph;                 // 1: particle-hole symmetric bath, only G_up kept (G_dn = 1 - G_up^T)
+  int spin;               // 1: spin-dependent baths (GridDev::spin)
 };
 
 constexpr int kThreads = 512;   // threads per persistent workgroup (8 wave64)
@@ -115,7 +121,7 @@ hipError_t launch_sweeps(const SweepParams& p, int n_wg, int lds, hipStream_t s)
 // workgroups per grid, direct LU with the grid's panel width ref_nb,
 // workspace slots 0..4 n_grids-1.
 hipError_t prepare_reference(int lds);
-hipError_t launch_reference(const SweepParams& p, int lds, int scratch, hipStream_t s);
+hipError_t launch_reference(const SweepParams& p, int lds, int scratch, int dn, hipStream_t s);
 hipError_t launch_reduce(const GridDev* grids, int n_grids, int n_bins, hipStream_t s);
 
 // Achievable-peak probes (hfqmc_peaks.hip).  Copy / read: n16 16-byte

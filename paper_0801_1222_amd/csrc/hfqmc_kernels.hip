@@ -201,6 +201,9 @@ struct Chain {
   const double* refH[2];
   int lu_nb;       // LU panel width of this grid
   bool reduced;    // recompute against the uniform-field references
+  const double* G0d;      // spin-down bath and references (spin-dependent baths)
+  const double* refQd[2];
+  const double* refHd[2];
 };
 
 // Control state every thread keeps (uniform); the statistics live in LDS.
@@ -881,7 +884,7 @@ __device__ __forceinline__ double reduced_product_slabs(
 //
 // rhs_k (direct form only): right-hand side K = 1 - G0 instead of G0 (the
 // reference matrices Q_r).
-template <typename GT>
+template <typename GT, bool SPIN = false>
 __device__ __forceinline__ double dyson_solve(const Chain& ch, int sigma, GT* Gs_,
                                               int NB, bool reduced, bool rhs_k) {
   const int L = ch.L;
@@ -890,7 +893,8 @@ __device__ __forceinline__ double dyson_solve(const Chain& ch, int sigma, GT* Gs
   const double ep = ch.ep, em = ch.em;
   const int8_t* s = ch.s;
   typename GlobalOf<GT>::type* __restrict__ Gs = (typename GlobalOf<GT>::type*)Gs_;
-  gcdouble* __restrict__ G0 = (gcdouble*)ch.G0;
+  // (SPIN: spin-dependent baths, spin down has a bath and references of its own)
+  gcdouble* __restrict__ G0 = (gcdouble*)((SPIN && sigma < 0) ? ch.G0d : ch.G0);
   double* __restrict__ A = ch.A;
   int* sr = ch.sr;                                       // reduced form only
   char* const lu_scr = ch.scratch + (reduced ? ((4 * L + 15) & ~15) : 0);
@@ -912,8 +916,8 @@ __device__ __forceinline__ double dyson_solve(const Chain& ch, int sigma, GT* Gs
     (void)block_exclusive_scan(na, reinterpret_cast<int*>(ch.red), &n_a);
     const int ref = (n_a >= L - n_a) ? 0 : 1;          // 0: reference d_a, 1: d_b
     c = ref == 0 ? (em - ep) : (ep - em);
-    Qr = (gcdouble*)ch.refQ[ref];
-    Hr = (gcdouble*)ch.refH[ref];
+    Qr = (gcdouble*)((SPIN && sigma < 0) ? ch.refQd[ref] : ch.refQ[ref]);
+    Hr = (gcdouble*)((SPIN && sigma < 0) ? ch.refHd[ref] : ch.refH[ref]);
     const int want = ref == 0 ? -1 : 1;                // sign of sigma s_l on S
     int ms = 0;
     for (int l = l0; l < l1; ++l) ms += (sigma * s[l] == want) ? 1 : 0;
@@ -1321,7 +1325,7 @@ __device__ __forceinline__ double dyson_solve(const Chain& ch, int sigma, GT* Gs
 // spin-down sum over i becomes, with j = (i - k) mod L,
 //   sum_i sgn G_dn(i, j) = L delta_k0 - sum_j sgn' G_up(j, (j + k) mod L),
 // sgn' = -1 where j + k wraps: again one contiguous stretch of a row per step.
-template <typename GT>
+template <typename GT, bool SPIN = false>
 __device__ __forceinline__ void measure(const Chain& ch, int bin, bool ph) {
   const int L = ch.L;
   double* accg = ch.accg;
@@ -1365,10 +1369,21 @@ __device__ __forceinline__ void measure(const Chain& ch, int bin, bool ph) {
       }
       dn = (k == 0 ? (double)L : 0.0) - tr;
     }
-    const double val = (up + dn) / (2.0 * L);
-    const long long base = (long long)bin * (L + 1);
-    accg[base + k] += val;
-    if (k == 0) accg[base + L] += 1.0 - val;
+    if constexpr (SPIN) {
+      // spin-resolved: [bin][up, down][L+1], G_sigma(beta-) = 1 - G_sigma(0+)
+      const long long base = (long long)bin * 2 * (L + 1);
+      accg[base + k] += up / L;
+      accg[base + (L + 1) + k] += dn / L;
+      if (k == 0) {
+        accg[base + L] += 1.0 - up / L;
+        accg[base + (L + 1) + L] += 1.0 - dn / L;
+      }
+    } else {
+      const double val = (up + dn) / (2.0 * L);
+      const long long base = (long long)bin * (L + 1);
+      accg[base + k] += val;
+      if (k == 0) accg[base + L] += 1.0 - val;
+    }
   }
   double dsum = 0.0;
   for (int l = threadIdx.x; l < L; l += kThreads) {
@@ -1443,7 +1458,7 @@ __device__ __forceinline__ void log_flip(const ChainIO& io, long long* st, long 
 
 // Dyson recompute of both spins (the kernel's only call site of the LU, so it
 // is inlined once).  The initial recompute of a chain is not counted as one.
-template <typename GT>
+template <typename GT, bool SPIN = false>
 __device__ __forceinline__ void recompute_both(const SweepParams& p, const Chain& ch, Counters& k,
                                                bool counted) {
   const long long t0 = wall_clock64();
@@ -1451,8 +1466,8 @@ __device__ __forceinline__ void recompute_both(const SweepParams& p, const Chain
   const int nsp = p.ph ? 1 : 2;
 #pragma unroll 1
   for (int sp = 0; sp < nsp; ++sp)
-    d = fmax(d, dyson_solve(ch, sp ? -1 : +1, reinterpret_cast<GT*>(sp ? ch.Gd : ch.Gu), ch.lu_nb,
-                            ch.reduced, false));
+    d = fmax(d, dyson_solve<GT, SPIN>(ch, sp ? -1 : +1, reinterpret_cast<GT*>(sp ? ch.Gd : ch.Gu),
+                                      ch.lu_nb, ch.reduced, false));
   if (counted && threadIdx.x == 0) {
     *ch.drift = fmax(*ch.drift, d);
     ch.st[ST_RECOMPUTES] += 1;
@@ -2285,10 +2300,13 @@ __device__ __forceinline__ void setup_chain(Chain& ch, const SweepParams& p, con
   ch.scratch_bytes = scratch_bytes;
 }
 
-template <bool G32>
+// VAR 0: every mode, chosen at run time; 1: mixed with G stored in FP32;
+// 2: spin-dependent baths (every mode, FP64-stored G, spin-resolved estimators)
+template <int VAR>
 __device__ __forceinline__ void run_chain(const SweepParams& p, const GridDev* gd, int chain, double* ws,
                           char* lds) {
-  typedef typename std::conditional<G32, float, double>::type GT;   // stored G
+  typedef typename std::conditional<VAR == 1, float, double>::type GT;   // stored G
+  constexpr bool SPIN = VAR == 2;
   Chain ch;
   setup_chain(ch, p, gd, chain, ws, lds, gd->lu_nb, p.lds_scratch_bytes);
   const int L = ch.L;
@@ -2296,7 +2314,15 @@ __device__ __forceinline__ void run_chain(const SweepParams& p, const GridDev* g
 
   // this chain's accumulators
   const int nb = p.n_bins;
-  ch.accg = gd->acc_g + (long long)chain * nb * (L + 1);
+  const int ng = SPIN ? 2 * (L + 1) : L + 1;   // estimator entries per sample
+  ch.accg = gd->acc_g + (long long)chain * nb * ng;
+  if constexpr (SPIN) {
+    ch.G0d = gd->G0d;
+    ch.refQd[0] = gd->refQd[0];
+    ch.refQd[1] = gd->refQd[1];
+    ch.refHd[0] = gd->refHd[0];
+    ch.refHd[1] = gd->refHd[1];
+  }
   ch.accd = gd->acc_d + (long long)chain * nb;
   ch.accn = gd->acc_n + (long long)chain * nb;
 
@@ -2329,7 +2355,7 @@ __device__ __forceinline__ void run_chain(const SweepParams& p, const GridDev* g
   bool need_rec = true, first = true;
   for (;;) {
     if (need_rec) {
-      recompute_both<GT>(p, ch, k, !first);
+      recompute_both<GT, SPIN>(p, ch, k, !first);
       first = false;
       need_rec = false;
     }
@@ -2338,7 +2364,7 @@ __device__ __forceinline__ void run_chain(const SweepParams& p, const GridDev* g
         const long long t1 = wall_clock64();
         const long long msw = sw - p.warmup;
         const int bin = (int)((msw * nb) / p.sweeps);
-        measure<GT>(ch, bin, p.ph != 0);
+        measure<GT, SPIN>(ch, bin, p.ph != 0);
         stat_add(ch.st, ST_T_MEAS, wall_clock64() - t1);
       }
       __syncthreads();
@@ -2349,7 +2375,7 @@ __device__ __forceinline__ void run_chain(const SweepParams& p, const GridDev* g
     const long long t0 = wall_clock64();
     const long long f0 = threadIdx.x == 0 ? ch.st[ST_T_FLUSH] : 0;
     int nl;
-    if constexpr (G32) {
+    if constexpr (VAR == 1) {
       nl = sweep_window<true, float>(p, ch, sw, k, io, l);
     } else {
       if (p.mode == MODE_RANK1)
@@ -2389,9 +2415,9 @@ __device__ __forceinline__ void run_chain(const SweepParams& p, const GridDev* g
 
 // ------------------------------------------------- persistent kernel ----
 
-// G32: the mixed update with G stored in FP32 (a kernel of its own; the other
-// modes share one kernel and choose their sweep at run time)
-template <bool G32>
+// One kernel per variant of run_chain (VAR above): the default kernel carries
+// no code of the other two
+template <int VAR>
 __global__ void __launch_bounds__(kThreads) k_sweeps(SweepParams p) {
   extern __shared__ __align__(16) char lds[];
   __shared__ int s_unit;
@@ -2404,7 +2430,7 @@ __global__ void __launch_bounds__(kThreads) k_sweeps(SweepParams p) {
     if (unit >= p.n_units) break;
     const int code = p.units[unit];
     const int gi = code >> 20, c = code & 0xFFFFF;
-    run_chain<G32>(p, p.grids + gi, c, ws, lds);
+    run_chain<VAR>(p, p.grids + gi, c, ws, lds);
   }
 }
 
@@ -2412,18 +2438,22 @@ __global__ void __launch_bounds__(kThreads) k_sweeps(SweepParams p) {
 // M_r X = G0 (kind 0, X = H_r) or M_r X = 1 - G0 (kind 1, X = Q_r) with the
 // direct LU, M_r = 1 + d_r (1 - G0), d_0 = e^{lambda} - 1, d_1 = e^{-lambda} - 1
 // (the field s = +1 everywhere, spin up for r = 0 and down for r = 1).
-__global__ void __launch_bounds__(kThreads) k_reference(SweepParams p, int scratch_bytes) {
+// dn: the spin-down references of grids with spin-dependent baths (from G0d).
+__global__ void __launch_bounds__(kThreads) k_reference(SweepParams p, int scratch_bytes, int dn) {
   extern __shared__ __align__(16) char lds[];
   const int gi = blockIdx.x >> 2, r = (blockIdx.x >> 1) & 1, kind = blockIdx.x & 1;
   const GridDev* gd = p.grids + gi;
   if (gd->direct) return;   // grids recomputed in full size need no references
+  if (dn && !gd->spin) return;
   const int nb = gd->ref_nb;
   Chain ch;
   setup_chain(ch, p, gd, 0, p.work + (long long)blockIdx.x * p.work_stride, lds, nb, scratch_bytes);
+  if (dn) ch.G0 = gd->G0d;
   for (int l = threadIdx.x; l < ch.L; l += kThreads) ch.s[l] = 1;
   if (threadIdx.x < NSTAT) ch.st[threadIdx.x] = 0;
   __syncthreads();
-  double* out = const_cast<double*>(kind ? gd->refQ[r] : gd->refH[r]);
+  double* out = const_cast<double*>(dn ? (kind ? gd->refQd[r] : gd->refHd[r])
+                                       : (kind ? gd->refQ[r] : gd->refH[r]));
   (void)dyson_solve(ch, r == 0 ? 1 : -1, out, nb, false, kind == 1);
   if (threadIdx.x == 0 && ch.st[ST_SINGULAR]) *gd->ref_sing = 1;
 }
@@ -2434,15 +2464,16 @@ __global__ void __launch_bounds__(kThreads) k_reference(SweepParams p, int scrat
 __global__ void k_reduce(const GridDev* grids, int n_bins) {
   const GridDev& g = grids[blockIdx.x];
   const int L = g.L;
+  const int ng = g.spin ? 2 * (L + 1) : L + 1;   // G entries per sample
   const int ns_tot = g.n_chains * n_bins;
-  for (int k = threadIdx.x; k <= L + 1; k += blockDim.x) {
-    // k == L + 1 handles D
+  for (int k = threadIdx.x; k <= ng; k += blockDim.x) {
+    // k == ng handles D
     double sum = 0.0;
     int ns = 0;
     for (int q = 0; q < ns_tot; ++q) {
       const long long n = g.acc_n[q];
       if (n <= 0) continue;
-      const double v = (k <= L ? g.acc_g[(long long)q * (L + 1) + k] : g.acc_d[q]) / (double)n;
+      const double v = (k < ng ? g.acc_g[(long long)q * ng + k] : g.acc_d[q]) / (double)n;
       sum += v;
       ++ns;
     }
@@ -2451,11 +2482,11 @@ __global__ void k_reduce(const GridDev* grids, int n_bins) {
     for (int q = 0; q < ns_tot; ++q) {
       const long long n = g.acc_n[q];
       if (n <= 0) continue;
-      const double v = (k <= L ? g.acc_g[(long long)q * (L + 1) + k] : g.acc_d[q]) / (double)n;
+      const double v = (k < ng ? g.acc_g[(long long)q * ng + k] : g.acc_d[q]) / (double)n;
       var += (v - mean) * (v - mean);
     }
     const double err = ns > 1 ? sqrt(var / (ns - 1)) / sqrt((double)ns) : 0.0;
-    if (k <= L) {
+    if (k < ng) {
       g.g_out[k] = mean;
       g.g_err[k] = err;
     } else {
@@ -2575,18 +2606,22 @@ hipError_t launch_zero_i32(int* p, long long n, hipStream_t s) {
 
 hipError_t prepare_sweeps(int lds) {
   if (lds <= 64 * 1024) return hipSuccess;
-  const hipError_t e = hipFuncSetAttribute((const void*)k_sweeps<false>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_sweeps<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             lds);
+  hipError_t e = hipFuncSetAttribute((const void*)k_sweeps<0>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_sweeps<1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_sweeps<2>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  return e;
 }
 
 hipError_t launch_sweeps(const SweepParams& p, int n_wg, int lds, hipStream_t s) {
   if (p.mode == MODE_MIXED_G32)
-    hipLaunchKernelGGL(k_sweeps<true>, dim3(n_wg), dim3(kThreads), lds, s, p);
+    hipLaunchKernelGGL(k_sweeps<1>, dim3(n_wg), dim3(kThreads), lds, s, p);
+  else if (p.spin)
+    hipLaunchKernelGGL(k_sweeps<2>, dim3(n_wg), dim3(kThreads), lds, s, p);
   else
-    hipLaunchKernelGGL(k_sweeps<false>, dim3(n_wg), dim3(kThreads), lds, s, p);
+    hipLaunchKernelGGL(k_sweeps<0>, dim3(n_wg), dim3(kThreads), lds, s, p);
   return hipGetLastError();
 }
 
@@ -2595,8 +2630,8 @@ hipError_t prepare_reference(int lds) {
   return hipFuncSetAttribute((const void*)k_reference, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
 }
 
-hipError_t launch_reference(const SweepParams& p, int lds, int scratch, hipStream_t s) {
-  hipLaunchKernelGGL(k_reference, dim3(4 * p.n_grids), dim3(kThreads), lds, s, p, scratch);
+hipError_t launch_reference(const SweepParams& p, int lds, int scratch, int dn, hipStream_t s) {
+  hipLaunchKernelGGL(k_reference, dim3(4 * p.n_grids), dim3(kThreads), lds, s, p, scratch, dn);
   return hipGetLastError();
 }
 
