@@ -304,6 +304,29 @@ def reduce_chains(results):
     return g, g_err, float(D), float(d_err)
 
 
+def reduce_chains_spin(results):
+    """``reduce_chains`` for the spin-resolved estimator: (G_sigma [2, L+1], its
+    error, D, D error) over all (chain, bin) sample means."""
+    g_samples, d_samples = [], []
+    for r in results:
+        for b in range(r["bins_n"].shape[0]):
+            n = r["bins_n"][b]
+            if n > 0:
+                g_samples.append(r["bins_gs"][b] / n)
+                d_samples.append(r["bins_d"][b] / n)
+    g_samples = np.array(g_samples)
+    d_samples = np.array(d_samples)
+    ns = g_samples.shape[0]
+    g = g_samples.mean(axis=0)
+    if ns > 1:
+        g_err = g_samples.std(axis=0, ddof=1) / np.sqrt(ns)
+        d_err = float(d_samples.std(ddof=1) / np.sqrt(ns))
+    else:
+        g_err = np.zeros_like(g)
+        d_err = 0.0
+    return g, g_err, float(d_samples.mean()), d_err
+
+
 def solve(g_tau, U, beta, seed, n_chains=1, warmup=0, sweeps=1, n_rec=100,
           n_bins=None, grid_id=0, **kw):
     """Fixed-dtau solve: n_chains independent chains (chain c uses seed + c)."""

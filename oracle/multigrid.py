@@ -112,6 +112,43 @@ def multigrid_solve(bath_iw, m3, U, beta, dtaus, seed, n_chains, warmup, sweeps,
                 e_interp=np.array(ei), Ls=Ls, dtaus=dts, D=float(d0[0]), D_err=float(d0e[0]))
 
 
+def multigrid_solve_spin(baths, m3, U, beta, dtaus, seed, n_chains, warmup, sweeps,
+                         n_rec=100, n_fine=200):
+    """Multigrid solve with spin-dependent baths (up, down): one spin-resolved
+    fixed-dtau solve per grid, then steps (i) and (ii) for each spin with that
+    spin's reference model.  g: [2, n_fine] (up, down); g_interp: [n_grids, 2, n_fine]."""
+    Ls, dts = grid_lengths(beta, dtaus)
+    tau_f = fine_grid(beta, n_fine)
+    n_bins = 20 if n_chains == 1 else 1
+    gref_f = [reference_tau(b, m3, U, beta, tau_f) for b in baths]
+    gi, ei, d_g, d_e = [], [], [], []
+    for i, L in enumerate(Ls):
+        g_taus = tuple(B.bath_to_tau(b, m3, beta, L) for b in baths)
+        res = [H.run_chain(g_taus, U, beta, seed, chain=c, grid_id=i, warmup=warmup,
+                           sweeps=sweeps, n_rec=n_rec, n_bins=n_bins) for c in range(n_chains)]
+        gs, gs_err, D, D_err = H.reduce_chains_spin(res)
+        tau_k = np.arange(L + 1) * (beta / L)
+        gf, ef = [], []
+        for sp in (0, 1):
+            gref_k = reference_tau(baths[sp], m3, U, beta, tau_k)
+            a, e = interpolate_grid(gs[sp], gs_err[sp], beta, gref_k, gref_f[sp], tau_f)
+            gf.append(a)
+            ef.append(e)
+        gi.append(gf)
+        ei.append(ef)
+        d_g.append([D])
+        d_e.append([D_err])
+    gi = np.array(gi)
+    ei = np.array(ei)
+    g = np.empty((2, n_fine))
+    g_err = np.empty((2, n_fine))
+    for sp in (0, 1):
+        g[sp], g_err[sp] = extrapolate(dts, gi[:, sp], ei[:, sp])
+    d0, d0e = extrapolate(dts, np.array(d_g), np.array(d_e))
+    return dict(g=g, g_err=g_err, tau=tau_f, g_interp=gi, e_interp=ei, Ls=Ls, dtaus=dts,
+                D=float(d0[0]), D_err=float(d0e[0]))
+
+
 def spline_fourier(tau, values, beta, n_iw):
     """Exact int_0^beta e^{i w_n tau} S(tau) d tau for the natural cubic spline S.
 
@@ -182,3 +219,32 @@ def dmft_loop(bath_iw, U, beta, t, dtaus, seed, n_iter, n_chains, warmup, sweeps
             new = 1j * new.imag
         bath = mixing * bath + (1.0 - mixing) * new
     return dict(bath=bath, g=r["g"], g_err=r["g_err"], tau=tau_f, history=np.array(hist))
+
+
+def dmft_loop_af(baths, U, beta, t, dtaus, seed, n_iter, n_chains, warmup, sweeps, n_rec=100,
+                 n_fine=200, mixing=0.0):
+    """The DMFT cycle for Neel order on the bipartite Bethe lattice: sublattice B
+    is sublattice A with the spins exchanged, so spin sigma's new bath closes
+    over the other spin's Green function, Bath_sigma = 1/(i w - t^2 G_-sigma(i w))
+    (the paper's closing remarks on magnetic phases; Fig. 1(c) otherwise).
+    history[it] = (max |g - g_prev| over both spins, max g_err, D, D_err,
+    m = n_up - n_dn), n_sigma = G_sigma(beta-) extrapolated."""
+    m3 = t * t
+    bu = np.asarray(baths[0], dtype=np.complex128).copy()
+    bd = np.asarray(baths[1], dtype=np.complex128).copy()
+    tau_f = fine_grid(beta, n_fine)
+    prev = np.array([reference_tau(bu, m3, 0.0, beta, tau_f), reference_tau(bd, m3, 0.0, beta, tau_f)])
+    hist = []
+    r = None
+    for it in range(n_iter):
+        r = multigrid_solve_spin((bu, bd), m3, U, beta, dtaus, seed + (it << 32), n_chains, warmup,
+                                 sweeps, n_rec=n_rec, n_fine=n_fine)
+        g = r["g"]
+        hist.append((float(np.abs(g - prev).max()), float(r["g_err"].max()), r["D"], r["D_err"],
+                     float(g[0, -1] - g[1, -1])))
+        prev = g
+        new_dn = dmft_bethe_step(g[0], tau_f, bu, m3, U, beta, t)
+        new_up = dmft_bethe_step(g[1], tau_f, bd, m3, U, beta, t)
+        bu = mixing * bu + (1.0 - mixing) * new_up
+        bd = mixing * bd + (1.0 - mixing) * new_dn
+    return dict(baths=(bu, bd), g=r["g"], g_err=r["g_err"], tau=tau_f, history=np.array(hist))

@@ -106,3 +106,25 @@ def test_dmft_loop_keeps_particle_hole_symmetry():
     assert np.all(out["bath"].imag < 0)
     # an interacting bath moved away from the semicircle
     assert np.abs(out["bath"] - bath).max() > 1e-3
+
+
+def test_af_cycle_u0_semicircle_is_fixed_point():
+    # U = 0: each spin's G is its bath, and the crossed closure returns the semicircle
+    beta, t = 10.0, 1.0
+    b = B.semicircle_iw(beta, t, 2000)
+    r = MG.dmft_loop_af((b, b), 0.0, beta, t, [0.5, 0.4, 0.25], 1, 2, n_chains=2, warmup=1,
+                        sweeps=3, n_fine=81)
+    assert np.abs(r["baths"][0] - b).max() < 1e-12 and np.abs(r["baths"][1] - b).max() < 1e-12
+    assert np.abs(r["history"][:, 4]).max() < 1e-13
+
+
+def test_spin_multigrid_with_equal_baths_averages_to_plain_multigrid():
+    # the same chains: per grid, the mean of the two spins' interpolated G equals
+    # the spin-averaged solve's (extrapolations differ only through their weights)
+    beta, U, t = 4.0, 3.0, 1.0
+    b = B.semicircle_iw(beta, t, 2000)
+    kw = dict(n_chains=2, warmup=2, sweeps=10, n_fine=41)
+    a = MG.multigrid_solve(b, t * t, U, beta, [0.5, 0.4, 0.25], 5, **kw)
+    s = MG.multigrid_solve_spin((b, b), t * t, U, beta, [0.5, 0.4, 0.25], 5, **kw)
+    assert np.abs(s["g_interp"].mean(axis=1) - a["g_interp"]).max() < 1e-12
+    assert abs(s["D"] - a["D"]) < 1e-12
