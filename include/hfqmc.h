@@ -276,6 +276,35 @@ int dmft_solve(hfqmc_ctx *ctx, double U, double beta, double t, const double *dt
                int32_t n_iw, int32_t n_iter, double mixing, double *bath_iw, double *g_fine,
                double *g_fine_err, double *history);
 
+/* multigrid_solve with spin-dependent baths bath_up, bath_dn (both with the
+ * 1/(i w)^3 moment bath_m3): one spin-resolved batched launch (as
+ * hfqmc_solve_spin, grid i with Philox grid key i), then per spin the
+ * reference-model spline (that spin's bath in the reference) and the
+ * quadratic fit in dtau^2.  g_fine[2 n_fine] = G_up(tau_j) then G_dn(tau_j),
+ * g_fine_err likewise or NULL; docc[2] (or NULL) the extrapolated D and its
+ * error.  Errors as multigrid_solve and hfqmc_solve_spin. */
+int multigrid_solve_spin(hfqmc_ctx *ctx, const double *bath_up, const double *bath_dn,
+                         int32_t n_iw, double bath_m3, double U, double beta, const double *dtaus,
+                         int32_t n_grids, uint64_t seed, const hfqmc_opts *opts, int32_t n_fine,
+                         double *g_fine, double *g_fine_err, double *docc);
+
+/* The DMFT cycle for Neel order on the bipartite Bethe lattice (the method's
+ * magnetic phases): sublattice B is sublattice A with the spins exchanged, so
+ * each iteration runs multigrid_solve_spin(bath_up, bath_dn, seed + (it << 32))
+ * and closes bath_up_new = 1/(i w - t^2 G_dn(i w)), bath_dn_new = 1/(i w - t^2
+ * G_up(i w)) (dmft_bethe_step per spin), then mixes as dmft_solve.  bath_up,
+ * bath_dn [2 n_iw] hold the starting baths (a spin-symmetric start stays
+ * symmetric only up to noise; a small staggered field seeds the order) and the
+ * last baths on return.  g_fine[2 n_fine] (and g_fine_err or NULL) the last
+ * iteration's extrapolated G_up, G_dn; history[5 n_iter] (or NULL): max
+ * |g_fine change| over both spins, max error bar, D, D error, and the
+ * staggered moment m = n_up - n_dn = G_up(beta-) - G_dn(beta-).  Errors as
+ * dmft_solve. */
+int dmft_solve_af(hfqmc_ctx *ctx, double U, double beta, double t, const double *dtaus,
+                  int32_t n_grids, uint64_t seed, const hfqmc_opts *opts, int32_t n_fine,
+                  int32_t n_iw, int32_t n_iter, double mixing, double *bath_up, double *bath_dn,
+                  double *g_fine, double *g_fine_err, double *history);
+
 /* U = 0 starting bath: Bethe-lattice local Green function, half-bandwidth 2t. */
 int bethe_semicircle_bath(double beta, double t, int32_t n_iw, double *bath_iw);
 

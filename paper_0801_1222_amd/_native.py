@@ -82,6 +82,12 @@ lib.hfqmc_solve.restype = C.c_int
 lib.hfqmc_solve_spin.argtypes = [_ctx_p, _pd, _pd, _i32, _f64, _f64, _f64, _u64, C.POINTER(Opts),
                                  _pd, _pd, _pd, C.POINTER(Stats)]
 lib.hfqmc_solve_spin.restype = C.c_int
+lib.multigrid_solve_spin.argtypes = [_ctx_p, _pd, _pd, _i32, _f64, _f64, _f64, _pd, _i32, _u64,
+                                     C.POINTER(Opts), _i32, _pd, _pd, _pd]
+lib.multigrid_solve_spin.restype = C.c_int
+lib.dmft_solve_af.argtypes = [_ctx_p, _f64, _f64, _f64, _pd, _i32, _u64, C.POINTER(Opts), _i32, _i32,
+                              _i32, _f64, _pd, _pd, _pd, _pd, _pd]
+lib.dmft_solve_af.restype = C.c_int
 lib.hfqmc_solve_dev.argtypes = [_ctx_p, C.c_void_p, _i32, _f64, _f64, _f64, _u64, C.POINTER(Opts),
                                 C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(Stats)]
 lib.hfqmc_solve_dev.restype = C.c_int
@@ -113,7 +119,8 @@ FLAG_G_FP32 = 16           # mixed mode: G stored in FP32 between recomputes
 
 EXPORTED = ["hfqmc_create", "hfqmc_destroy", "hfqmc_set_stream", "hfqmc_last_error",
             "hfqmc_solve", "hfqmc_solve_spin", "hfqmc_solve_dev", "hfqmc_solve_grids", "multigrid_solve", "dmft_bethe_step",
-            "bethe_semicircle_bath", "bethe_atomic_bath", "bath_to_tau", "hfqmc_measure_peaks", "dmft_solve"]
+            "bethe_semicircle_bath", "bethe_atomic_bath", "bath_to_tau", "hfqmc_measure_peaks", "dmft_solve",
+            "multigrid_solve_spin", "dmft_solve_af"]
 
 
 def ptr(a, ctype=C.c_double):

@@ -330,6 +330,56 @@ def dmft_solve(ctx, U, beta, t, dtaus, seed, n_iter, bath_iw=None, n_iw=4096, n_
                 tau=np.arange(n_fine) * (beta / (n_fine - 1)), history=hist.reshape(-1, 4))
 
 
+def multigrid_solve_spin(ctx, bath_up, bath_dn, bath_m3, U, beta, dtaus, seed, n_fine=200,
+                         n_chains=1, warmup=0, sweeps=1, mode="rank1", recompute_every=0,
+                         delay_k=0, n_bins=0, drift_limit=0.0, eager=False, heat_bath=False,
+                         direct=False):
+    """multigrid_solve with spin-dependent baths: dict(g [2, n_fine] (up, down),
+    g_err, tau, D, D_err)."""
+    bu = np.ascontiguousarray(np.asarray(bath_up, dtype=np.complex128)).view(np.float64)
+    bd = np.ascontiguousarray(np.asarray(bath_dn, dtype=np.complex128)).view(np.float64)
+    if bu.shape != bd.shape:
+        raise ValueError("bath_up and bath_dn differ in length")
+    dt = np.ascontiguousarray(dtaus, dtype=np.float64)
+    o = _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drift_limit,
+              _flags(eager, heat_bath, direct))
+    gf = np.zeros(2 * n_fine)
+    ef = np.zeros(2 * n_fine)
+    dx = np.zeros(2)
+    rc = N.lib.multigrid_solve_spin(ctx.handle, N.ptr(bu), N.ptr(bd), bu.shape[0] // 2,
+                                    float(bath_m3), float(U), float(beta), N.ptr(dt), dt.shape[0],
+                                    int(seed), C.byref(o), int(n_fine), N.ptr(gf), N.ptr(ef),
+                                    N.ptr(dx))
+    N.check(rc, "multigrid_solve_spin")
+    return dict(g=gf.reshape(2, n_fine), g_err=ef.reshape(2, n_fine),
+                tau=np.arange(n_fine) * (beta / (n_fine - 1)), D=float(dx[0]), D_err=float(dx[1]))
+
+
+def dmft_solve_af(ctx, U, beta, t, dtaus, seed, n_iter, bath_up, bath_dn, n_fine=200, mixing=0.0,
+                  n_chains=1, warmup=0, sweeps=1, mode="rank1", recompute_every=0, delay_k=0,
+                  n_bins=0, drift_limit=0.0, eager=False, heat_bath=False, direct=False):
+    """Neel-order DMFT cycle on the Bethe lattice from the given spin baths;
+    returns dict(baths (up, down), g [2, n_fine], g_err, tau, history [n_iter, 5])
+    with history[it] = (max |g change|, max g_err, D, D_err, n_up - n_dn)."""
+    bu = np.ascontiguousarray(np.asarray(bath_up, dtype=np.complex128)).copy().view(np.float64)
+    bd = np.ascontiguousarray(np.asarray(bath_dn, dtype=np.complex128)).copy().view(np.float64)
+    if bu.shape != bd.shape:
+        raise ValueError("bath_up and bath_dn differ in length")
+    dt = np.ascontiguousarray(dtaus, dtype=np.float64)
+    o = _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drift_limit,
+              _flags(eager, heat_bath, direct))
+    gf = np.zeros(2 * n_fine)
+    ef = np.zeros(2 * n_fine)
+    hist = np.zeros(5 * int(n_iter))
+    rc = N.lib.dmft_solve_af(ctx.handle, float(U), float(beta), float(t), N.ptr(dt), dt.shape[0],
+                             int(seed), C.byref(o), int(n_fine), bu.shape[0] // 2, int(n_iter),
+                             float(mixing), N.ptr(bu), N.ptr(bd), N.ptr(gf), N.ptr(ef), N.ptr(hist))
+    N.check(rc, "dmft_solve_af")
+    return dict(baths=(bu.view(np.complex128), bd.view(np.complex128)), g=gf.reshape(2, n_fine),
+                g_err=ef.reshape(2, n_fine), tau=np.arange(n_fine) * (beta / (n_fine - 1)),
+                history=hist.reshape(-1, 5))
+
+
 def dmft_bethe_step(g_fine, bath_iw_prev, bath_m3, U, beta, t):
     """New bath 1/(i w - t^2 G(i w)) on the frequencies of bath_iw_prev."""
     g = np.ascontiguousarray(g_fine, dtype=np.float64)

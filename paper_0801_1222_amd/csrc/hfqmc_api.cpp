@@ -1049,3 +1049,134 @@ extern "C" int dmft_solve(hfqmc_ctx* c, double U, double beta, double t, const d
   if (g_fine_err) std::memcpy(g_fine_err, err.data(), sizeof(double) * n_fine);
   return HFQMC_OK;
 }
+
+// The multigrid step with spin-dependent baths: one batched spin-resolved
+// launch over the grids, then for each spin the reference-model spline onto
+// the fine grid (that spin's bath in the reference) and the extrapolation.
+extern "C" int multigrid_solve_spin(hfqmc_ctx* c, const double* bath_up, const double* bath_dn,
+                                    int32_t n_iw, double bath_m3, double U, double beta,
+                                    const double* dtaus, int32_t n_grids, uint64_t seed,
+                                    const hfqmc_opts* opts, int32_t n_fine, double* g_fine,
+                                    double* g_fine_err, double* docc) {
+  if (!bath_up || !bath_dn || !dtaus || !g_fine)
+    return fail(HFQMC_EINVAL, "multigrid_solve_spin: null pointer");
+  if (n_grids < 3) return fail(HFQMC_EINVAL, "multigrid_solve_spin: n_grids=%d < 3", n_grids);
+  if (n_fine < 4) return fail(HFQMC_EINVAL, "multigrid_solve_spin: n_fine=%d < 4", n_fine);
+  if (n_iw < 16) return fail(HFQMC_EINVAL, "multigrid_solve_spin: n_iw=%d < 16", n_iw);
+  if (!(beta > 0) || !(U >= 0)) return fail(HFQMC_EINVAL, "multigrid_solve_spin: U=%g beta=%g", U, beta);
+  std::vector<int32_t> Ls(n_grids);
+  std::vector<double> dts(n_grids);
+  long long Lsum = 0, Psum = 0;
+  for (int i = 0; i < n_grids; ++i) {
+    if (!(dtaus[i] > 0)) return fail(HFQMC_EINVAL, "dtau[%d]=%g", i, dtaus[i]);
+    Ls[i] = (int32_t)std::lround(beta / dtaus[i]);
+    dts[i] = beta / Ls[i];
+    Lsum += Ls[i];
+    Psum += 2 * (Ls[i] + 1);
+  }
+  const double* baths[2] = {bath_up, bath_dn};
+  std::vector<double> g0u(Lsum), g0d(Lsum), gg(Psum), ge(Psum), dd(2 * (size_t)n_grids);
+  long long off = 0;
+  for (int i = 0; i < n_grids; ++i) {
+    int rc = bath_to_tau(bath_up, n_iw, bath_m3, beta, Ls[i], g0u.data() + off);
+    if (!rc) rc = bath_to_tau(bath_dn, n_iw, bath_m3, beta, Ls[i], g0d.data() + off);
+    if (rc) return rc;
+    off += Ls[i];
+  }
+  Call call;
+  call.g0_dn = g0d.data();
+  int rc = solve_grids_impl(c, n_grids, Ls.data(), g0u.data(), U, beta, seed, opts, gg.data(),
+                            ge.data(), dd.data(), nullptr, call);
+  if (rc) return rc;
+  std::vector<double> tf(n_fine), gref_f(n_fine);
+  for (int j = 0; j < n_fine; ++j) tf[j] = j * (beta / (n_fine - 1));
+  for (int sp = 0; sp < 2; ++sp) {
+    host::reference_tau(baths[sp], n_iw, bath_m3, U, beta, tf.data(), n_fine, gref_f.data());
+    std::vector<double> gi((size_t)n_grids * n_fine), ei((size_t)n_grids * n_fine);
+    off = 0;
+    for (int i = 0; i < n_grids; ++i) {
+      const int L = Ls[i];
+      const long long o = off + (long long)sp * (L + 1);   // [grid][spin][L+1]
+      std::vector<double> tk(L + 1), gref_k(L + 1), d(L + 1);
+      for (int k = 0; k <= L; ++k) tk[k] = k * (beta / L);
+      host::reference_tau(baths[sp], n_iw, bath_m3, U, beta, tk.data(), L + 1, gref_k.data());
+      for (int k = 0; k <= L; ++k) d[k] = gg[o + k] - gref_k[k];
+      host::Spline spl(tk.data(), d.data(), L + 1);
+      for (int j = 0; j < n_fine; ++j) {
+        gi[(size_t)i * n_fine + j] = gref_f[j] + spl(tf[j]);
+        const double x = tf[j] / (beta / L);
+        int k0 = (int)std::floor(x);
+        if (k0 < 0) k0 = 0;
+        if (k0 > L - 1) k0 = L - 1;
+        const double fr = x - k0;
+        ei[(size_t)i * n_fine + j] = ge[o + k0] * (1.0 - fr) + ge[o + k0 + 1] * fr;
+      }
+      off += 2 * (L + 1);
+    }
+    std::vector<double> err(n_fine);
+    host::extrapolate(dts.data(), n_grids, gi.data(), ei.data(), n_fine, g_fine + (size_t)sp * n_fine,
+                      err.data());
+    if (g_fine_err) std::memcpy(g_fine_err + (size_t)sp * n_fine, err.data(), sizeof(double) * n_fine);
+  }
+  if (docc) {
+    std::vector<double> dv(n_grids), de(n_grids);
+    for (int i = 0; i < n_grids; ++i) {
+      dv[i] = dd[2 * i];
+      de[i] = dd[2 * i + 1];
+    }
+    host::extrapolate(dts.data(), n_grids, dv.data(), de.data(), 1, &docc[0], &docc[1]);
+  }
+  return HFQMC_OK;
+}
+
+extern "C" int dmft_solve_af(hfqmc_ctx* c, double U, double beta, double t, const double* dtaus,
+                             int32_t n_grids, uint64_t seed, const hfqmc_opts* opts, int32_t n_fine,
+                             int32_t n_iw, int32_t n_iter, double mixing, double* bath_up,
+                             double* bath_dn, double* g_fine, double* g_fine_err,
+                             double* history) {
+  if (!bath_up || !bath_dn || !g_fine || !dtaus || !opts)
+    return fail(HFQMC_EINVAL, "dmft_solve_af: null pointer");
+  if (n_iter < 1) return fail(HFQMC_EINVAL, "dmft_solve_af: n_iter=%d", n_iter);
+  if (!(mixing >= 0.0 && mixing < 1.0)) return fail(HFQMC_EINVAL, "dmft_solve_af: mixing=%g", mixing);
+  if (!(t > 0)) return fail(HFQMC_EINVAL, "dmft_solve_af: t=%g", t);
+  if (n_fine < 4 || n_iw < 16) return fail(HFQMC_EINVAL, "dmft_solve_af: n_fine=%d n_iw=%d", n_fine, n_iw);
+  const double m3 = t * t;
+  std::vector<double> prev(2 * (size_t)n_fine), err(2 * (size_t)n_fine);
+  std::vector<double> nb_up(2 * (size_t)n_iw), nb_dn(2 * (size_t)n_iw);
+  {
+    std::vector<double> tf(n_fine);
+    for (int j = 0; j < n_fine; ++j) tf[j] = j * (beta / (n_fine - 1));
+    host::reference_tau(bath_up, n_iw, m3, 0.0, beta, tf.data(), n_fine, prev.data());
+    host::reference_tau(bath_dn, n_iw, m3, 0.0, beta, tf.data(), n_fine, prev.data() + n_fine);
+  }
+  for (int it = 0; it < n_iter; ++it) {
+    const uint64_t s_it = seed + ((uint64_t)it << 32);
+    double dx[2] = {0.0, 0.0};
+    int rc = multigrid_solve_spin(c, bath_up, bath_dn, n_iw, m3, U, beta, dtaus, n_grids, s_it, opts,
+                                  n_fine, g_fine, err.data(), dx);
+    if (rc) return rc;
+    double dmax = 0.0, emax = 0.0;
+    for (size_t j = 0; j < 2 * (size_t)n_fine; ++j) {
+      dmax = std::max(dmax, std::fabs(g_fine[j] - prev[j]));
+      emax = std::max(emax, err[j]);
+      prev[j] = g_fine[j];
+    }
+    if (history) {
+      history[5 * it] = dmax;
+      history[5 * it + 1] = emax;
+      history[5 * it + 2] = dx[0];
+      history[5 * it + 3] = dx[1];
+      history[5 * it + 4] = g_fine[n_fine - 1] - g_fine[2 * n_fine - 1];   // n_up - n_dn
+    }
+    // Neel order on the bipartite lattice: spin sigma's bath closes over G_-sigma
+    rc = host::bethe_step(g_fine, n_fine, bath_up, n_iw, m3, U, beta, t, nb_dn.data());
+    if (!rc) rc = host::bethe_step(g_fine + n_fine, n_fine, bath_dn, n_iw, m3, U, beta, t, nb_up.data());
+    if (rc) return fail(rc, "dmft_solve_af: Bethe step failed in iteration %d", it);
+    for (size_t q = 0; q < nb_up.size(); ++q) {
+      bath_up[q] = mixing * bath_up[q] + (1.0 - mixing) * nb_up[q];
+      bath_dn[q] = mixing * bath_dn[q] + (1.0 - mixing) * nb_dn[q];
+    }
+  }
+  if (g_fine_err) std::memcpy(g_fine_err, err.data(), sizeof(double) * 2 * n_fine);
+  return HFQMC_OK;
+}
