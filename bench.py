@@ -213,12 +213,21 @@ def cpu_baseline(sample_chains, warmup, sweeps, procs):
     with ctx.Pool(procs) as pool:
         pool.map(_oracle_chain, [(c, warmup, sweeps) for c in range(sample_chains)])
     dt = time.perf_counter() - t0
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return dict(value=sample_chains * (warmup + sweeps) / dt, unit="sweeps/s", cores=procs,
                 kind="oracle",
                 sample="chains 0..%d of the beta=40 U=4.5 L=400 workload, %d+%d sweeps each, "
                        "FP64 rank-1 with recompute every 100, one chain per process, "
-                       "%d processes x 1 BLAS thread, %.1f s wall"
-                       % (sample_chains - 1, warmup, sweeps, procs, dt))
+                       "%d processes x 1 BLAS thread on %s, %.1f s wall"
+                       % (sample_chains - 1, warmup, sweeps, procs, model, dt))
 
 
 def _oracle_chain(args):
