@@ -220,6 +220,40 @@ struct GridHost {
 
 // How a solve is called: host or device buffers, a cap on the LU panel width
 // (autotuner trials), and whether it is a trial launch of the autotuner.
+// LU panel widths and LDS of a launch.  Where LDS forces a panel below 16 on
+// some grid and every grid reaches 16 with its panel in the workspace, the
+// launch moves the panels there (pg = 1): long grids keep the matrix-core LU.
+struct LuPlan {
+  std::vector<int> nb;
+  int lds = 0, scratch = 0, lu_nb = 0, pg = 0;
+};
+
+LuPlan plan_lu(int n_grids, const int32_t* Ls, int Lmax, int mode, int nb_max, int direct,
+               bool allow_pg) {
+  LuPlan a;
+  for (int pg = 0; pg < 2; ++pg) {
+    LuPlan b;
+    b.nb.resize(n_grids);
+    b.pg = pg;
+    bool narrow = false;
+    for (int i = 0; i < n_grids; ++i) {
+      int sc = 0;
+      const int l = lds_bytes(Lmax, Ls[i], mode, nb_max, direct, &b.nb[i], &sc, pg);
+      b.lds = std::max(b.lds, l);
+      b.scratch = std::max(b.scratch, sc);
+      b.lu_nb = std::max(b.lu_nb, b.nb[i]);
+      narrow = narrow || b.nb[i] < 16;
+    }
+    if (pg == 0) {
+      a = b;
+      if (!narrow || direct || !allow_pg) break;
+    } else if (!narrow) {
+      a = b;
+    }
+  }
+  return a;
+}
+
 struct Call {
   bool dev_io = false;
   int nb_max = 0;
@@ -268,13 +302,9 @@ int autotune(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double* g0_tau,
     if (he != hipSuccess) return fail(HFQMC_EDEVICE, "autotune: bath copy: %s", hipGetErrorString(he));
     g0 = g0h.data();
   }
-  int nb_widest = 0, scratch = 0;
   const int direct = (opts->flags & HFQMC_FLAG_DIRECT_RECOMPUTE) ? 1 : 0;
-  for (int i = 0; i < n_grids; ++i) {
-    int nb = 0;
-    (void)lds_bytes(Lmax, Ls[i], opts->mode, 0, direct, &nb, &scratch);
-    nb_widest = std::max(nb_widest, nb);
-  }
+  const int nb_widest =
+      plan_lu(n_grids, Ls, Lmax, opts->mode, 0, direct, !(opts->flags & HFQMC_FLAG_G_FP32)).lu_nb;
   std::vector<int> nbs = {nb_widest};
   if (nb_widest == 32) nbs.push_back(16);
   hfqmc_opts to;
@@ -371,15 +401,10 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
   // per grid: the recompute form and its LU panel width; the launch's LDS
   // covers the largest need (the head and update buffers are sized for Lmax)
   const int direct = (opts->flags & HFQMC_FLAG_DIRECT_RECOMPUTE) ? 1 : 0;
-  std::vector<int> g_nb(n_grids);
-  int lu_nb = 0, scratch = 0, lds = 0;
-  for (int i = 0; i < n_grids; ++i) {
-    int sc = 0;
-    const int l = lds_bytes(Lmax, Ls[i], r.mode, nb_max, direct, &g_nb[i], &sc);
-    lds = std::max(lds, l);
-    scratch = std::max(scratch, sc);
-    lu_nb = std::max(lu_nb, g_nb[i]);
-  }
+  const LuPlan plan = plan_lu(n_grids, Ls, Lmax, r.mode, nb_max, direct,
+                              !spin && !(opts->flags & HFQMC_FLAG_G_FP32));
+  const std::vector<int>& g_nb = plan.nb;
+  const int lu_nb = plan.lu_nb, scratch = plan.scratch, lds = plan.lds;
   if (lds + 1024 > c->lds_max)
     return fail(HFQMC_EUNSUPPORTED, "L=%d needs %d bytes of LDS, device allows %d", Lmax, lds, c->lds_max);
   std::vector<int> g_ref_nb(n_grids, 0);
@@ -548,6 +573,7 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
   p.direct = direct;
   p.ph = (opts->flags & HFQMC_FLAG_PH_SYMMETRIC) ? 1 : 0;
   p.spin = spin ? 1 : 0;
+  p.pg = plan.pg;
 
   // ---- the device launch sequence: bath matrices, zeroed accumulators and
   // counters (fill kernels), the persistent sweep kernel, the chain reduction

@@ -92,6 +92,7 @@ struct SweepParams {
   int direct;             // 1: recompute with the full L x L system (no reference reduction)
   int ph;                 // 1: particle-hole symmetric bath, only G_up kept (G_dn = 1 - G_up^T)
   int spin;               // 1: spin-dependent baths (GridDev::spin)
+  int pg;                 // 1: the LU panel lives in the workspace instead of LDS (large L)
 };
 
 constexpr int kThreads = 512;   // threads per persistent workgroup (8 wave64)
@@ -100,13 +101,19 @@ constexpr int kMaxK = 64;       // largest delayed rank
 
 // Workspace (doubles) needed per workgroup for chains of length up to Lmax.
 long long workspace_doubles(int Lmax, int kmax);
+// The LU panel's share of it, at its end ([Lmax + kNBMax][kNBMax + 2] doubles):
+// where LDS cannot hold a 16-wide panel of the reduced system, the panel moves
+// there and the recompute keeps the matrix-core path.
+constexpr long long panel_doubles(int Lmax) { return (long long)(Lmax + kNBMax) * (kNBMax + 2); }
 // Dynamic LDS bytes of the persistent kernel for a grid of L slices in a launch
 // whose longest grid has Lmax (the head and the update buffers are sized for
 // Lmax), and that grid's LU panel width (the widest that fits the LDS budget,
 // at most nb_max).  direct = 0 sizes the LU for the reduced system (at most
 // L/2 rows; the reduced form's product streams G[S,:] through LDS in slabs
-// that fit); the reference kernel uses direct = 1.
-int lds_bytes(int Lmax, int L, int mode, int nb_max, int direct, int* lu_nb, int* scratch_bytes);
+// that fit); the reference kernel uses direct = 1.  pg = 1: the panel is in the
+// workspace (panel_doubles), LDS holds the rest of the LU's state.
+int lds_bytes(int Lmax, int L, int mode, int nb_max, int direct, int* lu_nb, int* scratch_bytes,
+              int pg = 0);
 // Sets the kernel's dynamic-LDS limit (needed above 64 KiB); call before a
 // launch or a stream capture.
 hipError_t prepare_sweeps(int lds);

@@ -204,6 +204,7 @@ struct Chain {
   const double* G0d;      // spin-down bath and references (spin-dependent baths)
   const double* refQd[2];
   const double* refHd[2];
+  double* Pg;             // LU panel in the workspace (large L)
 };
 
 // Control state every thread keeps (uniform); the statistics live in LDS.
@@ -884,7 +885,7 @@ __device__ __forceinline__ double reduced_product_slabs(
 //
 // rhs_k (direct form only): right-hand side K = 1 - G0 instead of G0 (the
 // reference matrices Q_r).
-template <typename GT, bool SPIN = false>
+template <typename GT, bool SPIN = false, bool PG = false>
 __device__ __forceinline__ double dyson_solve(const Chain& ch, int sigma, GT* Gs_,
                                               int NB, bool reduced, bool rhs_k) {
   const int L = ch.L;
@@ -987,9 +988,10 @@ __device__ __forceinline__ double dyson_solve(const Chain& ch, int sigma, GT* Gs
     }
   }
 
-  double* P = reinterpret_cast<double*>(lu_scr);         // [np][ps]
+  // (PG: the panel in the workspace, the rest of the LU's state in LDS)
+  double* P = PG ? ch.Pg : reinterpret_cast<double*>(lu_scr);   // [np][ps]
   const int ls = NB + 1;
-  double* Li = P + np * ps;                              // [NB][ls] inverted diagonal triangle
+  double* Li = PG ? reinterpret_cast<double*>(lu_scr) : P + np * ps;  // [NB][ls] inverted triangle
   double* redv = Li + NB * ls;                           // [kThreads/64]
   int* redi = reinterpret_cast<int*>(redv + kThreads / 64);
   int* piv = redi + kThreads / 64;                       // [NB]
@@ -1458,7 +1460,7 @@ __device__ __forceinline__ void log_flip(const ChainIO& io, long long* st, long 
 
 // Dyson recompute of both spins (the kernel's only call site of the LU, so it
 // is inlined once).  The initial recompute of a chain is not counted as one.
-template <typename GT, bool SPIN = false>
+template <typename GT, bool SPIN = false, bool PG = false>
 __device__ __forceinline__ void recompute_both(const SweepParams& p, const Chain& ch, Counters& k,
                                                bool counted) {
   const long long t0 = wall_clock64();
@@ -1466,8 +1468,9 @@ __device__ __forceinline__ void recompute_both(const SweepParams& p, const Chain
   const int nsp = p.ph ? 1 : 2;
 #pragma unroll 1
   for (int sp = 0; sp < nsp; ++sp)
-    d = fmax(d, dyson_solve<GT, SPIN>(ch, sp ? -1 : +1, reinterpret_cast<GT*>(sp ? ch.Gd : ch.Gu),
-                                      ch.lu_nb, ch.reduced, false));
+    d = fmax(d, dyson_solve<GT, SPIN, PG>(ch, sp ? -1 : +1,
+                                          reinterpret_cast<GT*>(sp ? ch.Gd : ch.Gu), ch.lu_nb,
+                                          ch.reduced, false));
   if (counted && threadIdx.x == 0) {
     *ch.drift = fmax(*ch.drift, d);
     ch.st[ST_RECOMPUTES] += 1;
@@ -2301,12 +2304,14 @@ __device__ __forceinline__ void setup_chain(Chain& ch, const SweepParams& p, con
 }
 
 // VAR 0: every mode, chosen at run time; 1: mixed with G stored in FP32;
-// 2: spin-dependent baths (every mode, FP64-stored G, spin-resolved estimators)
+// 2: spin-dependent baths (every mode, FP64-stored G, spin-resolved estimators);
+// 3: as 0 with the LU panel in the workspace (long grids)
 template <int VAR>
 __device__ __forceinline__ void run_chain(const SweepParams& p, const GridDev* gd, int chain, double* ws,
                           char* lds) {
   typedef typename std::conditional<VAR == 1, float, double>::type GT;   // stored G
   constexpr bool SPIN = VAR == 2;
+  constexpr bool PG = VAR == 3;
   Chain ch;
   setup_chain(ch, p, gd, chain, ws, lds, gd->lu_nb, p.lds_scratch_bytes);
   const int L = ch.L;
@@ -2316,6 +2321,7 @@ __device__ __forceinline__ void run_chain(const SweepParams& p, const GridDev* g
   const int nb = p.n_bins;
   const int ng = SPIN ? 2 * (L + 1) : L + 1;   // estimator entries per sample
   ch.accg = gd->acc_g + (long long)chain * nb * ng;
+  if constexpr (PG) ch.Pg = ws + p.work_stride - panel_doubles(p.Lmax);
   if constexpr (SPIN) {
     ch.G0d = gd->G0d;
     ch.refQd[0] = gd->refQd[0];
@@ -2355,7 +2361,7 @@ __device__ __forceinline__ void run_chain(const SweepParams& p, const GridDev* g
   bool need_rec = true, first = true;
   for (;;) {
     if (need_rec) {
-      recompute_both<GT, SPIN>(p, ch, k, !first);
+      recompute_both<GT, SPIN, PG>(p, ch, k, !first);
       first = false;
       need_rec = false;
     }
@@ -2503,6 +2509,7 @@ long long workspace_doubles(int Lmax, int kmax) {
   const long long Lp = Lmax + kNBMax;  // LU padding
   long long w = 2 * L2 + 2 * Lp * Lp + Lp * kNBMax + 256;
   if (kmax > 1) w += 4LL * kMaxK * kWin + 4LL * Lmax * kMaxK;
+  w += panel_doubles(Lmax);   // last: the LU panel when it leaves LDS
   return (w + 63) & ~63LL;
 }
 
@@ -2512,27 +2519,30 @@ constexpr long long kLuExtra = 1024 + 2LL * (kThreads / 64) * (kNBMax + 2) * 8 +
 
 // LU panel width: the widest of 32/16/8/4 (at most nb_max) whose padded LDS
 // panel fits the budget.
-static int lu_panel(int Lmax, long long budget, int nb_max) {
+static int lu_panel(int Lmax, long long budget, int nb_max, int pg) {
   const int cand[4] = {32, 16, 8, 4};
   for (int q = 0; q < 4; ++q) {
     const int nb = cand[q];
     if (nb > nb_max) continue;
     const long long np = (Lmax + nb - 1) / nb * nb;
     if (nb >= 16 && np > (long long)kThreads * (nb == 32 ? 1 : 2)) continue;  // register panel
-    if (np * (nb + 2) * 8 + (long long)nb * (nb + 1) * 8 + kLuExtra <= budget) return nb;
+    const long long panel = pg ? 0 : np * (nb + 2) * 8;
+    if (panel + (long long)nb * (nb + 1) * 8 + kLuExtra <= budget) return nb;
   }
   return 4;
 }
 
-int lds_bytes(int Lmax, int L, int mode, int nb_max, int direct, int* lu_nb, int* scratch_bytes) {
+int lds_bytes(int Lmax, int L, int mode, int nb_max, int direct, int* lu_nb, int* scratch_bytes,
+              int pg) {
   const long long head = ((Lmax + 15) & ~15) + kUW * 8 + 64 * 8 + kStatBytes;
   const long long srb = direct ? 0 : ((4LL * L + 15) & ~15);   // reduced form's slice lists
   const long long budget = 150 * 1024 - head - srb;
   const int nsys = direct ? L : (L / 2 > 0 ? L / 2 : 1);
-  const int nb = lu_panel(nsys, budget, nb_max > 0 ? nb_max : kNBMax);
+  const int nb = lu_panel(nsys, budget, nb_max > 0 ? nb_max : kNBMax, pg);
   *lu_nb = nb;
   const long long np = (nsys + nb - 1) / nb * nb;
-  const long long lu = srb + np * (nb + 2) * 8 + (long long)nb * (nb + 1) * 8 + kLuExtra;
+  const long long lu =
+      srb + (pg ? 0 : np * (nb + 2) * 8) + (long long)nb * (nb + 1) * 8 + kLuExtra;
   long long sc = lu;
   if (mode == MODE_RANK1) {
     const long long r1 = 4LL * Lmax * 8;
@@ -2612,6 +2622,8 @@ hipError_t prepare_sweeps(int lds) {
     e = hipFuncSetAttribute((const void*)k_sweeps<1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)k_sweeps<2>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_sweeps<3>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
   return e;
 }
 
@@ -2620,6 +2632,8 @@ hipError_t launch_sweeps(const SweepParams& p, int n_wg, int lds, hipStream_t s)
     hipLaunchKernelGGL(k_sweeps<1>, dim3(n_wg), dim3(kThreads), lds, s, p);
   else if (p.spin)
     hipLaunchKernelGGL(k_sweeps<2>, dim3(n_wg), dim3(kThreads), lds, s, p);
+  else if (p.pg)
+    hipLaunchKernelGGL(k_sweeps<3>, dim3(n_wg), dim3(kThreads), lds, s, p);
   else
     hipLaunchKernelGGL(k_sweeps<0>, dim3(n_wg), dim3(kThreads), lds, s, p);
   return hipGetLastError();
