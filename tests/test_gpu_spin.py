@@ -141,3 +141,32 @@ def test_spin_baths_reject_single_matrix_and_fp32_storage(ctx):
                                            beta / L, 0, A.C.byref(o), P._native.ptr(g), None, None,
                                            None)
         assert rc == -1
+
+
+def test_spin_single_chain_bins_and_final_green(ctx):
+    # one chain: 20 bins of the spin-resolved estimator, then the final G of
+    # each spin against the exact Dyson solution with that spin's bath
+    import paper_0801_1222_amd as P
+    from oracle import philox
+    beta, U, L, seed = 6.0, 4.0, 24, 4
+    bu, bd = _baths(beta, L, eps_dn=0.35)
+    out = P.hfqmc_solve_spin(ctx, bu, bd, U, beta, beta / L, seed, n_chains=1, warmup=3, sweeps=40,
+                             mode="delayed", delay_k=8, flip_cap=20000, want_chain=True,
+                             want_green=True)
+    ref = OH.run_chain((bu, bd), U, beta, seed, chain=0, warmup=3, sweeps=40, n_rec=32, n_bins=20)
+    assert out["chain_g"].shape == (1, 20, 2, L + 1)
+    assert list(out["flips"][0]) == _codes(ref, L)
+    for b in range(20):
+        n = out["chain_n"][0][b]
+        assert n == ref["bins_n"][b] == 2
+        assert np.abs(out["chain_g"][0][b] / n - ref["bins_gs"][b] / n).max() < 1e-10
+    # binned mean and error of each spin
+    samples = ref["bins_gs"] / ref["bins_n"][:, None, None]
+    assert np.abs(out["g_up"] - samples[:, 0].mean(axis=0)).max() < 1e-10
+    assert np.abs(out["err_dn"] - samples[:, 1].std(axis=0, ddof=1) / np.sqrt(20)).max() < 1e-10
+    field = philox.initial_field(seed, 0, 0, L).astype(np.int64)
+    for code in out["flips"][0]:
+        field[code % L] *= -1
+    Gu, Gd = OH.green_from_field((OH.g0_matrix(bu), OH.g0_matrix(bd)), field, OH.hs_lambda(U, beta / L))
+    assert np.abs(out["green"][0, 0] - Gu).max() < 1e-10
+    assert np.abs(out["green"][0, 1] - Gd).max() < 1e-10
