@@ -104,7 +104,7 @@ typedef struct {
                                the choice is cached in the context */
   int32_t n_bins;           /* measurement bins per chain; 0 -> 20 if n_chains == 1 else 1 */
   int32_t flags;            /* HFQMC_FLAG_* bits */
-  double drift_limit;       /* 0: report only; > 0: HFQMC_EDRIFT if any recompute drift exceeds it */
+  double drift_limit;       /* 0: report only; > 0: HFQMC_EDRIFT if a sampled recompute drift exceeds it */
   /* Optional test hooks (NULL to disable).  Flip codes are sweep * L + l. */
   int64_t *flip_log;        /* [n_grids][n_chains][flip_cap] accepted flips, in order */
   int64_t *flip_count;      /* [n_grids][n_chains] number of accepted flips (may exceed flip_cap) */
@@ -115,13 +115,16 @@ typedef struct {
   double *chain_g;          /* [n_grids][n_chains][n_bins][L_i+1] per-bin sums of G(tau_k) */
   double *chain_d;          /* [n_grids][n_chains][n_bins] per-bin sums of D */
   int64_t *chain_n;         /* [n_grids][n_chains][n_bins] measurements per bin */
-  double *chain_drift;      /* [n_grids][n_chains] max elementwise drift at recomputes */
+  double *chain_drift;      /* [n_grids][n_chains] max elementwise drift at sampled recomputes */
   double *final_green;      /* single grid only: [n_chains][2][L][L] G_up, G_dn after the last sweep */
 } hfqmc_opts;
 
 typedef struct {
   double acc_rate;          /* accepted / proposed */
-  double max_drift;         /* max elementwise |G_updated - G_recomputed| over recomputes */
+  double max_drift;         /* max elementwise |G_updated - G_recomputed| over the sampled
+                               recomputes: the first and every 8th of each chain (before the
+                               others the pending flips are not flushed, the recompute
+                               replacing G); a non-finite G is reported at any recompute */
   double seconds_total;     /* wall time of the call */
   double seconds_kernel;    /* HIP-event time of the persistent sweep kernel */
   int64_t n_proposed, n_accepted, n_recomputes, n_bad_ratio, n_singular;

@@ -211,7 +211,15 @@ struct Chain {
 struct Counters {
   long long rep_i;   // next entry of the replay list
   int acc_since;     // accepted flips since the last recompute
+  int n_rec;         // recomputes so far (the initial one not counted)
 };
+
+// The drift (updated G against its recompute) is sampled on the first and
+// every kDriftEvery-th recompute of a chain.  Before the others the pending
+// flips are not flushed: the recompute replaces G by the exact G of the field,
+// which already holds those flips, so the chain is unchanged.
+constexpr int kDriftEvery = 8;
+__device__ __forceinline__ bool drift_sampled(int j) { return (j - 1) % kDriftEvery == 0; }
 
 // Adds v to statistic `which` (thread 0 keeps the LDS copy).
 __device__ __forceinline__ void stat_add(long long* st, int which, long long v) {
@@ -445,7 +453,8 @@ __device__ __forceinline__ void lu_strip_backward_mfma(double* __restrict__ A, i
                                                        int ns, int L,
                                                        const int* __restrict__ rowmap,
                                                        double& dmax,
-                                                       const int* __restrict__ perm) {
+                                                       const int* __restrict__ perm,
+                                                       bool drift) {
   constexpr int KS = NB / 4;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int li = lane & 15, lq = lane >> 4;
@@ -469,8 +478,17 @@ __device__ __forceinline__ void lu_strip_backward_mfma(double* __restrict__ A, i
         const int row = kb + 16 * ob + 4 * r + lq;
         const bool ok = row < ns && gc < L;
         grow[ob][r] = ok ? (rowmap ? rowmap[row] : row) : 0;
-        gold[ob][r] = ok ? Gs[grow[ob][r] * L + gc] : 0.0;
+        gold[ob][r] = 0.0;
       }
+    if (drift) {
+#pragma unroll
+      for (int ob = 0; ob < NB / 16; ++ob)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = kb + 16 * ob + 4 * r + lq;
+          if (row < ns && gc < L) gold[ob][r] = Gs[grow[ob][r] * L + gc];
+        }
+    }
 #pragma unroll
     for (int ob = 0; ob < NB / 16; ++ob) {
       doublex4 acc = {0.0, 0.0, 0.0, 0.0};
@@ -485,7 +503,7 @@ __device__ __forceinline__ void lu_strip_backward_mfma(double* __restrict__ A, i
         if (row < ns && gc < L) {
           // rows kb.. are final: write G and record the drift
           const double x = acc[r];
-          dmax = fmax(dmax, fabs(x - gold[ob][r]));
+          if (drift) dmax = fmax(dmax, fabs(x - gold[ob][r]));
           if (!(fabs(x) < INFINITY)) dmax = INFINITY;
           Gs[grow[ob][r] * L + gc] = x;
         }
@@ -747,7 +765,7 @@ template <typename GT>
 __device__ __forceinline__ double reduced_product_slabs(
     const double* __restrict__ Aq, double* __restrict__ Pq, double* __restrict__ Zl,
     GT* __restrict__ Gs_, const double* __restrict__ Hr_, const int* __restrict__ sr, int ns,
-    int nR, int kr, int L, long long lu_scr_bytes) {
+    int nR, int kr, int L, long long lu_scr_bytes, bool drift) {
   typename GlobalOf<GT>::type* __restrict__ Gs = (typename GlobalOf<GT>::type*)Gs_;
   gcdouble* __restrict__ Hr = (gcdouble*)Hr_;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -848,7 +866,7 @@ __device__ __forceinline__ double reduced_product_slabs(
                 const double x = acc[tt][r];
                 if (last) {
                   // the drift against the updated G the final rows replace
-                  dmax = fmax(dmax, fabs(x - Gs[oR[r] * L + col]));
+                  if (drift) dmax = fmax(dmax, fabs(x - Gs[oR[r] * L + col]));
                   if (!(fabs(x) < INFINITY)) dmax = INFINITY;
                   Gs[oR[r] * L + col] = x;
                 } else {
@@ -885,9 +903,11 @@ __device__ __forceinline__ double reduced_product_slabs(
 //
 // rhs_k (direct form only): right-hand side K = 1 - G0 instead of G0 (the
 // reference matrices Q_r).
+// drift = false: the G being replaced is not read (no drift is taken)
 template <typename GT, bool SPIN = false, bool PG = false>
 __device__ __forceinline__ double dyson_solve(const Chain& ch, int sigma, GT* Gs_,
-                                              int NB, bool reduced, bool rhs_k) {
+                                              int NB, bool reduced, bool rhs_k,
+                                              bool drift = true) {
   const int L = ch.L;
   const int t = threadIdx.x;
   const int lane = t & 63, wv = t >> 6;
@@ -937,7 +957,7 @@ __device__ __forceinline__ double dyson_solve(const Chain& ch, int sigma, GT* Gs
 #pragma unroll 4
         for (int j = lane; j < L; j += 64) {
           const double x = Hr[i * L + j];
-          dm = fmax(dm, fabs(x - Gs[i * L + j]));
+          if (drift) dm = fmax(dm, fabs(x - Gs[i * L + j]));
           if (!(fabs(x) < INFINITY)) dm = INFINITY;
           Gs[i * L + j] = x;
         }
@@ -1153,10 +1173,10 @@ __device__ __forceinline__ double dyson_solve(const Chain& ch, int sigma, GT* Gs
     if (NB >= 16) {
       if (NB == 32)
         lu_strip_backward_mfma<32, GT>(A, lda, kb, np, cend16, P, ps, Li, ls, Gs, ns, L, rowmap,
-                                       dmax, perm);
+                                       dmax, perm, drift);
       else
         lu_strip_backward_mfma<16, GT>(A, lda, kb, np, cend16, P, ps, Li, ls, Gs, ns, L, rowmap,
-                                       dmax, perm);
+                                       dmax, perm, drift);
     } else {
       switch (NB) {
         case 8: lu_strip_backward<8>(A, lda, kb, np, cend, P, ps); break;
@@ -1172,7 +1192,7 @@ __device__ __forceinline__ double dyson_solve(const Chain& ch, int sigma, GT* Gs
 #pragma unroll 4
       for (int j = lane; j < L; j += 64) {
         const double x = A[i * lda + np + j];
-        dmax = fmax(dmax, fabs(x - Gs[gi * L + j]));
+        if (drift) dmax = fmax(dmax, fabs(x - Gs[gi * L + j]));
         if (!(fabs(x) < INFINITY)) dmax = INFINITY;
         Gs[gi * L + j] = x;
       }
@@ -1211,7 +1231,8 @@ __device__ __forceinline__ double dyson_solve(const Chain& ch, int sigma, GT* Gs
       // G[S,:] does not fit LDS 16 columns wide: K in slabs (large L)
       dmax = fmax(dmax, reduced_product_slabs(Aq, A + (long long)nR * kr,
                                               reinterpret_cast<double*>(lu_scr), Gs_,
-                                              (const double*)Hr, sr, ns, nR, kr, L, lu_scr_bytes));
+                                              (const double*)Hr, sr, ns, nR, kr, L, lu_scr_bytes,
+                                              drift));
     } else {
       int zw = 64;                                        // chunk width
       while (zw > 16 && (long long)kr * (zw + 2) * 8 > lu_scr_bytes) zw >>= 1;
@@ -1260,7 +1281,7 @@ __device__ __forceinline__ double dyson_solve(const Chain& ch, int sigma, GT* Gs
   #pragma unroll
             for (int r = 0; r < 4; ++r) {
               acc[tt][r] = (tt < ntile) ? Hr[oR[r] * L + col] : 0.0;
-              gold[tt][r] = (tt < ntile) ? Gs[oR[r] * L + col] : 0.0;
+              gold[tt][r] = (drift && tt < ntile) ? Gs[oR[r] * L + col] : 0.0;
             }
           }
           // steps q0.. of this lane's K range (clamped, in bounds: ks is even)
@@ -1299,7 +1320,7 @@ __device__ __forceinline__ double dyson_solve(const Chain& ch, int sigma, GT* Gs
               for (int r = 0; r < 4; ++r) {
                 if (orow[r] < nR) {
                   const double x = acc[tt][r];
-                  dmax = fmax(dmax, fabs(x - gold[tt][r]));
+                  if (drift) dmax = fmax(dmax, fabs(x - gold[tt][r]));
                   if (!(fabs(x) < INFINITY)) dmax = INFINITY;
                   Gs[oR[r] * L + col] = x;
                 }
@@ -1470,10 +1491,14 @@ __device__ __forceinline__ void recompute_both(const SweepParams& p, const Chain
   for (int sp = 0; sp < nsp; ++sp)
     d = fmax(d, dyson_solve<GT, SPIN, PG>(ch, sp ? -1 : +1,
                                           reinterpret_cast<GT*>(sp ? ch.Gd : ch.Gu), ch.lu_nb,
-                                          ch.reduced, false));
-  if (counted && threadIdx.x == 0) {
-    *ch.drift = fmax(*ch.drift, d);
-    ch.st[ST_RECOMPUTES] += 1;
+                                          ch.reduced, false, counted && drift_sampled(k.n_rec + 1)));
+  if (counted) {
+    k.n_rec += 1;
+    if (threadIdx.x == 0) {
+      // (a non-finite G is reported whether or not the drift is sampled)
+      if (drift_sampled(k.n_rec) || !(d < INFINITY)) *ch.drift = fmax(*ch.drift, d);
+      ch.st[ST_RECOMPUTES] += 1;
+    }
   }
   k.acc_since = 0;
   stat_add(ch.st, ST_T_REC, wall_clock64() - t0);
@@ -2240,6 +2265,11 @@ __device__ __forceinline__ int sweep_window(const SweepParams& p, const Chain& c
       capture_coefficients(ch, w, l0 - pos, m0, m, nsp);
       if (t == 0) ch.st[ST_T_FLUSH] += wall_clock64() - t0;
     }
+    // a recompute that does not sample the drift needs no flush before it
+    if (m > 0 && k.acc_since == p.n_rec && !drift_sampled(k.n_rec + 1)) {
+      m = 0;
+      m_inv = 0;
+    }
     // flush at delay_k pending, before a recompute and at the sweep end
     if (m > 0 && (close || l0 >= L)) {
       const long long t0 = wall_clock64();
@@ -2340,7 +2370,7 @@ __device__ __forceinline__ void run_chain(const SweepParams& p, const GridDev* g
   if (threadIdx.x < NSTAT) ch.st[threadIdx.x] = 0;
   if (threadIdx.x == 0) *ch.drift = 0.0;
   __syncthreads();
-  Counters k = {0, 0};
+  Counters k = {0, 0, 0};
 
   ChainIO io;
   io.flog = gd->flip_log ? gd->flip_log + (long long)chain * p.flip_cap : nullptr;
