@@ -11,7 +11,10 @@
 //                   blocked FP64 LU with partial pivoting inside the workgroup
 //   measurement     after every measured sweep: translation/spin-averaged G(tau_k), D
 // The formulas are the standard Hirsch-Fye ones that the paper relies on
-// (Introduction: Trotter slices, binary HS field, MC sampling).
+// (Introduction: Trotter slices, binary HS field, MC sampling).  The sweep
+// kernel comes in four instantiations (run_chain's VAR): every update mode
+// chosen at run time; the mixed mode with G stored in FP32; spin-dependent
+// baths; and the first with the LU panel in the workspace for long grids.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -1359,7 +1362,7 @@ __device__ __forceinline__ void measure(const Chain& ch, int bin, bool ph) {
     // G(i, i - k), with sign - where i - k wraps
     double up = 0.0, dn = 0.0;
     if (!ph) {
-#pragma unroll 8
+#pragma unroll 16
       for (int i = 0; i < L; ++i) {
         int j = i - k;
         double sg = 1.0;
@@ -1374,7 +1377,7 @@ __device__ __forceinline__ void measure(const Chain& ch, int bin, bool ph) {
     } else {
       // and G_up(i, i + k), with sign - where i + k wraps, for the spin-down term
       double tr = 0.0;
-#pragma unroll 8
+#pragma unroll 16
       for (int i = 0; i < L; ++i) {
         int j = i - k, j2 = i + k;
         double sg = 1.0, sg2 = 1.0;
