@@ -181,6 +181,32 @@ def batched_grids(P, ctx, name, beta, U, dtaus, n_chains, warmup, sweeps, mode, 
                 workgroups=st[0]["n_workgroups"])
 
 
+def single_chain_l20(P, ctx):
+    """The smallest workload: one chain, beta=10 U=4 dtau=0.5 (L=20), seed 0,
+    1000+20000 sweeps, FP64 rank-1, recompute every 100, 20 bins; beside it the
+    oracle on the same chain for 100+2000 sweeps on one host core."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import bath as OB
+    from oracle import hfqmc as OH
+    beta, U, L = 10.0, 4.0, 20
+    g0 = P.bath_to_tau(P.bethe_semicircle_bath(beta, 1.0, 20000), 1.0, beta, L)
+    r = P.hfqmc_solve(ctx, g0, U, beta, beta / L, 0, n_chains=1, warmup=1000, sweeps=20000,
+                      mode="rank1")
+    st = r["stats"]
+    g0o = OB.bath_to_tau(OB.semicircle_iw(beta, 1.0, 20000), 1.0, beta, L)
+    t0 = time.perf_counter()
+    with threadpool_limits(1):
+        OH.run_chain(g0o, U, beta, 0, warmup=100, sweeps=2000, n_bins=20)
+    dt = time.perf_counter() - t0
+    return dict(workload="one chain, beta=10 U=4 dtau=0.5 (L=20), 1000+20000 sweeps, rank-1",
+                sweeps_per_s=21000 / st["seconds_kernel"], kernel_s=st["seconds_kernel"],
+                acc_rate=st["acc_rate"], D=float(r["D"]), D_err=float(r["D_err"]),
+                g_beta_half=float(r["g"][L // 2]), g_beta_half_err=float(r["g_err"][L // 2]),
+                oracle_sweeps_per_s=2100 / dt,
+                note="latency-bound: one workgroup; oracle timed on 100+2000 sweeps, 1 core")
+
+
 def n_rec_flops(L, st, n_chains, spins=2):
     return (st["n_recomputes"] + n_chains) * spins * (8.0 / 3.0) * float(L) ** 3
 
@@ -402,6 +428,10 @@ def main():
         extra["three_grids_mixed"] = three
         progress("three grids L=400/500/800 (mixed): %.0f L=400-equivalent chain-sweeps/s"
                  % three["l400_equiv_sweeps_per_s"])
+        extra["single_chain_L20"] = single_chain_l20(P, ctx)
+        progress("one chain, L=20, 1000+20000 sweeps: %.0f sweeps/s (oracle %.0f)"
+                 % (extra["single_chain_L20"]["sweeps_per_s"],
+                    extra["single_chain_L20"]["oracle_sweeps_per_s"]))
     add_measured_peaks(rf, peaks)
     add_measured_peaks(rf["secondary"], peaks)
     phv = None
