@@ -102,3 +102,27 @@ def test_delayed_c2_shape_sampled_chains(ctx):
         assert list(out["flips"][c]) == _codes(ref, L)
         got = out["chain_g"][c][0] / out["chain_n"][c][0]
         assert np.abs(got - ref["bins_g"][0] / ref["bins_n"][0]).max() < 1e-10
+
+
+def test_drift_limit_raises_and_sampled_drift_is_reported(ctx):
+    # the FP32 flush leaves a drift far above 1e-12: the limit turns it into
+    # HFQMC_EDRIFT; a generous limit passes and the sampled drift is reported
+    import paper_0801_1222_amd as P
+    beta, U, L = 20.0, 4.5, 200
+    g0 = _bath(beta, L)
+    kw = dict(n_chains=4, warmup=1, sweeps=4, mode="mixed", delay_k=32)
+    with pytest.raises(P.HFQMCError) as e:
+        P.hfqmc_solve(ctx, g0, U, beta, 0.1, 3, drift_limit=1e-12, **kw)
+    assert e.value.code == -5
+    out = P.hfqmc_solve(ctx, g0, U, beta, 0.1, 3, drift_limit=1.0, **kw)
+    st = out["stats"]
+    assert st["n_recomputes"] > 4 and 1e-12 < st["max_drift"] < 1.0
+    # FP64 delayed: the same chains whether or not the drift is sampled at a
+    # recompute (the recompute replaces G): identical to the oracle flip for flip
+    ref = OH.run_chain(g0, U, beta, 3, chain=0, warmup=1, sweeps=12, n_rec=128)
+    f64 = P.hfqmc_solve(ctx, g0, U, beta, 0.1, 3, n_chains=1, warmup=1, sweeps=12, n_bins=1,
+                        mode="delayed", delay_k=32, flip_cap=20000, want_chain=True)
+    assert ref["n_recomputes"] > 8
+    assert list(f64["flips"][0]) == _codes(ref, L)
+    assert np.abs(f64["chain_g"][0][0] / f64["chain_n"][0][0]
+                  - ref["bins_g"][0] / ref["bins_n"][0]).max() < 1e-10
