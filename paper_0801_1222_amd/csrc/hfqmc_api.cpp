@@ -268,7 +268,8 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
 // Autotuner: k in {16, 32, 64} (recompute interval 4k unless given) and the
 // LU panel width (the widest that fits, and 16 where 32 fits), each timed on a
 // short trial launch of the caller's grids and chain count (no warm-up, two
-// sweeps, eager launches); the fastest kernel time wins and is cached.
+// sweeps, one where a grid reaches L = 1000; eager launches); the fastest
+// kernel time wins and is cached.
 int autotune(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double* g0_tau, bool dev_io,
              double U, double beta, uint64_t seed, const hfqmc_opts* opts, int Lmax,
              TuneChoice* out, double* seconds) {
@@ -312,7 +313,7 @@ int autotune(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double* g0_tau,
   to.n_chains = opts->n_chains;
   to.mode = opts->mode;
   to.warmup = 0;
-  to.sweeps = 2;
+  to.sweeps = Lmax >= 1000 ? 1 : 2;   // long grids: one sweep already takes seconds
   to.recompute_every = opts->recompute_every;
   to.n_bins = 1;
   to.flags = (opts->flags & (HFQMC_FLAG_HEAT_BATH | HFQMC_FLAG_DIRECT_RECOMPUTE |
