@@ -327,14 +327,25 @@ def reduce_chains_spin(results):
     return g, g_err, float(d_samples.mean()), d_err
 
 
+def _chain_job(job):
+    """run_chain(*args, **kw) for a (args, kw) pair (a picklable job for process pools)."""
+    args, kw = job
+    return run_chain(*args, **kw)
+
+
 def solve(g_tau, U, beta, seed, n_chains=1, warmup=0, sweeps=1, n_rec=100,
-          n_bins=None, grid_id=0, **kw):
-    """Fixed-dtau solve: n_chains independent chains (chain c uses seed + c)."""
+          n_bins=None, grid_id=0, mapper=None, **kw):
+    """Fixed-dtau solve: n_chains independent chains (chain c uses seed + c).
+
+    ``mapper``: optional map-like callable (e.g. a process pool's ``map``) that
+    runs the independent chains; the results are the same as with ``map``.
+    """
     if n_bins is None:
         n_bins = 20 if n_chains == 1 else 1
-    res = [run_chain(g_tau, U, beta, seed, chain=c, grid_id=grid_id, warmup=warmup,
-                     sweeps=sweeps, n_rec=n_rec, n_bins=n_bins, **kw)
-           for c in range(n_chains)]
+    jobs = [((g_tau, U, beta, seed), dict(chain=c, grid_id=grid_id, warmup=warmup,
+                                          sweeps=sweeps, n_rec=n_rec, n_bins=n_bins, **kw))
+            for c in range(n_chains)]
+    res = list((mapper or map)(_chain_job, jobs))
     g, g_err, D, d_err = reduce_chains(res)
     return dict(g=g, g_err=g_err, D=D, D_err=d_err, chains=res)
 

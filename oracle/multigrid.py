@@ -86,8 +86,11 @@ def extrapolate(dtaus, g_interp, e_interp):
 
 
 def multigrid_solve(bath_iw, m3, U, beta, dtaus, seed, n_chains, warmup, sweeps,
-                    n_rec=100, n_fine=200):
-    """Oracle multigrid solve: one fixed-dtau solve per grid (grid_id = i), then (i), (ii)."""
+                    n_rec=100, n_fine=200, mapper=None):
+    """Oracle multigrid solve: one fixed-dtau solve per grid (grid_id = i), then (i), (ii).
+
+    ``mapper``: optional map-like callable running each grid's independent chains
+    (see ``hfqmc.solve``); it does not change the result."""
     Ls, dts = grid_lengths(beta, dtaus)
     tau_f = fine_grid(beta, n_fine)
     gref_f = reference_tau(bath_iw, m3, U, beta, tau_f)
@@ -95,7 +98,7 @@ def multigrid_solve(bath_iw, m3, U, beta, dtaus, seed, n_chains, warmup, sweeps,
     for i, L in enumerate(Ls):
         g_tau = B.bath_to_tau(bath_iw, m3, beta, L)
         r = H.solve(g_tau, U, beta, seed, n_chains=n_chains, warmup=warmup,
-                    sweeps=sweeps, n_rec=n_rec, grid_id=i)
+                    sweeps=sweeps, n_rec=n_rec, grid_id=i, mapper=mapper)
         tau_k = np.arange(L + 1) * (beta / L)
         gref_k = reference_tau(bath_iw, m3, U, beta, tau_k)
         g_f, e_f = interpolate_grid(r["g"], r["g_err"], beta, gref_k, gref_f, tau_f)
