@@ -2,9 +2,9 @@
  *
  * Method: multigrid Hirsch-Fye quantum Monte Carlo for dynamical mean-field
  * theory (N. Bluemer, arXiv:0801.1222).  The impurity problem is solved at a
- * fixed bath on several Trotter grids dtau_i by Monte Carlo sampling of a
- * binary Hubbard-Stratonovich field (Introduction; section "Multigrid HF-QMC
- * method"), the grid results are interpolated onto a common fine tau grid
+ * fixed bath on several Trotter grids dtau_i, each by Metropolis updates of the
+ * Ising-like auxiliary field s_l on the time slices (Introduction; section
+ * "Multigrid HF-QMC method"), the grid results are interpolated onto a common fine tau grid
  * with a reference model and extrapolated quadratically in dtau^2 to dtau -> 0
  * (same section, steps (i) and (ii)); the DMFT cycle is closed on the Bethe
  * lattice with semi-elliptic DOS, W = 4t (Fig. 1 and "Benchmark results").
@@ -104,7 +104,8 @@ typedef struct {
                                the choice is cached in the context */
   int32_t n_bins;           /* measurement bins per chain; 0 -> 20 if n_chains == 1 else 1 */
   int32_t flags;            /* HFQMC_FLAG_* bits */
-  double drift_limit;       /* 0: report only; > 0: HFQMC_EDRIFT if a sampled recompute drift exceeds it */
+  double drift_limit;       /* 0: report only; > 0: HFQMC_EDRIFT if a sampled recompute drift exceeds it
+                               (max_drift or max_drift_gtau of hfqmc_stats) */
   /* Optional test hooks (NULL to disable).  Flip codes are sweep * L + l. */
   int64_t *flip_log;        /* [n_grids][n_chains][flip_cap] accepted flips, in order */
   int64_t *flip_count;      /* [n_grids][n_chains] number of accepted flips (may exceed flip_cap) */
@@ -117,14 +118,19 @@ typedef struct {
   int64_t *chain_n;         /* [n_grids][n_chains][n_bins] measurements per bin */
   double *chain_drift;      /* [n_grids][n_chains] max elementwise drift at sampled recomputes */
   double *final_green;      /* single grid only: [n_chains][2][L][L] G_up, G_dn after the last sweep */
+  int32_t drift_every;      /* the drift against the recomputed G is taken on recompute 1,
+                               1 + drift_every, 1 + 2 drift_every, ... of each chain; 0 -> 8,
+                               1 -> every recompute (complete drift; the delayed modes then
+                               flush their pending flips before every recompute) */
 } hfqmc_opts;
 
 typedef struct {
   double acc_rate;          /* accepted / proposed */
   double max_drift;         /* max elementwise |G_updated - G_recomputed| over the sampled
-                               recomputes: the first and every 8th of each chain (before the
-                               others the pending flips are not flushed, the recompute
-                               replacing G); a non-finite G is reported at any recompute */
+                               recomputes: the first and every drift_every-th of each chain
+                               (before the others the pending flips are not flushed, the
+                               recompute replacing G); a non-finite G is reported at any
+                               recompute.  A lower bound of the drift unless drift_every = 1 */
   double seconds_total;     /* wall time of the call */
   double seconds_kernel;    /* HIP-event time of the persistent sweep kernel */
   int64_t n_proposed, n_accepted, n_recomputes, n_bad_ratio, n_singular;
@@ -154,6 +160,10 @@ typedef struct {
   double seconds_sweep_kernel;  /* HIP-event time of the persistent sweep kernel alone (the
                                    launch sequence of seconds_kernel also builds the bath
                                    matrices and references and reduces the chains) */
+  double max_drift_gtau;    /* drift of the result itself: max over the sampled recomputes and
+                               the lags k of |G(tau_k) of G_updated - G(tau_k) of G_recomputed|,
+                               the translation- and spin-averaged estimator of the output
+                               (both spin-resolved estimators for spin-dependent baths) */
 } hfqmc_stats;
 
 /* Fixed-dtau solve: hfqmc_solve(G0(tau), U, beta, dtau, sweeps, seed) -> G(tau).

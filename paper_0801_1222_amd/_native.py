@@ -34,7 +34,7 @@ class Opts(C.Structure):
         ("flip_log", _pi64), ("flip_count", _pi64), ("flip_cap", _i64),
         ("replay_log", _pi64), ("replay_count", _pi64), ("replay_cap", _i64),
         ("chain_g", _pd), ("chain_d", _pd), ("chain_n", _pi64), ("chain_drift", _pd),
-        ("final_green", _pd),
+        ("final_green", _pd), ("drift_every", _i32),
     ]
 
 
@@ -52,6 +52,7 @@ class Stats(C.Structure):
         ("n_reduced_rows", _i64), ("recompute_reduced", _i32), ("reserved", _i32),
         ("chain_s_lu_gemm", _f64), ("chain_s_flush_vectors", _f64), ("chain_s_flush_gemm", _f64),
         ("chain_s_window_apply", _f64), ("chain_s_fold", _f64), ("seconds_sweep_kernel", _f64),
+        ("max_drift_gtau", _f64),
     ]
 
     def as_dict(self):

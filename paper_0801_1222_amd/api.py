@@ -67,8 +67,10 @@ def _flags(eager=False, heat_bath=False, direct=False, ph=False, g_fp32=False):
             | (N.FLAG_PH_SYMMETRIC if ph else 0) | (N.FLAG_G_FP32 if g_fp32 else 0))
 
 
-def _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drift_limit, flags=0):
+def _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drift_limit, flags=0,
+          drift_every=0):
     o = N.Opts()
+    o.drift_every = int(drift_every)
     o.flags = int(flags)
     o.n_chains = int(n_chains)
     o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
@@ -153,14 +155,14 @@ class _Hooks:
 
 
 def hfqmc_solve(ctx, g0_tau, U, beta, dtau, seed, n_chains=1, warmup=0, sweeps=1,
-                mode="rank1", recompute_every=0, delay_k=0, n_bins=0, drift_limit=0.0,
+                mode="rank1", recompute_every=0, delay_k=0, n_bins=0, drift_limit=0.0, drift_every=0,
                 flip_cap=0, replay=None, want_chain=False, want_green=False, eager=False,
                 heat_bath=False, direct=False, ph=False, g_fp32=False):
     """Fixed-dtau solve; returns dict(g, g_err, D, D_err, stats, [hooks])."""
     g0 = np.ascontiguousarray(g0_tau, dtype=np.float64)
     L = g0.shape[0]
     o = _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drift_limit,
-              _flags(eager, heat_bath, direct, ph, g_fp32))
+              _flags(eager, heat_bath, direct, ph, g_fp32), drift_every=drift_every)
     hk = _Hooks(o, 1, n_chains, [L], n_bins, flip_cap,
                 [replay] if replay is not None else None, want_chain, want_green)
     g = np.zeros(L + 1)
@@ -183,7 +185,7 @@ def hfqmc_solve(ctx, g0_tau, U, beta, dtau, seed, n_chains=1, warmup=0, sweeps=1
 
 
 def hfqmc_solve_spin(ctx, g0_up, g0_dn, U, beta, dtau, seed, n_chains=1, warmup=0, sweeps=1,
-                     mode="rank1", recompute_every=0, delay_k=0, n_bins=0, drift_limit=0.0,
+                     mode="rank1", recompute_every=0, delay_k=0, n_bins=0, drift_limit=0.0, drift_every=0,
                      flip_cap=0, replay=None, want_chain=False, want_green=False, eager=False,
                      heat_bath=False, direct=False):
     """Fixed-dtau solve with spin-dependent baths; returns dict(g_up, g_dn,
@@ -194,7 +196,7 @@ def hfqmc_solve_spin(ctx, g0_up, g0_dn, U, beta, dtau, seed, n_chains=1, warmup=
         raise ValueError("g0_up and g0_dn differ in length")
     L = gu.shape[0]
     o = _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drift_limit,
-              _flags(eager, heat_bath, direct))
+              _flags(eager, heat_bath, direct), drift_every=drift_every)
     hk = _Hooks(o, 1, n_chains, [L], n_bins, flip_cap,
                 [replay] if replay is not None else None, want_chain, want_green, spins=2)
     g = np.zeros(2 * (L + 1))
@@ -217,12 +219,12 @@ def hfqmc_solve_spin(ctx, g0_up, g0_dn, U, beta, dtau, seed, n_chains=1, warmup=
 
 def hfqmc_solve_dev(ctx, g0_tau, L, U, beta, dtau, seed, g_tau, g_err=None, docc=None,
                     n_chains=1, warmup=0, sweeps=1, mode="rank1", recompute_every=0, delay_k=0,
-                    n_bins=0, drift_limit=0.0, eager=False, heat_bath=False, direct=False,
+                    n_bins=0, drift_limit=0.0, drift_every=0, eager=False, heat_bath=False, direct=False,
                     ph=False, g_fp32=False):
     """hfqmc_solve on device buffers (raw device addresses as ints, e.g. a torch
     tensor's data_ptr(), on the context's device and stream); returns the stats."""
     o = _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drift_limit,
-              _flags(eager, heat_bath, direct, ph, g_fp32))
+              _flags(eager, heat_bath, direct, ph, g_fp32), drift_every=drift_every)
     st = N.Stats()
     rc = N.lib.hfqmc_solve_dev(ctx.handle, C.c_void_p(int(g0_tau)), int(L), float(U), float(beta),
                                float(dtau), int(seed), C.byref(o), C.c_void_p(int(g_tau)),
@@ -241,7 +243,7 @@ def hfqmc_measure_peaks(ctx):
 
 
 def hfqmc_solve_grids(ctx, Ls, g0_taus, U, beta, seed, n_chains=1, warmup=0, sweeps=1,
-                      mode="rank1", recompute_every=0, delay_k=0, n_bins=0, drift_limit=0.0,
+                      mode="rank1", recompute_every=0, delay_k=0, n_bins=0, drift_limit=0.0, drift_every=0,
                       flip_cap=0, replay=None, want_chain=False, eager=False, heat_bath=False,
                       direct=False, ph=False, g_fp32=False):
     """Several grids in one persistent launch; per-grid lists in the result."""
@@ -251,7 +253,7 @@ def hfqmc_solve_grids(ctx, Ls, g0_taus, U, beta, seed, n_chains=1, warmup=0, swe
     g0 = np.ascontiguousarray(np.concatenate([np.asarray(x, dtype=np.float64) for x in g0_taus]))
     assert g0.shape[0] == sum(Ls)
     o = _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drift_limit,
-              _flags(eager, heat_bath, direct, ph, g_fp32))
+              _flags(eager, heat_bath, direct, ph, g_fp32), drift_every=drift_every)
     hk = _Hooks(o, n, n_chains, Ls, n_bins, flip_cap, replay, want_chain, False)
     P = sum(L + 1 for L in Ls)
     g = np.zeros(P)
@@ -275,14 +277,14 @@ def hfqmc_solve_grids(ctx, Ls, g0_taus, U, beta, seed, n_chains=1, warmup=0, swe
 
 def multigrid_solve(ctx, bath_iw, bath_m3, U, beta, dtaus, seed, n_fine=200, n_chains=1,
                     warmup=0, sweeps=1, mode="rank1", recompute_every=0, delay_k=0, n_bins=0,
-                    drift_limit=0.0, eager=False, heat_bath=False, direct=False,
+                    drift_limit=0.0, drift_every=0, eager=False, heat_bath=False, direct=False,
                     ph=False, g_fp32=False):
     """dtau -> 0 extrapolated G(tau_j), tau_j = j beta/(n_fine-1)."""
     b = np.ascontiguousarray(np.asarray(bath_iw, dtype=np.complex128)).view(np.float64)
     n_iw = b.shape[0] // 2
     dt = np.ascontiguousarray(dtaus, dtype=np.float64)
     o = _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drift_limit,
-              _flags(eager, heat_bath, direct, ph, g_fp32))
+              _flags(eager, heat_bath, direct, ph, g_fp32), drift_every=drift_every)
     Ls = [int(round(beta / x)) for x in dt]
     gf = np.zeros(n_fine)
     ef = np.zeros(n_fine)
@@ -306,7 +308,7 @@ def multigrid_solve(ctx, bath_iw, bath_m3, U, beta, dtaus, seed, n_fine=200, n_c
 
 def dmft_solve(ctx, U, beta, t, dtaus, seed, n_iter, bath_iw=None, n_iw=4096, n_fine=200,
                mixing=0.0, n_chains=1, warmup=0, sweeps=1, mode="rank1", recompute_every=0,
-               delay_k=0, n_bins=0, drift_limit=0.0, eager=False, heat_bath=False, direct=False,
+               delay_k=0, n_bins=0, drift_limit=0.0, drift_every=0, eager=False, heat_bath=False, direct=False,
                ph=False, g_fp32=False):
     """Multigrid DMFT cycle on the Bethe lattice; starts from bath_iw (default:
     the U = 0 semicircle).  Returns dict(bath, g, g_err, tau, history) with
@@ -318,7 +320,7 @@ def dmft_solve(ctx, U, beta, t, dtaus, seed, n_iter, bath_iw=None, n_iw=4096, n_
     n_iw = b.shape[0] // 2
     dt = np.ascontiguousarray(dtaus, dtype=np.float64)
     o = _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drift_limit,
-              _flags(eager, heat_bath, direct, ph, g_fp32))
+              _flags(eager, heat_bath, direct, ph, g_fp32), drift_every=drift_every)
     gf = np.zeros(n_fine)
     ef = np.zeros(n_fine)
     hist = np.zeros(4 * int(n_iter))
@@ -332,7 +334,7 @@ def dmft_solve(ctx, U, beta, t, dtaus, seed, n_iter, bath_iw=None, n_iw=4096, n_
 
 def multigrid_solve_spin(ctx, bath_up, bath_dn, bath_m3, U, beta, dtaus, seed, n_fine=200,
                          n_chains=1, warmup=0, sweeps=1, mode="rank1", recompute_every=0,
-                         delay_k=0, n_bins=0, drift_limit=0.0, eager=False, heat_bath=False,
+                         delay_k=0, n_bins=0, drift_limit=0.0, drift_every=0, eager=False, heat_bath=False,
                          direct=False):
     """multigrid_solve with spin-dependent baths: dict(g [2, n_fine] (up, down),
     g_err, tau, D, D_err)."""
@@ -342,7 +344,7 @@ def multigrid_solve_spin(ctx, bath_up, bath_dn, bath_m3, U, beta, dtaus, seed, n
         raise ValueError("bath_up and bath_dn differ in length")
     dt = np.ascontiguousarray(dtaus, dtype=np.float64)
     o = _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drift_limit,
-              _flags(eager, heat_bath, direct))
+              _flags(eager, heat_bath, direct), drift_every=drift_every)
     gf = np.zeros(2 * n_fine)
     ef = np.zeros(2 * n_fine)
     dx = np.zeros(2)
@@ -357,7 +359,7 @@ def multigrid_solve_spin(ctx, bath_up, bath_dn, bath_m3, U, beta, dtaus, seed, n
 
 def dmft_solve_af(ctx, U, beta, t, dtaus, seed, n_iter, bath_up, bath_dn, n_fine=200, mixing=0.0,
                   n_chains=1, warmup=0, sweeps=1, mode="rank1", recompute_every=0, delay_k=0,
-                  n_bins=0, drift_limit=0.0, eager=False, heat_bath=False, direct=False):
+                  n_bins=0, drift_limit=0.0, drift_every=0, eager=False, heat_bath=False, direct=False):
     """Neel-order DMFT cycle on the Bethe lattice from the given spin baths;
     returns dict(baths (up, down), g [2, n_fine], g_err, tau, history [n_iter, 5])
     with history[it] = (max |g change|, max g_err, D, D_err, n_up - n_dn)."""
@@ -367,7 +369,7 @@ def dmft_solve_af(ctx, U, beta, t, dtaus, seed, n_iter, bath_up, bath_dn, n_fine
         raise ValueError("bath_up and bath_dn differ in length")
     dt = np.ascontiguousarray(dtaus, dtype=np.float64)
     o = _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drift_limit,
-              _flags(eager, heat_bath, direct))
+              _flags(eager, heat_bath, direct), drift_every=drift_every)
     gf = np.zeros(2 * n_fine)
     ef = np.zeros(2 * n_fine)
     hist = np.zeros(5 * int(n_iter))

@@ -173,7 +173,7 @@ extern "C" int hfqmc_set_stream(hfqmc_ctx* c, void* stream) {
 namespace {
 
 struct Resolved {
-  int n_chains, mode, n_rec, delay_k, window_b, n_bins;
+  int n_chains, mode, n_rec, delay_k, window_b, n_bins, drift_every;
   long long warmup, sweeps;
 };
 
@@ -185,6 +185,7 @@ int resolve_opts(const hfqmc_opts* o, Resolved* r) {
   if (o->mode < 0 || o->mode > 2) return fail(HFQMC_EINVAL, "mode=%d", o->mode);
   if (o->recompute_every < 0) return fail(HFQMC_EINVAL, "recompute_every=%d", o->recompute_every);
   if (o->n_bins < 0) return fail(HFQMC_EINVAL, "n_bins=%d", o->n_bins);
+  if (o->drift_every < 0) return fail(HFQMC_EINVAL, "drift_every=%d", o->drift_every);
   if (o->drift_limit < 0) return fail(HFQMC_EINVAL, "drift_limit < 0");
   if (o->flip_log && (!o->flip_count || o->flip_cap < 1)) return fail(HFQMC_EINVAL, "flip_log needs flip_count and flip_cap >= 1");
   if (o->replay_log && (!o->replay_count || o->replay_cap < 1)) return fail(HFQMC_EINVAL, "replay_log needs replay_count and replay_cap >= 1");
@@ -209,6 +210,7 @@ int resolve_opts(const hfqmc_opts* o, Resolved* r) {
   r->n_rec = o->recompute_every > 0 ? o->recompute_every
                                     : (o->mode == MODE_RANK1 ? 100 : 4 * r->delay_k);
   r->n_bins = o->n_bins > 0 ? o->n_bins : (o->n_chains == 1 ? 20 : 1);
+  r->drift_every = o->drift_every > 0 ? o->drift_every : 8;
   if (r->n_bins > r->sweeps) return fail(HFQMC_EINVAL, "n_bins=%d > sweeps", r->n_bins);
   return HFQMC_OK;
 }
@@ -315,6 +317,7 @@ int autotune(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double* g0_tau,
   to.warmup = 0;
   to.sweeps = Lmax >= 1000 ? 1 : 2;   // long grids: one sweep already takes seconds
   to.recompute_every = opts->recompute_every;
+  to.drift_every = opts->drift_every;
   to.n_bins = 1;
   to.flags = (opts->flags & (HFQMC_FLAG_HEAT_BATH | HFQMC_FLAG_DIRECT_RECOMPUTE |
                              HFQMC_FLAG_PH_SYMMETRIC | HFQMC_FLAG_G_FP32)) | HFQMC_FLAG_EAGER;
@@ -443,6 +446,7 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
       g.acc_n = b.take<long long>((size_t)nch * nbin);
       g.cstats = b.take<long long>((size_t)nch * NSTAT);
       g.cdrift = b.take<double>(nch);
+      g.cdrift_gt = b.take<double>(nch);
       g.flip_log = opts->flip_log ? b.take<long long>((size_t)nch * opts->flip_cap) : nullptr;
       g.replay = opts->replay_log ? b.take<long long>((size_t)nch * opts->replay_cap) : nullptr;
       g.replay_n = opts->replay_log ? b.take<long long>(nch) : nullptr;
@@ -575,6 +579,7 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
   p.ph = (opts->flags & HFQMC_FLAG_PH_SYMMETRIC) ? 1 : 0;
   p.spin = spin ? 1 : 0;
   p.pg = plan.pg;
+  p.drift_every = r.drift_every;
 
   // ---- the device launch sequence: bath matrices, zeroed accumulators and
   // counters (fill kernels), the persistent sweep kernel, the chain reduction
@@ -599,7 +604,8 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
       if ((e = launch_zero(g.acc_d, (long long)nch * nbin, s)) != hipSuccess) break;
       if ((e = launch_zero_i64(g.acc_n, (long long)nch * nbin, s)) != hipSuccess) break;
       if ((e = launch_zero_i64(g.cstats, (long long)nch * NSTAT, s)) != hipSuccess) break;
-      e = launch_zero(g.cdrift, nch, s);
+      if ((e = launch_zero(g.cdrift, nch, s)) != hipSuccess) break;
+      e = launch_zero(g.cdrift_gt, nch, s);
       if (e == hipSuccess && !direct) e = launch_zero_i32(g.ref_sing, 4, s);
     }
     if (e == hipSuccess && !direct) e = launch_reference(p, ref_lds, ref_scratch, 0, s);
@@ -685,11 +691,11 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
                        : hipMemcpyAsync(dst, src, sizeof(double) * n, hipMemcpyDeviceToHost, st);
   };
   std::vector<long long> cst((size_t)nch * NSTAT);
-  std::vector<double> cdr(nch);
+  std::vector<double> cdr(nch), cdg(nch);
   int ref_bad = 0;
   std::vector<double> gcheck;
   long long goff = 0;
-  double max_drift = 0.0;
+  double max_drift = 0.0, max_drift_gt = 0.0;
   bool numeric_bad = false;
   hfqmc_stats tot;
   std::memset(&tot, 0, sizeof tot);
@@ -706,6 +712,7 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
     }
     HIPCHK(hipMemcpyAsync(cst.data(), g.cstats, sizeof(long long) * cst.size(), hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(cdr.data(), g.cdrift, sizeof(double) * nch, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(cdg.data(), g.cdrift_gt, sizeof(double) * nch, hipMemcpyDeviceToHost, st));
     int rs = 0;
     if (!direct) HIPCHK(hipMemcpyAsync(&rs, g.ref_sing, sizeof(int), hipMemcpyDeviceToHost, st));
     const size_t cb = (size_t)i * nch;
@@ -726,7 +733,7 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
     ref_bad |= rs;
     hfqmc_stats gs;
     std::memset(&gs, 0, sizeof gs);
-    double gdrift = 0.0;
+    double gdrift = 0.0, gdrift_gt = 0.0;
     for (int ch = 0; ch < nch; ++ch) {
       const long long* s = &cst[(size_t)ch * NSTAT];
       gs.n_proposed += s[ST_PROPOSED];
@@ -752,10 +759,13 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
       gs.chain_s_fold += s[ST_T_FOLD] * f;
       gdrift = std::max(gdrift, cdr[ch]);
       if (!(cdr[ch] == cdr[ch])) gdrift = INFINITY;
+      gdrift_gt = std::max(gdrift_gt, cdg[ch]);
+      if (!(cdg[ch] == cdg[ch])) gdrift_gt = INFINITY;
       if (opts->flip_count) opts->flip_count[cb + ch] = s[ST_FLIPS];
       if (opts->chain_drift) opts->chain_drift[cb + ch] = cdr[ch];
     }
     gs.max_drift = gdrift;
+    gs.max_drift_gtau = gdrift_gt;
     gs.acc_rate = gs.n_proposed ? (double)gs.n_accepted / gs.n_proposed : 0.0;
     gs.delay_k = r.delay_k;
     gs.recompute_every = r.n_rec;
@@ -787,6 +797,7 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
     tot.chain_s_window_apply += gs.chain_s_window_apply;
     tot.chain_s_fold += gs.chain_s_fold;
     max_drift = std::max(max_drift, gdrift);
+    max_drift_gt = std::max(max_drift_gt, gdrift_gt);
     const double* gv = call.dev_io ? gcheck.data() : g_tau + goff;
     for (int k = 0; k < (call.dev_io ? L + 1 : ng); ++k)
       if (!std::isfinite(gv[k])) numeric_bad = true;
@@ -798,6 +809,7 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
   const double wall =
       std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
   tot.max_drift = max_drift;
+  tot.max_drift_gtau = max_drift_gt;
   tot.acc_rate = tot.n_proposed ? (double)tot.n_accepted / tot.n_proposed : 0.0;
   tot.seconds_kernel = ms * 1e-3;
   tot.seconds_sweep_kernel = ms_k * 1e-3;
@@ -823,9 +835,11 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
   }
   if (ref_bad) return fail(HFQMC_ENUMERIC, "singular uniform-field reference matrix");
   if (tot.n_singular) return fail(HFQMC_ENUMERIC, "singular Dyson matrix in %lld recomputes", (long long)tot.n_singular);
-  if (numeric_bad || !(max_drift < INFINITY)) return fail(HFQMC_ENUMERIC, "non-finite Green function");
-  if (opts->drift_limit > 0 && max_drift > opts->drift_limit)
-    return fail(HFQMC_EDRIFT, "recompute drift %.3e exceeds limit %.3e", max_drift, opts->drift_limit);
+  if (numeric_bad || !(max_drift < INFINITY) || !(max_drift_gt < INFINITY))
+    return fail(HFQMC_ENUMERIC, "non-finite Green function");
+  if (opts->drift_limit > 0 && std::max(max_drift, max_drift_gt) > opts->drift_limit)
+    return fail(HFQMC_EDRIFT, "recompute drift %.3e (G(tau): %.3e) exceeds limit %.3e", max_drift,
+                max_drift_gt, opts->drift_limit);
   return HFQMC_OK;
 }
 

@@ -55,6 +55,7 @@ struct GridDev {
   long long* acc_n;       // [n_chains][n_bins] measurement counts
   long long* cstats;      // [n_chains][NSTAT]
   double* cdrift;         // [n_chains] max elementwise recompute drift
+  double* cdrift_gt;      // [n_chains] max drift of the G(tau) estimator at sampled recomputes
   long long* flip_log;    // [n_chains][flip_cap] or null
   const long long* replay;    // [n_chains][replay_cap] or null
   const long long* replay_n;  // [n_chains] or null
@@ -93,12 +94,15 @@ struct SweepParams {
   int ph;                 // 1: particle-hole symmetric bath, only G_up kept (G_dn = 1 - G_up^T)
   int spin;               // 1: spin-dependent baths (GridDev::spin)
   int pg;                 // 1: the LU panel lives in the workspace instead of LDS (large L)
+  int drift_every;        // the drift is taken on recompute 1, 1 + drift_every, ... of a chain
 };
 
 constexpr int kThreads = 512;   // threads per persistent workgroup (8 wave64)
 constexpr int kNBMax = 32;      // largest LU panel width
 constexpr int kMaxK = 64;       // largest delayed rank
 
+// Workspace doubles of the estimator kept across a sampled recompute (two per lag).
+constexpr long long gtd_doubles(int Lmax) { return (2LL * (Lmax + 1) + 63) & ~63LL; }
 // Workspace (doubles) needed per workgroup for chains of length up to Lmax.
 long long workspace_doubles(int Lmax, int kmax);
 // The LU panel's share of it, at its end ([Lmax + kNBMax][kNBMax + 2] doubles):

@@ -165,13 +165,16 @@ template <typename GT> struct GlobalOf;
 template <> struct GlobalOf<double> { typedef gdouble type; };
 template <> struct GlobalOf<float> { typedef gfloat type; };
 
-constexpr int kStatBytes = 256;   // LDS statistics block: NSTAT counters + drift
-static_assert(NSTAT * 8 + 8 <= kStatBytes, "statistics block too small");
+constexpr int kStatBytes = 256;   // LDS statistics block: NSTAT counters + two drifts
+static_assert(NSTAT * 8 + 16 <= kStatBytes, "statistics block too small");
 constexpr int kUW = 64;           // acceptance uniforms held in LDS at a time
 
 // Acceptance uniforms u(l, sweep) (stream 0) of slices l0 .. l0 + n - 1 into uw.
+// The leading barrier orders the stores after every wave's reads of the previous
+// block: a rejected proposal reaches no barrier of its own.
 __device__ __forceinline__ void fill_uniforms(double* uw, uint64_t key0, uint64_t grid, long long sw,
                                               int l0, int n) {
+  __syncthreads();
   if ((int)threadIdx.x < n)
     uw[threadIdx.x] = uniform53(key0, grid, (uint64_t)(l0 + threadIdx.x), (uint64_t)sw, 0ull);
   __syncthreads();
@@ -199,6 +202,8 @@ struct Chain {
   double* red;     // reduction scratch, LDS
   long long* st;   // per-chain statistics [NSTAT] (ST_*), LDS, written by thread 0 only
   double* drift;   // largest recompute drift so far, LDS, thread 0 only
+  double* drift_gt;  // largest drift of the G(tau) estimator so far, LDS, thread 0 only
+  double* gtd;     // workspace [2 (Lmax + 1)]: the estimator before a sampled recompute
   int* sr;         // LDS [L] at the start of the scratch during a reduced solve: S, then R
   const double* refQ[2];
   const double* refH[2];
@@ -218,11 +223,11 @@ struct Counters {
 };
 
 // The drift (updated G against its recompute) is sampled on the first and
-// every kDriftEvery-th recompute of a chain.  Before the others the pending
-// flips are not flushed: the recompute replaces G by the exact G of the field,
-// which already holds those flips, so the chain is unchanged.
-constexpr int kDriftEvery = 8;
-__device__ __forceinline__ bool drift_sampled(int j) { return (j - 1) % kDriftEvery == 0; }
+// every `every`-th recompute of a chain (SweepParams::drift_every, 8 unless the
+// caller asks otherwise; 1 samples all).  Before the others the pending flips
+// are not flushed: the recompute replaces G by the exact G of the field, which
+// already holds those flips, so the chain is unchanged.
+__device__ __forceinline__ bool drift_sampled(int j, int every) { return (j - 1) % every == 0; }
 
 // Adds v to statistic `which` (thread 0 keeps the LDS copy).
 __device__ __forceinline__ void stat_add(long long* st, int which, long long v) {
@@ -1351,6 +1356,53 @@ __device__ __forceinline__ double dyson_solve(const Chain& ch, int sigma, GT* Gs
 // spin-down sum over i becomes, with j = (i - k) mod L,
 //   sum_i sgn G_dn(i, j) = L delta_k0 - sum_j sgn' G_up(j, (j + k) mod L),
 // sgn' = -1 where j + k wraps: again one contiguous stretch of a row per step.
+// Sums of the estimator at lag k over the rows: up = sum_i sgn G_up(i, i - k),
+// dn the same for G_dn (from G_up's transposed diagonals when only G_up is
+// stored, see above).
+template <typename GT>
+__device__ __forceinline__ void lag_sums(const GT* __restrict__ Gup, const GT* __restrict__ Gdn,
+                                         int L, int k, bool ph, double& up_, double& dn_) {
+  // step i: every thread of a wave reads row i (one contiguous stretch):
+  // G(i, i - k), with sign - where i - k wraps
+  double up = 0.0, dn = 0.0;
+  if (!ph) {
+#pragma unroll 16
+    for (int i = 0; i < L; ++i) {
+      int j = i - k;
+      double sg = 1.0;
+      if (j < 0) {
+        j += L;
+        sg = -1.0;
+      }
+      const long long o = (long long)i * L + j;
+      up += sg * Gup[o];
+      dn += sg * Gdn[o];
+    }
+  } else {
+    // and G_up(i, i + k), with sign - where i + k wraps, for the spin-down term
+    double tr = 0.0;
+#pragma unroll 16
+    for (int i = 0; i < L; ++i) {
+      int j = i - k, j2 = i + k;
+      double sg = 1.0, sg2 = 1.0;
+      if (j < 0) {
+        j += L;
+        sg = -1.0;
+      }
+      if (j2 >= L) {
+        j2 -= L;
+        sg2 = -1.0;
+      }
+      const GT* row = Gup + (long long)i * L;
+      up += sg * row[j];
+      tr += sg2 * row[j2];
+    }
+    dn = (k == 0 ? (double)L : 0.0) - tr;
+  }
+  up_ = up;
+  dn_ = dn;
+}
+
 template <typename GT, bool SPIN = false>
 __device__ __forceinline__ void measure(const Chain& ch, int bin, bool ph) {
   const int L = ch.L;
@@ -1358,43 +1410,8 @@ __device__ __forceinline__ void measure(const Chain& ch, int bin, bool ph) {
   const GT* Gup = reinterpret_cast<const GT*>(ch.Gu);
   const GT* Gdn = reinterpret_cast<const GT*>(ch.Gd);
   for (int k = threadIdx.x; k < L; k += kThreads) {
-    // step i: every thread of a wave reads row i (one contiguous stretch):
-    // G(i, i - k), with sign - where i - k wraps
-    double up = 0.0, dn = 0.0;
-    if (!ph) {
-#pragma unroll 16
-      for (int i = 0; i < L; ++i) {
-        int j = i - k;
-        double sg = 1.0;
-        if (j < 0) {
-          j += L;
-          sg = -1.0;
-        }
-        const long long o = (long long)i * L + j;
-        up += sg * Gup[o];
-        dn += sg * Gdn[o];
-      }
-    } else {
-      // and G_up(i, i + k), with sign - where i + k wraps, for the spin-down term
-      double tr = 0.0;
-#pragma unroll 16
-      for (int i = 0; i < L; ++i) {
-        int j = i - k, j2 = i + k;
-        double sg = 1.0, sg2 = 1.0;
-        if (j < 0) {
-          j += L;
-          sg = -1.0;
-        }
-        if (j2 >= L) {
-          j2 -= L;
-          sg2 = -1.0;
-        }
-        const GT* row = Gup + (long long)i * L;
-        up += sg * row[j];
-        tr += sg2 * row[j2];
-      }
-      dn = (k == 0 ? (double)L : 0.0) - tr;
-    }
+    double up, dn;
+    lag_sums<GT>(Gup, Gdn, L, k, ph, up, dn);
     if constexpr (SPIN) {
       // spin-resolved: [bin][up, down][L+1], G_sigma(beta-) = 1 - G_sigma(0+)
       const long long base = (long long)bin * 2 * (L + 1);
@@ -1422,6 +1439,36 @@ __device__ __forceinline__ void measure(const Chain& ch, int bin, bool ph) {
     ch.accd[bin] += dsum / L;
     ch.accn[bin] += 1;
   }
+}
+
+// Drift of the G(tau) estimator at a sampled recompute: the estimator of the
+// updated G is kept (snapshot, each thread its own lags in the workspace)
+// and, after the recompute, compared with the estimator of the recomputed G;
+// returns the largest change over the lags (every thread gets it).  The
+// spin-averaged estimator of measure(), or both spin-resolved ones for
+// spin-dependent baths.
+template <typename GT, bool SPIN = false>
+__device__ __forceinline__ double estimator_drift(const Chain& ch, bool ph, bool snapshot) {
+  const int L = ch.L;
+  const GT* Gup = reinterpret_cast<const GT*>(ch.Gu);
+  const GT* Gdn = reinterpret_cast<const GT*>(ch.Gd);
+  gdouble* __restrict__ keep = (gdouble*)ch.gtd;
+  double dm = 0.0;
+  for (int k = threadIdx.x; k < L; k += kThreads) {
+    double up, dn;
+    lag_sums<GT>(Gup, Gdn, L, k, ph, up, dn);
+    const double a = SPIN ? up / L : (up + dn) / (2.0 * L);
+    const double b = SPIN ? dn / L : 0.0;
+    if (snapshot) {
+      keep[2 * k] = a;
+      keep[2 * k + 1] = b;
+    } else {
+      dm = fmax(dm, fmax(fabs(a - keep[2 * k]), fabs(b - keep[2 * k + 1])));
+      if (!(fabs(a) < INFINITY && fabs(b) < INFINITY)) dm = INFINITY;
+    }
+  }
+  if (snapshot) return 0.0;
+  return block_max(dm, ch.red);
 }
 
 // ---------------------------------------------------------- proposals ----
@@ -1490,16 +1537,20 @@ __device__ __forceinline__ void recompute_both(const SweepParams& p, const Chain
   const long long t0 = wall_clock64();
   double d = 0.0;
   const int nsp = p.ph ? 1 : 2;
+  const bool samp = counted && drift_sampled(k.n_rec + 1, p.drift_every);
+  if (samp) (void)estimator_drift<GT, SPIN>(ch, p.ph != 0, true);
 #pragma unroll 1
   for (int sp = 0; sp < nsp; ++sp)
     d = fmax(d, dyson_solve<GT, SPIN, PG>(ch, sp ? -1 : +1,
                                           reinterpret_cast<GT*>(sp ? ch.Gd : ch.Gu), ch.lu_nb,
-                                          ch.reduced, false, counted && drift_sampled(k.n_rec + 1)));
+                                          ch.reduced, false, samp));
+  const double dg = samp ? estimator_drift<GT, SPIN>(ch, p.ph != 0, false) : 0.0;
   if (counted) {
     k.n_rec += 1;
     if (threadIdx.x == 0) {
       // (a non-finite G is reported whether or not the drift is sampled)
-      if (drift_sampled(k.n_rec) || !(d < INFINITY)) *ch.drift = fmax(*ch.drift, d);
+      if (samp || !(d < INFINITY)) *ch.drift = fmax(*ch.drift, d);
+      if (samp) *ch.drift_gt = fmax(*ch.drift_gt, dg);
       ch.st[ST_RECOMPUTES] += 1;
     }
   }
@@ -2269,7 +2320,7 @@ __device__ __forceinline__ int sweep_window(const SweepParams& p, const Chain& c
       if (t == 0) ch.st[ST_T_FLUSH] += wall_clock64() - t0;
     }
     // a recompute that does not sample the drift needs no flush before it
-    if (m > 0 && k.acc_since == p.n_rec && !drift_sampled(k.n_rec + 1)) {
+    if (m > 0 && k.acc_since == p.n_rec && !drift_sampled(k.n_rec + 1, p.drift_every)) {
       m = 0;
       m_inv = 0;
     }
@@ -2322,7 +2373,8 @@ __device__ __forceinline__ void setup_chain(Chain& ch, const SweepParams& p, con
     // U11^{-1} blocks
     const long long lp = L + kNBMax;
     ch.Ui = ch.A + 2 * lp * lp;
-    ch.wbuf = ch.Ui + lp * kNBMax;
+    ch.gtd = ch.Ui + lp * kNBMax;
+    ch.wbuf = ch.gtd + gtd_doubles(p.Lmax);
   }
   ch.grid = gd->grid_id;
   ch.s = reinterpret_cast<int8_t*>(lds);
@@ -2331,6 +2383,7 @@ __device__ __forceinline__ void setup_chain(Chain& ch, const SweepParams& p, con
   ch.red = ch.uw + kUW;
   ch.st = reinterpret_cast<long long*>(ch.red + 64);
   ch.drift = reinterpret_cast<double*>(ch.st + NSTAT);
+  ch.drift_gt = ch.drift + 1;
   ch.scratch = reinterpret_cast<char*>(ch.red + 64) + kStatBytes;
   ch.sr = reinterpret_cast<int*>(ch.scratch);
   ch.scratch_bytes = scratch_bytes;
@@ -2371,7 +2424,10 @@ __device__ __forceinline__ void run_chain(const SweepParams& p, const GridDev* g
   __syncthreads();
 
   if (threadIdx.x < NSTAT) ch.st[threadIdx.x] = 0;
-  if (threadIdx.x == 0) *ch.drift = 0.0;
+  if (threadIdx.x == 0) {
+    *ch.drift = 0.0;
+    *ch.drift_gt = 0.0;
+  }
   __syncthreads();
   Counters k = {0, 0, 0};
 
@@ -2434,6 +2490,7 @@ __device__ __forceinline__ void run_chain(const SweepParams& p, const GridDev* g
     ch.st[ST_REPLAYED] = k.rep_i;
     for (int q = 0; q < NSTAT; ++q) st[q] = ch.st[q];
     gd->cdrift[chain] = *ch.drift;
+    gd->cdrift_gt[chain] = *ch.drift_gt;
   }
   if (gd->g_final) {
     double* out = gd->g_final + (long long)chain * 2 * L2;
@@ -2540,7 +2597,7 @@ __global__ void k_reduce(const GridDev* grids, int n_bins) {
 long long workspace_doubles(int Lmax, int kmax) {
   const long long L2 = (long long)Lmax * Lmax;
   const long long Lp = Lmax + kNBMax;  // LU padding
-  long long w = 2 * L2 + 2 * Lp * Lp + Lp * kNBMax + 256;
+  long long w = 2 * L2 + 2 * Lp * Lp + Lp * kNBMax + gtd_doubles(Lmax) + 256;
   if (kmax > 1) w += 4LL * kMaxK * kWin + 4LL * Lmax * kMaxK;
   w += panel_doubles(Lmax);   // last: the LU panel when it leaves LDS
   return (w + 63) & ~63LL;
