@@ -69,10 +69,11 @@ enum {
 
 /* Option bits (hfqmc_opts.flags). */
 enum {
-  HFQMC_FLAG_EAGER = 1,      /* launch the set-up kernels (bath matrices, fills, references)
-                                one by one instead of replaying them as a captured HIP graph
-                                (results are identical); the sweep kernel and the chain
-                                reduction follow as two launches either way */
+  HFQMC_FLAG_EAGER = 1,      /* launch the kernels one by one instead of replaying the
+                                launch sequence (set-up kernels: bath matrices, fills,
+                                references; the persistent sweep kernel between its two
+                                timing events; the chain reduction) as one captured HIP
+                                graph; the results are identical */
   HFQMC_FLAG_HEAT_BATH = 2,  /* heat-bath acceptance u < R/(1+R) instead of Metropolis u < R */
   HFQMC_FLAG_DIRECT_RECOMPUTE = 4, /* recompute with the full L x L LU of [M | G0] instead of the
                                       reduced system against the uniform-field references */
@@ -146,7 +147,10 @@ typedef struct {
   int32_t recompute_every;  /* recompute interval actually used */
   int32_t n_workgroups;     /* persistent workgroups launched */
   int32_t lu_panel;         /* LU panel width of the recompute */
-  int32_t graph;            /* 1 if the set-up launches ran as a captured HIP graph */
+  int32_t graph;            /* 0: eager launches; 1: the whole launch sequence ran as one HIP
+                               graph (the sweep kernel between two event-record nodes);
+                               2: only the set-up launches were a graph (the runtime refused
+                               the event nodes), the sweep kernel and reduction followed it */
   int32_t autotuned;        /* 1 if k and the panel width came from the autotuner */
   double seconds_autotune;  /* time spent in trial launches during this call (0 on a cache hit) */
   int64_t n_reduced_rows;   /* sum over reduced-form recomputes of the system size |S| */

@@ -87,6 +87,7 @@ struct TuneChoice {
 struct GraphEntry {
   std::vector<unsigned long long> key;
   hipGraphExec_t exec = nullptr;
+  bool whole = false;   // set-up, sweep kernel and reduction; else the set-up only
 };
 
 struct hfqmc_ctx {
@@ -219,6 +220,32 @@ struct GridHost {
   int L;
   double lam;
 };
+
+// Adds per-chain counters (ST_* order) to the statistics, the phase clocks
+// converted from device wall-clock ticks to seconds.
+void add_counters(const long long* s, double wall_hz, hfqmc_stats* gs) {
+  gs->n_proposed += s[ST_PROPOSED];
+  gs->n_accepted += s[ST_ACCEPTED];
+  gs->n_recomputes += s[ST_RECOMPUTES];
+  gs->n_bad_ratio += s[ST_BAD];
+  gs->n_singular += s[ST_SINGULAR];
+  gs->n_flushes += s[ST_FLUSHES];
+  const double f = 1.0 / wall_hz;
+  gs->chain_s_sweep += s[ST_T_SWEEP] * f;
+  gs->chain_s_flush += s[ST_T_FLUSH] * f;
+  gs->chain_s_recompute += s[ST_T_REC] * f;
+  gs->chain_s_measure += s[ST_T_MEAS] * f;
+  gs->chain_s_lu_build += s[ST_T_LU_BUILD] * f;
+  gs->chain_s_lu_panel += s[ST_T_LU_PANEL] * f;
+  gs->chain_s_lu_strip += s[ST_T_LU_STRIP] * f;
+  gs->chain_s_lu_back += s[ST_T_LU_BACK] * f;
+  gs->n_reduced_rows += s[ST_RED_ROWS];
+  gs->chain_s_lu_gemm += s[ST_T_LU_GEMM] * f;
+  gs->chain_s_flush_vectors += s[ST_T_FL_VEC] * f;
+  gs->chain_s_flush_gemm += s[ST_T_FL_GEMM] * f;
+  gs->chain_s_window_apply += s[ST_T_WAPPLY] * f;
+  gs->chain_s_fold += s[ST_T_FOLD] * f;
+}
 
 // How a solve is called: host or device buffers, a cap on the LU panel width
 // (autotuner trials), and whether it is a trial launch of the autotuner.
@@ -585,10 +612,10 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
   // counters (fill kernels), the persistent sweep kernel, the chain reduction
   HIPCHK(prepare_sweeps(lds));
   if (!direct) HIPCHK(prepare_reference(ref_lds));
-  // The launch sequence in two parts: the set-up (bath matrices, zeroed
-  // accumulators and counters, uniform-field references: many small launches,
-  // replayed as one captured graph unless eager), then the persistent sweep
-  // kernel between two events (its own time) and the chain reduction.
+  // The launch sequence: the set-up (bath matrices, zeroed accumulators and
+  // counters, uniform-field references: many small launches), then the
+  // persistent sweep kernel between two events (its own time) and the chain
+  // reduction; captured once as a HIP graph and replayed unless eager.
   auto enqueue = [&](hipStream_t s) -> hipError_t {
     hipError_t e = hipSuccess;
     for (int i = 0; i < n_grids && e == hipSuccess; ++i) {
@@ -621,6 +648,7 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
     return e;
   };
   const bool use_graph = !(opts->flags & HFQMC_FLAG_EAGER);
+  bool whole = false;   // the graph holds the whole sequence, not only the set-up
   if (use_graph) {
     // key: everything the captured kernels' arguments depend on
     std::vector<unsigned long long> key;
@@ -638,20 +666,66 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
     for (size_t q = 0; q < c->graphs.size(); ++q) {
       if (c->graphs[q].key == key) {
         exec = c->graphs[q].exec;
+        whole = c->graphs[q].whole;
         std::rotate(c->graphs.begin(), c->graphs.begin() + q, c->graphs.begin() + q + 1);
         break;
       }
     }
     if (!exec) {
-      hipGraph_t graph = nullptr;
-      HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-      const hipError_t e = enqueue(c->cap_stream);
-      const hipError_t e2 = hipStreamEndCapture(c->cap_stream, &graph);
-      if (e != hipSuccess || e2 != hipSuccess) {
-        if (graph) (void)hipGraphDestroy(graph);
-        return fail(HFQMC_EDEVICE, "capturing the launch sequence: %s",
-                    hipGetErrorString(e != hipSuccess ? e : e2));
+      // three captures (set-up; the sweep kernel; the reduction) joined into one
+      // graph: set-up -> event ev_k0 -> sweep kernel -> event ev_k1 -> reduction.
+      // The events are explicit event-record nodes (a record under stream
+      // capture only orders the capture).  If the runtime refuses them, the
+      // graph holds the set-up only and the rest is launched after it.
+      auto capture = [&](int part, hipGraph_t* out) -> hipError_t {
+        *out = nullptr;
+        hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return e;
+        if (part == 0) e = enqueue(c->cap_stream);
+        else if (part == 1) e = launch_sweeps(p, n_wg, lds, c->cap_stream);
+        else e = launch_reduce(d_grids, n_grids, nbin, c->cap_stream);
+        const hipError_t e2 = hipStreamEndCapture(c->cap_stream, out);
+        if (e == hipSuccess) e = e2;
+        if (e != hipSuccess && *out) {
+          (void)hipGraphDestroy(*out);
+          *out = nullptr;
+        }
+        return e;
+      };
+      hipGraph_t graph = nullptr, gsw = nullptr, gred = nullptr;
+      hipError_t e = capture(0, &graph);
+      if (e != hipSuccess)
+        return fail(HFQMC_EDEVICE, "capturing the set-up launches: %s", hipGetErrorString(e));
+      if (capture(1, &gsw) == hipSuccess && capture(2, &gred) == hipSuccess) {
+        // the set-up's leaves: nodes that no edge leaves from
+        size_t nn = 0, ne = 0;
+        bool ok = hipGraphGetNodes(graph, nullptr, &nn) == hipSuccess &&
+                  hipGraphGetEdges(graph, nullptr, nullptr, &ne) == hipSuccess;
+        std::vector<hipGraphNode_t> nodes(nn), from(ne), to(ne), leaves;
+        ok = ok && hipGraphGetNodes(graph, nodes.data(), &nn) == hipSuccess &&
+             (ne == 0 || hipGraphGetEdges(graph, from.data(), to.data(), &ne) == hipSuccess);
+        if (ok)
+          for (hipGraphNode_t n : nodes)
+            if (std::find(from.begin(), from.end(), n) == from.end()) leaves.push_back(n);
+        hipGraphNode_t n0 = nullptr, nk = nullptr, n1 = nullptr, nr = nullptr;
+        ok = ok && !leaves.empty() &&
+             hipGraphAddEventRecordNode(&n0, graph, leaves.data(), leaves.size(), c->ev_k0) == hipSuccess &&
+             hipGraphAddChildGraphNode(&nk, graph, &n0, 1, gsw) == hipSuccess &&
+             hipGraphAddEventRecordNode(&n1, graph, &nk, 1, c->ev_k1) == hipSuccess &&
+             hipGraphAddChildGraphNode(&nr, graph, &n1, 1, gred) == hipSuccess;
+        if (ok) {
+          whole = true;
+        } else {
+          // start again from a clean set-up graph
+          (void)hipGraphDestroy(graph);
+          e = capture(0, &graph);
+          if (e != hipSuccess)
+            return fail(HFQMC_EDEVICE, "capturing the set-up launches: %s", hipGetErrorString(e));
+        }
       }
+      (void)hipGetLastError();   // a refused node leaves no sticky state behind
+      if (gsw) (void)hipGraphDestroy(gsw);
+      if (gred) (void)hipGraphDestroy(gred);
       const hipError_t e3 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
       (void)hipGraphDestroy(graph);
       if (e3 != hipSuccess) return fail(HFQMC_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e3));
@@ -662,12 +736,13 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
       GraphEntry ge;
       ge.key = key;
       ge.exec = exec;
+      ge.whole = whole;
       c->graphs.insert(c->graphs.begin(), ge);
     }
     HIPCHK(hipEventRecord(c->ev0, st));
     {
       hipError_t e = hipGraphLaunch(exec, st);
-      if (e == hipSuccess) e = enqueue_sweeps(st);
+      if (e == hipSuccess && !whole) e = enqueue_sweeps(st);
       if (e != hipSuccess)
         return fail(HFQMC_EDEVICE, "graph launch (%d workgroups, %d B LDS): %s", n_wg, lds,
                     hipGetErrorString(e));
@@ -736,27 +811,7 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
     double gdrift = 0.0, gdrift_gt = 0.0;
     for (int ch = 0; ch < nch; ++ch) {
       const long long* s = &cst[(size_t)ch * NSTAT];
-      gs.n_proposed += s[ST_PROPOSED];
-      gs.n_accepted += s[ST_ACCEPTED];
-      gs.n_recomputes += s[ST_RECOMPUTES];
-      gs.n_bad_ratio += s[ST_BAD];
-      gs.n_singular += s[ST_SINGULAR];
-      gs.n_flushes += s[ST_FLUSHES];
-      const double f = 1.0 / c->wall_hz;
-      gs.chain_s_sweep += s[ST_T_SWEEP] * f;
-      gs.chain_s_flush += s[ST_T_FLUSH] * f;
-      gs.chain_s_recompute += s[ST_T_REC] * f;
-      gs.chain_s_measure += s[ST_T_MEAS] * f;
-      gs.chain_s_lu_build += s[ST_T_LU_BUILD] * f;
-      gs.chain_s_lu_panel += s[ST_T_LU_PANEL] * f;
-      gs.chain_s_lu_strip += s[ST_T_LU_STRIP] * f;
-      gs.chain_s_lu_back += s[ST_T_LU_BACK] * f;
-      gs.n_reduced_rows += s[ST_RED_ROWS];
-      gs.chain_s_lu_gemm += s[ST_T_LU_GEMM] * f;
-      gs.chain_s_flush_vectors += s[ST_T_FL_VEC] * f;
-      gs.chain_s_flush_gemm += s[ST_T_FL_GEMM] * f;
-      gs.chain_s_window_apply += s[ST_T_WAPPLY] * f;
-      gs.chain_s_fold += s[ST_T_FOLD] * f;
+      add_counters(s, c->wall_hz, &gs);
       gdrift = std::max(gdrift, cdr[ch]);
       if (!(cdr[ch] == cdr[ch])) gdrift = INFINITY;
       gdrift_gt = std::max(gdrift_gt, cdg[ch]);
@@ -771,7 +826,7 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
     gs.recompute_every = r.n_rec;
     gs.n_workgroups = n_wg;
     gs.lu_panel = lu_nb;
-    gs.graph = use_graph ? 1 : 0;
+    gs.graph = use_graph ? (whole ? 1 : 2) : 0;
     gs.autotuned = tuned ? 1 : 0;
     gs.seconds_autotune = t_tune;
     gs.recompute_reduced = direct ? 0 : 1;
@@ -818,7 +873,7 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
   tot.recompute_every = r.n_rec;
   tot.n_workgroups = n_wg;
   tot.lu_panel = lu_nb;
-  tot.graph = use_graph ? 1 : 0;
+  tot.graph = use_graph ? (whole ? 1 : 2) : 0;
   tot.autotuned = tuned ? 1 : 0;
   tot.seconds_autotune = t_tune;
   tot.recompute_reduced = direct ? 0 : 1;

@@ -57,7 +57,7 @@ def test_graph_replays_equal_eager(ctx, mode, k):
         assert out["stats"]["graph"] == 1
         _same(out, ref)
         _eager_work()
-    # the sweep kernel's own events (recorded inside the graph and eagerly)
+    # the sweep kernel's own events (event-record nodes of the graph, or eager records)
     for st in (ref["stats"], out["stats"]):
         assert 0.0 < st["seconds_sweep_kernel"] <= st["seconds_kernel"]
 
