@@ -201,6 +201,30 @@ int hfqmc_solve_dev(hfqmc_ctx *ctx, const double *g0_tau, int32_t L, double U, d
                     double dtau, uint64_t seed, const hfqmc_opts *opts,
                     double *g_tau, double *g_err, double *docc, hfqmc_stats *stats);
 
+/* hfqmc_solve_dev that allocates nothing, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments, semantics and results (bit for bit the
+ * same kernels), but no device or host allocation.  Everything besides the
+ * caller's inputs and outputs lives in one static device buffer of 128 MiB
+ * per GPU, held by the library's code object from the first use of the
+ * device until the process ends: the grid data (bath matrix, uniform-field
+ * references, accumulators, counters) first, then as many per-workgroup
+ * workspaces as fit, which sets the number of workgroups (about 18 at
+ * L = 400 in the delayed modes, all chains at once for short grids).
+ * Limits: one grid; L up to about 880 (the reference solves need four
+ * workspaces), fewer with many chains; EINVAL names the sizes when a call
+ * exceeds the buffer.  delay_k must be given in the delayed modes (EINVAL for
+ * 0: the autotuner's trial launches allocate); the test hooks of hfqmc_opts
+ * (flip_log, replay_log, chain_*, final_green) give EINVAL; the set-up
+ * kernels run eagerly (HFQMC_FLAG_EAGER is implied).  Every call on a GPU
+ * shares that GPU's buffer and clears what it reads before use: calls that
+ * overlap on one GPU (another thread, another context, another stream) race
+ * and give undefined results.  EDEVICE if the buffer could not be located
+ * when the context was created. */
+int hfqmc_solve_dev_noalloc(hfqmc_ctx *ctx, const double *g0_tau, int32_t L, double U, double beta,
+                            double dtau, uint64_t seed, const hfqmc_opts *opts,
+                            double *g_tau, double *g_err, double *docc, hfqmc_stats *stats);
+
 /* hfqmc_solve with spin-dependent baths (a magnetic field, magnetic phases;
  * the paper's closing remarks on the method's generality): spin up sees the
  * bath g0_up[L], spin down g0_dn[L], both G0_sigma(k dtau) in the positive

@@ -6,5 +6,5 @@ declared in include/hfqmc.h); this package is its thin Python binding.
 from .api import (Context, HFQMCError, bath_to_tau, bethe_atomic_bath,  # noqa: F401
                   bethe_semicircle_bath,
                   dmft_bethe_step, dmft_solve, dmft_solve_af, hfqmc_measure_peaks, hfqmc_solve,
-                  hfqmc_solve_dev, hfqmc_solve_grids, hfqmc_solve_spin,
+                  hfqmc_solve_dev, hfqmc_solve_dev_noalloc, hfqmc_solve_grids, hfqmc_solve_spin,
                   multigrid_solve, multigrid_solve_spin)

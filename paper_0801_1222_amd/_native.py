@@ -92,6 +92,8 @@ lib.dmft_solve_af.restype = C.c_int
 lib.hfqmc_solve_dev.argtypes = [_ctx_p, C.c_void_p, _i32, _f64, _f64, _f64, _u64, C.POINTER(Opts),
                                 C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(Stats)]
 lib.hfqmc_solve_dev.restype = C.c_int
+lib.hfqmc_solve_dev_noalloc.argtypes = lib.hfqmc_solve_dev.argtypes
+lib.hfqmc_solve_dev_noalloc.restype = C.c_int
 lib.hfqmc_solve_grids.argtypes = [_ctx_p, _i32, _pi32, _pd, _f64, _f64, _u64, C.POINTER(Opts),
                                   _pd, _pd, _pd, C.POINTER(Stats)]
 lib.hfqmc_solve_grids.restype = C.c_int
@@ -121,7 +123,7 @@ FLAG_G_FP32 = 16           # mixed mode: G stored in FP32 between recomputes
 EXPORTED = ["hfqmc_create", "hfqmc_destroy", "hfqmc_set_stream", "hfqmc_last_error",
             "hfqmc_solve", "hfqmc_solve_spin", "hfqmc_solve_dev", "hfqmc_solve_grids", "multigrid_solve", "dmft_bethe_step",
             "bethe_semicircle_bath", "bethe_atomic_bath", "bath_to_tau", "hfqmc_measure_peaks", "dmft_solve",
-            "multigrid_solve_spin", "dmft_solve_af"]
+            "multigrid_solve_spin", "dmft_solve_af", "hfqmc_solve_dev_noalloc"]
 
 
 def ptr(a, ctype=C.c_double):

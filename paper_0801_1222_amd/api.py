@@ -234,6 +234,24 @@ def hfqmc_solve_dev(ctx, g0_tau, L, U, beta, dtau, seed, g_tau, g_err=None, docc
     return st.as_dict()
 
 
+def hfqmc_solve_dev_noalloc(ctx, g0_tau, L, U, beta, dtau, seed, g_tau, g_err=None, docc=None,
+                            n_chains=1, warmup=0, sweeps=1, mode="rank1", recompute_every=0,
+                            delay_k=0, n_bins=0, drift_limit=0.0, drift_every=0, heat_bath=False,
+                            direct=False, ph=False, g_fp32=False):
+    """hfqmc_solve_dev without any allocation (the library's static per-device
+    buffer; see include/hfqmc.h for its limits); returns the stats."""
+    o = _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drift_limit,
+              _flags(True, heat_bath, direct, ph, g_fp32), drift_every=drift_every)
+    st = N.Stats()
+    rc = N.lib.hfqmc_solve_dev_noalloc(ctx.handle, C.c_void_p(int(g0_tau)), int(L), float(U),
+                                       float(beta), float(dtau), int(seed), C.byref(o),
+                                       C.c_void_p(int(g_tau)),
+                                       C.c_void_p(int(g_err) if g_err else None),
+                                       C.c_void_p(int(docc) if docc else None), C.byref(st))
+    N.check(rc, "hfqmc_solve_dev_noalloc")
+    return st.as_dict()
+
+
 def hfqmc_measure_peaks(ctx):
     """Achievable HBM bandwidth (GB/s) and matrix-core / FMA rates (TFLOP/s)
     of the context's device, from the library's probe kernels."""

@@ -11,7 +11,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libhfqmc.so")
 
-SOURCES = ["hfqmc_kernels.hip", "hfqmc_peaks.hip", "hfqmc_api.cpp", "hfqmc_host.cpp"]
+SOURCES = ["hfqmc_kernels.hip", "hfqmc_peaks.hip", "hfqmc_noalloc.hip", "hfqmc_api.cpp",
+           "hfqmc_host.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -103,6 +103,8 @@ struct hfqmc_ctx {
   hipEvent_t ev_k0 = nullptr, ev_k1 = nullptr;  // around the sweep kernel (recorded inside graphs too)
   std::map<std::vector<int>, TuneChoice> tune;  // key: mode, chains, L_0, L_1, ...
   std::vector<GraphEntry> graphs;                // most recent first, at most kGraphCache
+  void* na_scratch = nullptr;    // this device's allocation-free buffer (hfqmc_noalloc.hip)
+  hipError_t na_status = hipSuccess;
 };
 
 namespace {
@@ -139,6 +141,9 @@ extern "C" int hfqmc_create(hfqmc_ctx** out, int device) {
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && khz > 0)
       c->wall_hz = khz * 1e3;
   }
+  // the allocation-free entry point's buffer on this device (looked up once per
+  // device; a failure is reported by that entry point only)
+  c->na_status = noalloc_scratch_lookup(device, &c->na_scratch);
   if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess ||
       hipEventCreate(&c->ev_k0) != hipSuccess || hipEventCreate(&c->ev_k1) != hipSuccess ||
       hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
@@ -931,6 +936,241 @@ extern "C" int hfqmc_solve_dev(hfqmc_ctx* c, const double* g0_tau, int32_t L, do
   Call call;
   call.dev_io = true;
   return solve_grids_impl(c, 1, Ls, g0_tau, U, beta, seed, opts, g_tau, g_err, docc, stats, call);
+}
+
+// hfqmc_solve_dev without any allocation: every buffer besides the caller's
+// inputs and outputs lives in this device's static buffer of kNoAllocBytes (the
+// grid data first, then as many per-workgroup workspaces as fit), the grid
+// record and the dispatch order are written by kernels, the statistics are
+// summed on the device and read back as one record, and the set-up kernels run
+// eagerly (no graph is instantiated).  The same kernels as hfqmc_solve_dev, so
+// the results are the same bit for bit.
+extern "C" int hfqmc_solve_dev_noalloc(hfqmc_ctx* c, const double* g0_tau, int32_t L, double U,
+                                       double beta, double dtau, uint64_t seed,
+                                       const hfqmc_opts* opts, double* g_tau, double* g_err,
+                                       double* docc, hfqmc_stats* stats) {
+  const auto t_start = std::chrono::steady_clock::now();
+  if (!c) return fail(HFQMC_EINVAL, "hfqmc_solve_dev_noalloc: ctx is NULL");
+  if (!g0_tau || !g_tau) return fail(HFQMC_EINVAL, "hfqmc_solve_dev_noalloc: null input/output pointer");
+  if (!(dtau > 0.0) || !(beta > 0.0) || !std::isfinite(beta))
+    return fail(HFQMC_EINVAL, "dtau=%g beta=%g", dtau, beta);
+  if (L < 2 || L > 4096) return fail(HFQMC_EINVAL, "L=%d (2..4096)", L);
+  if (std::fabs(beta / dtau - L) > 1e-9 * L) return fail(HFQMC_EINVAL, "beta/dtau=%.12g != L=%d", beta / dtau, L);
+  if (!(U >= 0.0) || !std::isfinite(U)) return fail(HFQMC_EINVAL, "U=%g", U);
+  Resolved r;
+  int rc = resolve_opts(opts, &r);
+  if (rc) return rc;
+  if (opts->flip_log || opts->replay_log || opts->chain_g || opts->chain_d || opts->chain_n ||
+      opts->chain_drift || opts->final_green)
+    return fail(HFQMC_EINVAL, "hfqmc_solve_dev_noalloc: the test hooks are not available here "
+                "(their device copies would need allocations)");
+  if (r.mode != MODE_RANK1 && r.delay_k == 0)
+    return fail(HFQMC_EINVAL, "hfqmc_solve_dev_noalloc: delay_k must be given in the delayed "
+                "modes (the autotuner's trial launches allocate)");
+  if (!c->na_scratch)
+    return fail(HFQMC_EDEVICE, "hfqmc_solve_dev_noalloc: no allocation-free buffer on device %d: %s",
+                c->device, hipGetErrorString(c->na_status));
+  HIPCHK(hipSetDevice(c->device));
+  hipStream_t st = c->stream;
+  const int nch = r.n_chains, nbin = r.n_bins;
+  const int direct = (opts->flags & HFQMC_FLAG_DIRECT_RECOMPUTE) ? 1 : 0;
+
+  // ---- launch shape (as plan_lu for one grid) and the reference solves' LDS
+  int nb = 0, sc = 0, pg = 0;
+  int lds = lds_bytes(L, L, r.mode, 0, direct, &nb, &sc, 0);
+  if (nb < 16 && !direct && !(opts->flags & HFQMC_FLAG_G_FP32)) {
+    int nb1 = 0, sc1 = 0;
+    const int l1 = lds_bytes(L, L, r.mode, 0, direct, &nb1, &sc1, 1);
+    if (nb1 >= 16) {
+      nb = nb1;
+      sc = sc1;
+      lds = l1;
+      pg = 1;
+    }
+  }
+  if (lds + 1024 > c->lds_max)
+    return fail(HFQMC_EUNSUPPORTED, "L=%d needs %d bytes of LDS, device allows %d", L, lds, c->lds_max);
+  int ref_nb = 0, ref_sc = 0, ref_lds = 0;
+  if (!direct) {
+    ref_lds = lds_bytes(L, L, -1, 0, 1, &ref_nb, &ref_sc);
+    if (ref_lds + 1024 > c->lds_max)
+      return fail(HFQMC_EUNSUPPORTED, "L=%d: reference solve needs %d bytes of LDS", L, ref_lds);
+  }
+
+  // ---- the buffer: grid data, then the per-workgroup workspaces
+  GridDev g;
+  std::memset(&g, 0, sizeof g);
+  GridDev* d_grid = nullptr;
+  int* d_units = nullptr;
+  int* d_queue = nullptr;
+  NoAllocSummary* d_sum = nullptr;
+  double* d_gtau = nullptr;
+  auto layout = [&](Bump& b) {
+    d_grid = b.take<GridDev>(1);
+    d_units = b.take<int>(nch);
+    d_queue = b.take<int>(64);
+    d_sum = b.take<NoAllocSummary>(1);
+    d_gtau = b.take<double>(L);
+    g.G0 = b.take<double>((size_t)L * L);
+    g.G0d = g.G0;
+    g.acc_g = b.take<double>((size_t)nch * nbin * (L + 1));
+    g.acc_d = b.take<double>((size_t)nch * nbin);
+    g.acc_n = b.take<long long>((size_t)nch * nbin);
+    g.cstats = b.take<long long>((size_t)nch * NSTAT);
+    g.cdrift = b.take<double>(nch);
+    g.cdrift_gt = b.take<double>(nch);
+    g.g_out = b.take<double>(L + 1);
+    g.g_err = b.take<double>(L + 1);
+    g.d_out = b.take<double>(2);
+    for (int q = 0; q < 2; ++q) {
+      g.refQ[q] = direct ? nullptr : b.take<double>((size_t)L * L);
+      g.refH[q] = direct ? nullptr : b.take<double>((size_t)L * L);
+      g.refQd[q] = g.refQ[q];
+      g.refHd[q] = g.refH[q];
+    }
+    g.ref_sing = direct ? nullptr : b.take<int>(4);
+  };
+  Bump sizing(nullptr);
+  layout(sizing);
+  const size_t head = (sizing.off + 255) & ~(size_t)255;
+  const long long wstride = workspace_doubles(L, r.mode == MODE_RANK1 ? 1 : kMaxK);
+  const long long slots =
+      head < kNoAllocBytes ? (long long)((kNoAllocBytes - head) / (sizeof(double) * wstride)) : 0;
+  const int need = direct ? 1 : 4;   // the reference solves use workspace slots 0..3
+  if (slots < need)
+    return fail(HFQMC_EINVAL, "hfqmc_solve_dev_noalloc: L=%d with %d chains exceeds the "
+                "allocation-free buffer of %zu bytes (grid data %zu bytes, then %d workspaces of "
+                "%lld bytes needed)", L, nch, kNoAllocBytes, head, need,
+                (long long)(sizeof(double) * wstride));
+  Bump assign(c->na_scratch);
+  layout(assign);
+  double* work = reinterpret_cast<double*>(static_cast<char*>(c->na_scratch) + head);
+  const int occ = std::max(1, std::min(c->lds_max / (lds + 1024), 2048 / kThreads));
+  const int n_wg = (int)std::min<long long>(std::min(nch, c->n_cu * occ), slots);
+
+  const double lam = std::acosh(std::exp(0.5 * dtau * U));
+  g.L = L;
+  g.n_chains = nch;
+  g.grid_id = 0;
+  g.unit_base = 0;
+  g.lu_nb = nb;
+  g.direct = direct;
+  g.ref_nb = ref_nb;
+  g.gp = std::expm1(2.0 * lam);
+  g.gm = std::expm1(-2.0 * lam);
+  g.ep = std::expm1(lam);
+  g.em = std::expm1(-lam);
+  g.spin = 0;
+
+  HIPCHK(launch_copy(g0_tau, d_gtau, L, st));
+  if (opts->flags & HFQMC_FLAG_PH_SYMMETRIC) {
+    // G0 = 1 - G0^T: G0(0+) = 1/2 and G0(tau) = G0(beta - tau) (the bath on the stack)
+    double hb[4096];
+    HIPCHK(hipMemcpyAsync(hb, d_gtau, sizeof(double) * L, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    double dev = std::fabs(hb[0] - 0.5);
+    for (int q = 1; q < L; ++q) dev = std::max(dev, std::fabs(hb[q] - hb[L - q]));
+    if (!(dev <= 1e-9))
+      return fail(HFQMC_EINVAL, "HFQMC_FLAG_PH_SYMMETRIC: the bath deviates from particle-hole "
+                  "symmetry by %.3e", dev);
+  }
+
+  SweepParams p;
+  std::memset(&p, 0, sizeof p);
+  p.grids = d_grid;
+  p.n_grids = 1;
+  p.units = d_units;
+  p.n_units = nch;
+  p.queue = d_queue;
+  p.seed = seed;
+  p.warmup = r.warmup;
+  p.sweeps = r.sweeps;
+  p.n_rec = r.n_rec;
+  p.mode = (opts->flags & HFQMC_FLAG_G_FP32) ? MODE_MIXED_G32 : r.mode;
+  p.delay_k = r.delay_k;
+  p.window_b = r.window_b;
+  p.n_bins = nbin;
+  p.lu_nb = nb;
+  p.work = work;
+  p.work_stride = wstride;
+  p.Lmax = L;
+  p.lds_scratch_bytes = sc;
+  p.heat_bath = (opts->flags & HFQMC_FLAG_HEAT_BATH) ? 1 : 0;
+  p.direct = direct;
+  p.ph = (opts->flags & HFQMC_FLAG_PH_SYMMETRIC) ? 1 : 0;
+  p.spin = 0;
+  p.pg = pg;
+  p.drift_every = r.drift_every;
+  HIPCHK(prepare_sweeps(lds));
+  if (!direct) HIPCHK(prepare_reference(ref_lds));
+
+  // ---- the launch sequence, eager; everything this call reads starts cleared
+  HIPCHK(hipEventRecord(c->ev0, st));
+  HIPCHK(launch_put_grid(g, d_grid, st));
+  HIPCHK(launch_iota(d_units, nch, st));
+  HIPCHK(launch_build_g0(d_gtau, L, const_cast<double*>(g.G0), st));
+  HIPCHK(launch_zero(g.acc_g, (long long)nch * nbin * (L + 1), st));
+  HIPCHK(launch_zero(g.acc_d, (long long)nch * nbin, st));
+  HIPCHK(launch_zero_i64(g.acc_n, (long long)nch * nbin, st));
+  HIPCHK(launch_zero_i64(g.cstats, (long long)nch * NSTAT, st));
+  HIPCHK(launch_zero(g.cdrift, nch, st));
+  HIPCHK(launch_zero(g.cdrift_gt, nch, st));
+  if (!direct) {
+    HIPCHK(launch_zero_i32(g.ref_sing, 4, st));
+    HIPCHK(launch_reference(p, ref_lds, ref_sc, 0, st));
+  }
+  HIPCHK(launch_zero_i32(d_queue, 64, st));
+  HIPCHK(hipEventRecord(c->ev_k0, st));
+  {
+    const hipError_t e = launch_sweeps(p, n_wg, lds, st);
+    if (e != hipSuccess)
+      return fail(HFQMC_EDEVICE, "sweep kernel (%d workgroups, %d B LDS): %s", n_wg, lds,
+                  hipGetErrorString(e));
+  }
+  HIPCHK(hipEventRecord(c->ev_k1, st));
+  HIPCHK(launch_reduce(d_grid, 1, nbin, st));
+  HIPCHK(hipEventRecord(c->ev1, st));
+  HIPCHK(launch_noalloc_summary(d_grid, d_sum, st));
+  HIPCHK(launch_copy(g.g_out, g_tau, L + 1, st));
+  if (g_err) HIPCHK(launch_copy(g.g_err, g_err, L + 1, st));
+  if (docc) HIPCHK(launch_copy(g.d_out, docc, 2, st));
+  NoAllocSummary hs;
+  HIPCHK(hipMemcpyAsync(&hs, d_sum, sizeof hs, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+
+  float ms = 0.f, ms_k = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+  HIPCHK(hipEventElapsedTime(&ms_k, c->ev_k0, c->ev_k1));
+  if (stats) {
+    hfqmc_stats tot;
+    std::memset(&tot, 0, sizeof tot);
+    add_counters(hs.stats, c->wall_hz, &tot);
+    tot.max_drift = hs.max_drift;
+    tot.max_drift_gtau = hs.max_drift_gtau;
+    tot.acc_rate = tot.n_proposed ? (double)tot.n_accepted / tot.n_proposed : 0.0;
+    tot.seconds_kernel = ms * 1e-3;
+    tot.seconds_sweep_kernel = ms_k * 1e-3;
+    tot.seconds_total =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    tot.delay_k = r.delay_k;
+    tot.recompute_every = r.n_rec;
+    tot.n_workgroups = n_wg;
+    tot.lu_panel = nb;
+    tot.graph = 0;
+    tot.autotuned = 0;
+    tot.seconds_autotune = 0.0;
+    tot.recompute_reduced = direct ? 0 : 1;
+    *stats = tot;
+  }
+  if (hs.ref_singular) return fail(HFQMC_ENUMERIC, "singular uniform-field reference matrix");
+  if (hs.stats[ST_SINGULAR])
+    return fail(HFQMC_ENUMERIC, "singular Dyson matrix in %lld recomputes", hs.stats[ST_SINGULAR]);
+  if (hs.nonfinite || !(hs.max_drift < INFINITY) || !(hs.max_drift_gtau < INFINITY))
+    return fail(HFQMC_ENUMERIC, "non-finite Green function");
+  if (opts->drift_limit > 0 && std::max(hs.max_drift, hs.max_drift_gtau) > opts->drift_limit)
+    return fail(HFQMC_EDRIFT, "recompute drift %.3e (G(tau): %.3e) exceeds limit %.3e",
+                hs.max_drift, hs.max_drift_gtau, opts->drift_limit);
+  return HFQMC_OK;
 }
 
 extern "C" int hfqmc_measure_peaks(hfqmc_ctx* c, hfqmc_peaks* out) {

@@ -135,6 +135,23 @@ hipError_t prepare_reference(int lds);
 hipError_t launch_reference(const SweepParams& p, int lds, int scratch, int dn, hipStream_t s);
 hipError_t launch_reduce(const GridDev* grids, int n_grids, int n_bins, hipStream_t s);
 
+// The allocation-free entry point (hfqmc_noalloc.hip): a static device buffer of
+// kNoAllocBytes per GPU holds everything a single-grid solve needs besides the
+// caller's inputs and outputs.
+constexpr size_t kNoAllocBytes = (size_t)128 << 20;
+struct NoAllocSummary {
+  long long stats[NSTAT];   // per-chain counters summed over the chains
+  double max_drift, max_drift_gtau;
+  int nonfinite;            // a reduced output (G(tau), its error, D) is not finite
+  int ref_singular;         // a uniform-field reference solve met a zero pivot
+};
+// Device address of device `device`'s buffer: looked up on the first call for that
+// device, which must be current then (hfqmc_create makes that call).
+hipError_t noalloc_scratch_lookup(int device, void** out);
+hipError_t launch_put_grid(const GridDev& g, GridDev* dst, hipStream_t s);
+hipError_t launch_iota(int* p, int n, hipStream_t s);
+hipError_t launch_noalloc_summary(const GridDev* gd, NoAllocSummary* out, hipStream_t s);
+
 // Achievable-peak probes (hfqmc_peaks.hip).  Copy / read: n16 16-byte
 // elements of src (and dst); out holds blocks * peak_threads() doubles.
 enum { PEAK_COPY = 0, PEAK_READ = 1, PEAK_MFMA64 = 2, PEAK_MFMA32 = 3, PEAK_FMA64 = 4 };
