@@ -1,4 +1,4 @@
-"""Bath Green functions for the half-filled Bethe lattice (oracle side).
+"""Bath Green functions for the Bethe lattice (oracle side).
 
 TEST INFRASTRUCTURE ONLY: nothing in the product path imports this module.
 
@@ -33,37 +33,40 @@ def semicircle_iw(beta, t, n_iw):
     return 1j * (w - np.sqrt(w * w + 4.0 * t * t)) / (2.0 * t * t)
 
 
-def iw_to_tau(f_iw, m3, beta, tau):
+def iw_to_tau(f_iw, m3, beta, tau, m2=0.0):
     """Positive-convention G(tau) at 0 <= tau < beta (tau = 0 means 0+).
 
     Fourier sum over the stored frequencies with the known high-frequency tail
-    1/(i w) + m3/(i w)^3 subtracted and added back in closed form:
-      G_std(tau) = -1/2 + m3 tau (beta - tau)/4
-                   + (2/beta) sum_n Re[e^{-i w_n tau} (F - 1/(i w) - m3/(i w)^3)]
+    1/(i w) + m2/(i w)^2 + m3/(i w)^3 subtracted and added back in closed form
+    ((1/beta) sum over all n of e^{-i w_n tau} / (i w_n)^p is -1/2, (2 tau -
+    beta)/4 and tau (beta - tau)/4 for p = 1, 2, 3):
+      G_std(tau) = -1/2 + m2 (2 tau - beta)/4 + m3 tau (beta - tau)/4
+                   + (2/beta) sum_n Re[e^{-i w_n tau} (F - 1/(i w) - m2/(i w)^2 - m3/(i w)^3)]
       G_pos(tau) = -G_std(tau).
-    Assumes a particle-hole symmetric function (no 1/(i w)^2 moment).
+    m2 = 0 for a particle-hole symmetric function (half filling).
     """
     f_iw = np.asarray(f_iw, dtype=np.complex128)
     tau = np.atleast_1d(np.asarray(tau, dtype=np.float64))
     w = matsubara(beta, f_iw.shape[0])
     iw = 1j * w
-    rem = f_iw - 1.0 / iw - m3 / iw ** 3
+    rem = f_iw - 1.0 / iw - m2 / iw ** 2 - m3 / iw ** 3
     out = np.empty(tau.shape[0])
     for a in range(tau.shape[0]):
         s = np.sum((np.exp(-1j * w * tau[a]) * rem).real)
-        g_std = -0.5 + m3 * tau[a] * (beta - tau[a]) / 4.0 + 2.0 / beta * s
+        g_std = (-0.5 + m2 * (2.0 * tau[a] - beta) / 4.0 + m3 * tau[a] * (beta - tau[a]) / 4.0
+                 + 2.0 / beta * s)
         out[a] = -g_std
     return out
 
 
-def bath_to_tau(bath_iw, m3, beta, L):
+def bath_to_tau(bath_iw, m3, beta, L, m2=0.0):
     """Bath on a Trotter grid: G(tau_k), tau_k = k beta / L, k = 0..L-1."""
     tau = np.arange(L) * (beta / L)
-    return iw_to_tau(bath_iw, m3, beta, tau)
+    return iw_to_tau(bath_iw, m3, beta, tau, m2=m2)
 
 
-def semicircle_tau_dos(beta, t, tau, n_nodes=20000):
-    """Independent route: G(tau) = int rho(e) e^{-tau e} / (1 + e^{-beta e}) de.
+def semicircle_tau_dos(beta, t, tau, n_nodes=20000, mu=0.0):
+    """Independent route: G(tau) = int rho(e) e^{-tau (e - mu)} / (1 + e^{-beta (e - mu)}) de.
 
     rho(e) = sqrt(4t^2 - e^2) / (2 pi t^2); with e = 2 t x this is
     (2/pi) int_{-1}^{1} sqrt(1 - x^2) f(2 t x) dx, evaluated by Gauss-Chebyshev
@@ -73,7 +76,7 @@ def semicircle_tau_dos(beta, t, tau, n_nodes=20000):
     th = i * np.pi / (n_nodes + 1)
     x = np.cos(th)
     wts = np.pi / (n_nodes + 1) * np.sin(th) ** 2
-    e = 2.0 * t * x
+    e = 2.0 * t * x - mu
     tau = np.atleast_1d(np.asarray(tau, dtype=np.float64))
     out = np.empty(tau.shape[0])
     for a in range(tau.shape[0]):
@@ -86,10 +89,39 @@ def semicircle_tau_dos(beta, t, tau, n_nodes=20000):
     return out
 
 
-def bethe_step_iw(g_iw, beta, t):
-    """Bethe-lattice closure of the DMFT cycle: new bath 1/(i w - t^2 G(i w))."""
+def bethe_step_iw(g_iw, beta, t, mu=0.0):
+    """Bethe-lattice closure of the DMFT cycle: new bath 1/(i w + mu - t^2 G(i w)).
+
+    mu is the chemical potential measured from half filling (the interaction
+    U (n_up n_dn - (n_up + n_dn)/2) of the symmetric decoupling carries the
+    Hartree shift of the half-filled case).  The new bath's tail is
+    1/(i w) - mu/(i w)^2 + (mu^2 + t^2)/(i w)^3 whatever G is."""
     w = matsubara(beta, g_iw.shape[0])
-    return 1.0 / (1j * w - t * t * np.asarray(g_iw))
+    return 1.0 / (1j * w + mu - t * t * np.asarray(g_iw))
+
+
+def bethe_lattice_iw(beta, t, mu, n_iw):
+    """Noninteracting local Green function of the Bethe lattice at chemical
+    potential mu: G(z) = (z - sqrt(z - 2t) sqrt(z + 2t)) / (2 t^2), z = i w + mu
+    (principal square roots: the branch with G ~ 1/z and Im G < 0), evaluated
+    as 2 / (z + sqrt(z - 2t) sqrt(z + 2t)), the same number without the
+    cancellation at large |z|.  At U = 0 it solves the closure G = 1/(z - t^2 G):
+    the fixed point of the cycle."""
+    z = 1j * matsubara(beta, n_iw) + mu
+    return 2.0 / (z + np.sqrt(z - 2.0 * t) * np.sqrt(z + 2.0 * t))
+
+
+def bethe_lattice_iw_dos(beta, t, mu, n_iw, n_nodes=20000):
+    """Independent route: G(i w) = int rho(e) / (i w + mu - e) de with the
+    semi-elliptic rho(e) = sqrt(4t^2 - e^2)/(2 pi t^2), by the Gauss-Chebyshev
+    quadrature of semicircle_tau_dos.  Used only to pin ``bethe_lattice_iw``."""
+    i = np.arange(1, n_nodes + 1)
+    th = i * np.pi / (n_nodes + 1)
+    x = np.cos(th)
+    wts = np.pi / (n_nodes + 1) * np.sin(th) ** 2
+    e = 2.0 * t * x
+    z = 1j * matsubara(beta, n_iw) + mu
+    return 2.0 / np.pi * (wts[None, :] / (z[:, None] - e[None, :])).sum(axis=1)
 
 
 def atomic_seed_iw(beta, t, U, n_iw):

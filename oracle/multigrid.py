@@ -152,6 +152,102 @@ def multigrid_solve_spin(baths, m3, U, beta, dtaus, seed, n_chains, warmup, swee
                 D=float(d0[0]), D_err=float(d0e[0]))
 
 
+# ------------------------------------------------ away from half filling ----
+# The method applies at any filling (closing remarks); the readings taken:
+#   * the bath's tail 1/(i w) + m2/(i w)^2 + m3/(i w)^3 (bath.iw_to_tau);
+#   * reference model at density n per spin: G_ref = 1/(1/Bath - Sigma_ref) with
+#     the first two high-frequency terms of the self-energy of the interaction
+#     U (n_up n_dn - (n_up + n_dn)/2), Sigma_ref(i w) = U (n - 1/2) + U^2 n (1 - n)/(i w)
+#     (n = 1/2: the half-filled reference above); G_ref's tail moments follow
+#     from the bath's;
+#   * n of the interpolation: the estimate G(beta-) of the finest grid; n of the
+#     closure's transform: the extrapolated G(beta-);
+#   * Bethe closure at chemical potential mu (from half filling):
+#     Bath = 1/(i w + mu - t^2 G), tail moments m2 = -mu, m3 = mu^2 + t^2.
+
+def reference_iw_n(bath_iw, U, beta, n):
+    """Reference model at density n per spin on the Matsubara axis."""
+    iw = 1j * B.matsubara(beta, bath_iw.shape[0])
+    return 1.0 / (1.0 / bath_iw - U * (n - 0.5) - U * U * n * (1.0 - n) / iw)
+
+
+def reference_moments(m2, m3, U, n):
+    """(M2, M3) of G_ref = 1/(1/Bath - s0 - s1/(i w)), Bath ~ 1/(i w) + m2/(i w)^2 + m3/(i w)^3:
+    1/Bath = i w - m2 + (m2^2 - m3)/(i w) + ..., so M2 = m2 + s0 and
+    M3 = M2^2 - (m2^2 - m3 - s1), with s0 = U (n - 1/2), s1 = U^2 n (1 - n)."""
+    s0 = U * (n - 0.5)
+    s1 = U * U * n * (1.0 - n)
+    M2 = m2 + s0
+    return M2, M2 * M2 - (m2 * m2 - m3 - s1)
+
+
+def reference_tau_n(bath_iw, m2, m3, U, beta, tau, n):
+    """Reference model at density n at imaginary times."""
+    M2, M3 = reference_moments(m2, m3, U, n)
+    return B.iw_to_tau(reference_iw_n(bath_iw, U, beta, n), M3, beta, tau, m2=M2)
+
+
+def multigrid_solve_n(bath_iw, m2, m3, U, beta, dtaus, seed, n_chains, warmup, sweeps,
+                      n_rec=100, n_fine=200, mapper=None):
+    """Multigrid solve at any filling: one fixed-dtau solve per grid (grid_id = i, the bath
+    with its 1/(i w)^2 moment m2), then steps (i) and (ii) with the reference model at
+    the finest grid's density n = G(beta-)."""
+    Ls, dts = grid_lengths(beta, dtaus)
+    tau_f = fine_grid(beta, n_fine)
+    per = []
+    for i, L in enumerate(Ls):
+        g_tau = B.bath_to_tau(bath_iw, m3, beta, L, m2=m2)
+        per.append(H.solve(g_tau, U, beta, seed, n_chains=n_chains, warmup=warmup,
+                           sweeps=sweeps, n_rec=n_rec, grid_id=i, mapper=mapper))
+    n_ref = float(per[int(np.argmax(Ls))]["g"][-1])
+    gref_f = reference_tau_n(bath_iw, m2, m3, U, beta, tau_f, n_ref)
+    gi, ei = [], []
+    for L, r in zip(Ls, per):
+        tau_k = np.arange(L + 1) * (beta / L)
+        gref_k = reference_tau_n(bath_iw, m2, m3, U, beta, tau_k, n_ref)
+        g_f, e_f = interpolate_grid(r["g"], r["g_err"], beta, gref_k, gref_f, tau_f)
+        gi.append(g_f)
+        ei.append(e_f)
+    c0, err = extrapolate(dts, np.array(gi), np.array(ei))
+    d0, d0e = extrapolate(dts, np.array([[r["D"]] for r in per]),
+                          np.array([[r["D_err"]] for r in per]))
+    return dict(g=c0, g_err=err, tau=tau_f, grids=per, g_interp=np.array(gi),
+                e_interp=np.array(ei), Ls=Ls, dtaus=dts, D=float(d0[0]), D_err=float(d0e[0]),
+                n_ref=n_ref)
+
+
+def dmft_bethe_step_n(g_fine, tau_fine, bath_iw, m2, m3, U, beta, t, mu):
+    """Closure at chemical potential mu: G(i w) = G_ref(i w) - FT[spline(G - G_ref)] with the
+    reference at the density n = G(beta-) of g_fine, then 1/(i w + mu - t^2 G(i w))."""
+    n = float(g_fine[-1])
+    gref_f = reference_tau_n(bath_iw, m2, m3, U, beta, tau_fine, n)
+    delta = spline_fourier(tau_fine, np.asarray(g_fine) - gref_f, beta, bath_iw.shape[0])
+    g_iw = reference_iw_n(bath_iw, U, beta, n) - delta
+    return B.bethe_step_iw(g_iw, beta, t, mu=mu)
+
+
+def dmft_loop_mu(bath_iw, U, mu, beta, t, dtaus, seed, n_iter, n_chains, warmup, sweeps,
+                 n_rec=100, n_fine=200, mixing=0.0):
+    """The DMFT cycle of Fig. 1(c) at chemical potential mu on the Bethe lattice: the
+    bath keeps the tail moments m2 = -mu, m3 = mu^2 + t^2.  history[it] = (max |g -
+    g_prev|, max g_err, D, D_err, n), n = G(beta-) extrapolated."""
+    m2, m3 = -mu, mu * mu + t * t
+    bath = np.asarray(bath_iw, dtype=np.complex128).copy()
+    tau_f = fine_grid(beta, n_fine)
+    prev = reference_tau_n(bath, m2, m3, 0.0, beta, tau_f, 0.5)   # U = 0: the bath itself
+    hist = []
+    r = None
+    for it in range(n_iter):
+        r = multigrid_solve_n(bath, m2, m3, U, beta, dtaus, seed + (it << 32), n_chains, warmup,
+                              sweeps, n_rec=n_rec, n_fine=n_fine)
+        hist.append((float(np.abs(r["g"] - prev).max()), float(r["g_err"].max()), r["D"],
+                     r["D_err"], float(r["g"][-1])))
+        prev = r["g"]
+        new = dmft_bethe_step_n(r["g"], tau_f, bath, m2, m3, U, beta, t, mu)
+        bath = mixing * bath + (1.0 - mixing) * new
+    return dict(bath=bath, g=r["g"], g_err=r["g_err"], tau=tau_f, history=np.array(hist))
+
+
 def spline_fourier(tau, values, beta, n_iw):
     """Exact int_0^beta e^{i w_n tau} S(tau) d tau for the natural cubic spline S.
 
