@@ -16,6 +16,20 @@ CPU oracle timed on a bounded sample of the workload.  Progress goes to stderr.
   python bench.py --mode delayed       # delayed rank-k, FP64 flush
   python bench.py --delay-k 64         # fixed k instead of the autotuner
   python bench.py --calib-copy         # copy kernel used to scale PMC counters
+
+Other workloads (one JSON line per DMFT iteration, then a summary line):
+
+  python bench.py --workload c5 --iterations 3 --state c5.json
+      the eight-grid multigrid DMFT cycle near the Mott transition: beta = 100,
+      U = 4.8, dtau 0.4 .. 0.05 (L = 250 .. 2000), 32 chains per grid, mixed
+      path with autotuned k, single-matrix form, 4001-point fine grid; the bath,
+      iteration count and history are kept in --state, so a run of many
+      iterations can be split over several calls (each call continues the
+      random streams where the last one stopped)
+  python bench.py --workload range-scan
+      the grid-range bias of the multigrid fixed point (the study of Fig. 4):
+      U = 4, beta = 45, the DMFT cycle converged separately on three dtau
+      ranges of five grids each; D of the last iterations per range
 """
 import argparse
 import hashlib
@@ -293,6 +307,107 @@ def calib_copy():
     print(json.dumps({"calib_copy_bytes_read": 8 * n, "calib_copy_bytes_written": 8 * n}))
 
 
+C5_DTAUS = [0.4, 0.35, 0.3, 0.25, 0.2, 0.15, 0.1, 0.05]     # L = 250 .. 2000 at beta = 100
+RANGES = {"[0.2,0.5]": [0.2, 0.25, 0.3, 0.4, 0.5],
+          "[0.3,0.7]": [0.3, 0.4, 0.5, 0.6, 0.7],
+          "[0.35,0.8]": [0.35, 0.45, 0.55, 0.65, 0.8]}
+
+
+def _cycle_opts(args, mode):
+    return dict(n_chains=args.chains, warmup=args.chain_warmup, sweeps=args.chain_sweeps,
+                mode=mode, delay_k=args.delay_k if mode != "rank1" else 0, ph=not args.two_matrix)
+
+
+def workload_c5(args):
+    """The eight-grid multigrid DMFT cycle, resumable through a JSON state file."""
+    import paper_0801_1222_amd as P
+    beta, t, U = 100.0, 1.0, args.U
+    n_iw, n_fine = 8192, 4001
+    st = None
+    if args.state and os.path.exists(args.state):
+        with open(args.state) as f:
+            st = json.load(f)
+        if st["beta"] != beta or st["U"] != U:
+            raise SystemExit("state file %s is for beta=%g U=%g" % (args.state, st["beta"], st["U"]))
+        bath = np.array(st["bath_re"]) + 1j * np.array(st["bath_im"])
+    else:
+        bath = P.bethe_semicircle_bath(beta, t, n_iw)
+        st = dict(beta=beta, U=U, iterations=0, history=[])
+    ctx = P.Context(0)
+    mode = args.mode
+    kw = _cycle_opts(args, mode)
+    Ls = [int(round(beta / d)) for d in C5_DTAUS]
+    progress("c5: beta=%g U=%g L=%s, %d chains x (%d+%d) sweeps per grid and iteration, mode %s%s"
+             % (beta, U, Ls, kw["n_chains"], kw["warmup"], kw["sweeps"], mode,
+                ", single-matrix form" if kw["ph"] else ""))
+    for _ in range(args.iterations):
+        it = st["iterations"]
+        t0 = time.perf_counter()
+        r = P.dmft_solve(ctx, U, beta, t, C5_DTAUS, args.seed + (it << 32), 1, bath_iw=bath,
+                         n_fine=n_fine, mixing=args.mixing, **kw)
+        dt = time.perf_counter() - t0
+        bath = r["bath"]
+        h = r["history"][0]
+        g = r["g"]
+        rec = dict(workload="c5", iteration=it, U=U, beta=beta, Ls=Ls, D=float(h[2]),
+                   D_err=float(h[3]), max_dg=float(h[0]), max_g_err=float(h[1]),
+                   g_beta_half=float(g[(n_fine - 1) // 2]),
+                   g_beta_half_err=float(r["g_err"][(n_fine - 1) // 2]), seconds=dt,
+                   chains=kw["n_chains"], warmup=kw["warmup"], sweeps=kw["sweeps"], mode=mode,
+                   single_matrix=kw["ph"], mixing=args.mixing)
+        st["history"].append(rec)
+        st["iterations"] = it + 1
+        st["bath_re"] = bath.real.tolist()
+        st["bath_im"] = bath.imag.tolist()
+        if args.state:
+            tmp = args.state + ".tmp"
+            with open(tmp, "w") as f:
+                json.dump(st, f)
+            os.replace(tmp, args.state)
+        print(json.dumps(rec), flush=True)
+        progress("c5 iteration %d: D = %.5f(%d), max |dG| %.2e, %.0f s"
+                 % (it, rec["D"], round(rec["D_err"] * 1e5), rec["max_dg"], dt))
+    ctx.close()
+    hist = st["history"]
+    print(json.dumps(dict(workload="c5", summary=True, iterations=st["iterations"],
+                          D=[h_["D"] for h_ in hist], D_err=[h_["D_err"] for h_ in hist],
+                          max_dg=[h_["max_dg"] for h_ in hist],
+                          seconds_per_iteration=[h_["seconds"] for h_ in hist])), flush=True)
+
+
+def workload_range_scan(args):
+    """Grid-range bias of the multigrid DMFT fixed point: one cycle per dtau range from a
+    common start; D and its error from the last iterations of each range."""
+    import paper_0801_1222_amd as P
+    beta, t, U = 45.0, 1.0, args.U
+    ctx = P.Context(0)
+    kw = _cycle_opts(args, args.mode)
+    # common start: a short cycle on the middle range
+    start = P.dmft_solve(ctx, U, beta, t, RANGES["[0.3,0.7]"], args.seed, args.iterations,
+                         n_iw=4096, n_fine=451, mixing=args.mixing, **kw)["bath"]
+    progress("range scan: common start after %d iterations" % args.iterations)
+    out = {}
+    for i, (name, dts) in enumerate(RANGES.items()):
+        r = P.dmft_solve(ctx, U, beta, t, dts, args.seed + ((i + 1) << 40), args.scan_iterations,
+                         bath_iw=start, n_fine=451, mixing=args.mixing, **kw)
+        d = r["history"][:, 2]
+        tail = d[args.scan_iterations // 4:]
+        rec = dict(workload="range-scan", range=name, dtaus=dts,
+                   Ls=[int(round(beta / x)) for x in dts], D=float(np.mean(tail)),
+                   D_err=float(np.std(tail, ddof=1) / np.sqrt(len(tail))), D_history=d.tolist(),
+                   chains=kw["n_chains"], warmup=kw["warmup"], sweeps=kw["sweeps"],
+                   mode=args.mode, single_matrix=kw["ph"])
+        out[name] = rec
+        print(json.dumps(rec), flush=True)
+        progress("range %s: D = %.5f(%d)" % (name, rec["D"], round(rec["D_err"] * 1e5)))
+    ref = out["[0.2,0.5]"]
+    print(json.dumps(dict(workload="range-scan", summary=True, U=U, beta=beta,
+                          shift_vs_0205={k: v["D"] - ref["D"] for k, v in out.items()},
+                          shift_err={k: float(np.hypot(v["D_err"], ref["D_err"]))
+                                     for k, v in out.items()})), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -314,6 +429,20 @@ def main():
                     help="time the mixed path with G stored in FP32 between recomputes")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the peak probes and the small-L / three-grid workloads")
+    ap.add_argument("--workload", default="headline", choices=["headline", "c5", "range-scan"])
+    ap.add_argument("--iterations", type=int, default=None,
+                    help="c5: DMFT iterations in this call (default 1); range-scan: "
+                         "iterations to the common start (default 6)")
+    ap.add_argument("--scan-iterations", type=int, default=16,
+                    help="range-scan: DMFT iterations per dtau range")
+    ap.add_argument("--state", default=None, help="c5: JSON state file (resume and save)")
+    ap.add_argument("--U", type=float, default=None,
+                    help="c5: U (default 4.8); range-scan: U (default 4)")
+    ap.add_argument("--chains", type=int, default=None)
+    ap.add_argument("--mixing", type=float, default=0.5)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--two-matrix", action="store_true",
+                    help="c5 / range-scan: both Green matrices (default: single-matrix form)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -324,6 +453,24 @@ def main():
         sys.exit(2)
     if args.calib_copy:
         calib_copy()
+        return
+    if args.workload != "headline":
+        import torch  # noqa: F401  (PyTorch's runtime comes up before the library's)
+        if args.workload == "c5":
+            args.U = 4.8 if args.U is None else args.U
+            args.chains = args.chains or 32
+            args.chain_warmup = 100 if args.chain_warmup is None else args.chain_warmup
+            args.chain_sweeps = args.chain_sweeps or 1000
+            args.iterations = 1 if args.iterations is None else args.iterations
+            workload_c5(args)
+        else:
+            args.U = 4.0 if args.U is None else args.U
+            args.chains = args.chains or 256
+            args.chain_warmup = 100 if args.chain_warmup is None else args.chain_warmup
+            args.chain_sweeps = args.chain_sweeps or 2000
+            args.mode = "delayed" if args.mode == "mixed" else args.mode
+            args.iterations = 6 if args.iterations is None else args.iterations
+            workload_range_scan(args)
         return
 
     import torch
@@ -427,7 +574,8 @@ def main():
                     peaks["fp32_mfma_tflops"], peaks["fp64_fma_tflops"]))
         # small grids, FP64 rank-1, all in one launch: latency of the per-flip dependency
         small = batched_grids(P, ctx, "seven grids", 20.0, 4.8,
-                              [0.4, 1 / 3, 2 / 7, 0.25, 0.2, 1 / 6, 0.125], 64, 20, 200, "rank1")
+                              [0.4, 1 / 3, 2 / 7, 0.25, 0.2, 1 / 6, 0.125], 64, 200, 2000, "rank1")
+        small["full_length"] = True
         fl = sum(4.0 * g_["L"] ** 2 * g_["accepted"] for g_ in small["grids"])
         small["fp64_update_tflops"] = fl / small["kernel_s"] / 1e12
         small["frac_of_measured_fp64_fma"] = (small["fp64_update_tflops"] / peaks["fp64_fma_tflops"]
@@ -437,6 +585,9 @@ def main():
                  % (small["chain_sweeps_per_s"], small["accepted_flips_per_s"]))
         three = batched_grids(P, ctx, "three grids", 50.0, 5.0, [0.125, 0.1, 0.0625], 128, 2, 10,
                               "mixed")
+        three["full_length"] = False
+        three["note"] = ("shortened to 2+10 sweeps per chain (the full 200+2000 take about 80 s); "
+                         "per-grid rates include the chain-initial recompute")
         extra["three_grids_mixed"] = three
         progress("three grids L=400/500/800 (mixed): %.0f L=400-equivalent chain-sweeps/s"
                  % three["l400_equiv_sweeps_per_s"])
@@ -504,9 +655,12 @@ def main():
         progress("plain rank-1 comparison done: %.0f sweeps/s" % rank1["sweeps_per_s"])
     cpu = None
     if not args.no_cpu_baseline:
-        procs = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-        procs = max(1, min(procs, 16))
+        aff = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+        # one process per core of this process's CPU share: the GPU host grants one GPU's
+        # job 16 cores whatever the affinity mask shows
+        procs = max(1, min(aff, 16))
         cpu = cpu_baseline(procs, 0, args.cpu_sweeps, procs)
+        cpu["affinity_cores"] = aff
         progress("cpu baseline done: %.2f sweeps/s on %d cores" % (cpu["value"], procs))
     ph = {k: st[k] for k in ("chain_s_sweep", "chain_s_flush", "chain_s_recompute",
                              "chain_s_measure", "chain_s_lu_build", "chain_s_lu_panel",

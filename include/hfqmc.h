@@ -346,6 +346,55 @@ int dmft_solve_af(hfqmc_ctx *ctx, double U, double beta, double t, const double 
                   int32_t n_iw, int32_t n_iter, double mixing, double *bath_up, double *bath_dn,
                   double *g_fine, double *g_fine_err, double *history);
 
+/* ------------------------------------------------------------------------------
+ * Away from half filling (the method's generality, closing remarks of the paper).
+ * Readings: the bath's tail is 1/(i w) + m2/(i w)^2 + m3/(i w)^3; the chemical
+ * potential mu is measured from half filling (the interaction is the symmetric
+ * U (n_up n_dn - (n_up + n_dn)/2) of every solve here); the reference model of
+ * the interpolation at density n per spin is 1/(1/bath - U (n - 1/2) - U^2 n (1 - n)/(i w)),
+ * the first two high-frequency terms of the self-energy (at n = 1/2 the
+ * half-filled reference of multigrid_solve).  The impurity solves are the
+ * two-matrix path (HFQMC_FLAG_PH_SYMMETRIC gives EINVAL).
+ * ------------------------------------------------------------------------------ */
+
+/* Noninteracting Bethe-lattice Green function at chemical potential mu (the U = 0
+ * solution of dmft_solve_mu): (z - sqrt(z - 2t) sqrt(z + 2t))/(2 t^2), z = i w + mu,
+ * on w_n, n = 0..n_iw-1.  Tail moments -mu, mu^2 + t^2.  EINVAL for a null
+ * pointer, beta <= 0, t <= 0, non-finite mu, n_iw < 1. */
+int bethe_lattice_bath(double beta, double t, double mu, int32_t n_iw, double *bath_iw);
+
+/* bath_to_tau with the 1/(i w)^2 moment m2 of the tail handled in closed form. */
+int bath_to_tau_m2(const double *bath_iw, int32_t n_iw, double m2, double m3, double beta,
+                   int32_t L, double *g_tau);
+
+/* multigrid_solve at any filling: grid i gets the bath transformed with both tail
+ * moments (bath_to_tau_m2); step (i) uses the reference model at the finest grid's
+ * density n = G(beta-) (returned in n_ref, or NULL); step (ii) as multigrid_solve.
+ * g_fine[n_fine], g_fine_err (or NULL), docc[2] (or NULL) as multigrid_solve.
+ * Errors as multigrid_solve, and EINVAL with HFQMC_FLAG_PH_SYMMETRIC. */
+int multigrid_solve_n(hfqmc_ctx *ctx, const double *bath_iw, int32_t n_iw, double m2, double m3,
+                      double U, double beta, const double *dtaus, int32_t n_grids, uint64_t seed,
+                      const hfqmc_opts *opts, int32_t n_fine, double *g_fine, double *g_fine_err,
+                      double *docc, double *n_ref);
+
+/* The Bethe closure at chemical potential mu: G(i w) = G_ref(i w) - int_0^beta e^{i w tau}
+ * S(tau) d tau, S the natural cubic spline of g_fine - G_ref, the reference at the
+ * density n = g_fine[n_fine - 1] built from bath_iw_prev (tail m2, m3); then
+ * bath_iw_new = 1/(i w + mu - t^2 G(i w)). */
+int dmft_bethe_step_mu(const double *g_fine, int32_t n_fine, const double *bath_iw_prev,
+                       int32_t n_iw, double m2, double m3, double U, double beta, double t,
+                       double mu, double *bath_iw_new);
+
+/* The multigrid DMFT cycle on the Bethe lattice at chemical potential mu (as
+ * dmft_solve, with multigrid_solve_n and dmft_bethe_step_mu; the bath keeps the tail
+ * moments -mu and mu^2 + t^2; a natural start is bethe_lattice_bath).
+ * history[5 n_iter] (or NULL): max |g_fine change|, max error bar, D, D error, and
+ * the density n = G(beta-) extrapolated.  Errors as dmft_solve. */
+int dmft_solve_mu(hfqmc_ctx *ctx, double U, double mu, double beta, double t, const double *dtaus,
+                  int32_t n_grids, uint64_t seed, const hfqmc_opts *opts, int32_t n_fine,
+                  int32_t n_iw, int32_t n_iter, double mixing, double *bath_iw, double *g_fine,
+                  double *g_fine_err, double *history);
+
 /* U = 0 starting bath: Bethe-lattice local Green function, half-bandwidth 2t. */
 int bethe_semicircle_bath(double beta, double t, int32_t n_iw, double *bath_iw);
 

@@ -111,6 +111,18 @@ lib.bath_to_tau.restype = C.c_int
 lib.dmft_solve.argtypes = [_ctx_p, _f64, _f64, _f64, _pd, _i32, _u64, C.POINTER(Opts), _i32, _i32,
                            _i32, _f64, _pd, _pd, _pd, _pd]
 lib.dmft_solve.restype = C.c_int
+lib.bethe_lattice_bath.argtypes = [_f64, _f64, _f64, _i32, _pd]
+lib.bethe_lattice_bath.restype = C.c_int
+lib.bath_to_tau_m2.argtypes = [_pd, _i32, _f64, _f64, _f64, _i32, _pd]
+lib.bath_to_tau_m2.restype = C.c_int
+lib.multigrid_solve_n.argtypes = [_ctx_p, _pd, _i32, _f64, _f64, _f64, _f64, _pd, _i32, _u64,
+                                  C.POINTER(Opts), _i32, _pd, _pd, _pd, _pd]
+lib.multigrid_solve_n.restype = C.c_int
+lib.dmft_bethe_step_mu.argtypes = [_pd, _i32, _pd, _i32, _f64, _f64, _f64, _f64, _f64, _f64, _pd]
+lib.dmft_bethe_step_mu.restype = C.c_int
+lib.dmft_solve_mu.argtypes = [_ctx_p, _f64, _f64, _f64, _f64, _pd, _i32, _u64, C.POINTER(Opts),
+                              _i32, _i32, _i32, _f64, _pd, _pd, _pd, _pd]
+lib.dmft_solve_mu.restype = C.c_int
 lib.hfqmc_measure_peaks.argtypes = [_ctx_p, C.POINTER(Peaks)]
 lib.hfqmc_measure_peaks.restype = C.c_int
 
@@ -123,7 +135,9 @@ FLAG_G_FP32 = 16           # mixed mode: G stored in FP32 between recomputes
 EXPORTED = ["hfqmc_create", "hfqmc_destroy", "hfqmc_set_stream", "hfqmc_last_error",
             "hfqmc_solve", "hfqmc_solve_spin", "hfqmc_solve_dev", "hfqmc_solve_grids", "multigrid_solve", "dmft_bethe_step",
             "bethe_semicircle_bath", "bethe_atomic_bath", "bath_to_tau", "hfqmc_measure_peaks", "dmft_solve",
-            "multigrid_solve_spin", "dmft_solve_af", "hfqmc_solve_dev_noalloc"]
+            "multigrid_solve_spin", "dmft_solve_af", "hfqmc_solve_dev_noalloc",
+            "bethe_lattice_bath", "bath_to_tau_m2", "multigrid_solve_n", "dmft_bethe_step_mu",
+            "dmft_solve_mu"]
 
 
 def ptr(a, ctype=C.c_double):

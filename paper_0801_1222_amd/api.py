@@ -432,3 +432,77 @@ def bath_to_tau(bath_iw, m3, beta, L):
     N.check(N.lib.bath_to_tau(N.ptr(b), b.shape[0] // 2, float(m3), float(beta), int(L), N.ptr(out)),
             "bath_to_tau")
     return out
+
+
+# ------------------------------------------------------ away from half filling
+
+
+def bethe_lattice_bath(beta, t, mu, n_iw):
+    """Noninteracting Bethe-lattice G at chemical potential mu (the U = 0 solution)."""
+    out = np.zeros(2 * int(n_iw))
+    N.check(N.lib.bethe_lattice_bath(float(beta), float(t), float(mu), int(n_iw), N.ptr(out)),
+            "bethe_lattice_bath")
+    return out.view(np.complex128)
+
+
+def bath_to_tau_m2(bath_iw, m2, m3, beta, L):
+    b = np.ascontiguousarray(np.asarray(bath_iw, dtype=np.complex128)).view(np.float64)
+    out = np.zeros(int(L))
+    N.check(N.lib.bath_to_tau_m2(N.ptr(b), b.shape[0] // 2, float(m2), float(m3), float(beta),
+                                 int(L), N.ptr(out)), "bath_to_tau_m2")
+    return out
+
+
+def multigrid_solve_n(ctx, bath_iw, m2, m3, U, beta, dtaus, seed, n_fine=200, n_chains=1,
+                      warmup=0, sweeps=1, mode="rank1", recompute_every=0, delay_k=0, n_bins=0,
+                      drift_limit=0.0, drift_every=0, eager=False, heat_bath=False, direct=False):
+    """multigrid_solve at any filling: dict(g, g_err, tau, D, D_err, n_ref)."""
+    b = np.ascontiguousarray(np.asarray(bath_iw, dtype=np.complex128)).view(np.float64)
+    dt = np.ascontiguousarray(dtaus, dtype=np.float64)
+    o = _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drift_limit,
+              _flags(eager, heat_bath, direct), drift_every=drift_every)
+    gf = np.zeros(n_fine)
+    ef = np.zeros(n_fine)
+    dx = np.zeros(2)
+    nr = np.zeros(1)
+    rc = N.lib.multigrid_solve_n(ctx.handle, N.ptr(b), b.shape[0] // 2, float(m2), float(m3),
+                                 float(U), float(beta), N.ptr(dt), dt.shape[0], int(seed),
+                                 C.byref(o), int(n_fine), N.ptr(gf), N.ptr(ef), N.ptr(dx),
+                                 N.ptr(nr))
+    N.check(rc, "multigrid_solve_n")
+    return dict(g=gf, g_err=ef, tau=np.arange(n_fine) * (beta / (n_fine - 1)), D=float(dx[0]),
+                D_err=float(dx[1]), n_ref=float(nr[0]))
+
+
+def dmft_bethe_step_mu(g_fine, bath_iw_prev, m2, m3, U, beta, t, mu):
+    """New bath 1/(i w + mu - t^2 G(i w)) on the frequencies of bath_iw_prev."""
+    g = np.ascontiguousarray(g_fine, dtype=np.float64)
+    b = np.ascontiguousarray(np.asarray(bath_iw_prev, dtype=np.complex128)).view(np.float64)
+    out = np.zeros(b.shape[0])
+    rc = N.lib.dmft_bethe_step_mu(N.ptr(g), g.shape[0], N.ptr(b), b.shape[0] // 2, float(m2),
+                                  float(m3), float(U), float(beta), float(t), float(mu), N.ptr(out))
+    N.check(rc, "dmft_bethe_step_mu")
+    return out.view(np.complex128)
+
+
+def dmft_solve_mu(ctx, U, mu, beta, t, dtaus, seed, n_iter, bath_iw=None, n_iw=4096, n_fine=200,
+                  mixing=0.0, n_chains=1, warmup=0, sweeps=1, mode="rank1", recompute_every=0,
+                  delay_k=0, n_bins=0, drift_limit=0.0, drift_every=0, eager=False,
+                  heat_bath=False, direct=False):
+    """Multigrid DMFT cycle at chemical potential mu, from bath_iw (default: the U = 0
+    lattice at mu).  history[it] = (max |g change|, max g_err, D, D_err, n)."""
+    if bath_iw is None:
+        bath_iw = bethe_lattice_bath(beta, t, mu, n_iw)
+    b = np.ascontiguousarray(np.asarray(bath_iw, dtype=np.complex128)).copy().view(np.float64)
+    dt = np.ascontiguousarray(dtaus, dtype=np.float64)
+    o = _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drift_limit,
+              _flags(eager, heat_bath, direct), drift_every=drift_every)
+    gf = np.zeros(n_fine)
+    ef = np.zeros(n_fine)
+    hist = np.zeros(5 * int(n_iter))
+    rc = N.lib.dmft_solve_mu(ctx.handle, float(U), float(mu), float(beta), float(t), N.ptr(dt),
+                             dt.shape[0], int(seed), C.byref(o), int(n_fine), b.shape[0] // 2,
+                             int(n_iter), float(mixing), N.ptr(b), N.ptr(gf), N.ptr(ef), N.ptr(hist))
+    N.check(rc, "dmft_solve_mu")
+    return dict(bath=b.view(np.complex128), g=gf, g_err=ef,
+                tau=np.arange(n_fine) * (beta / (n_fine - 1)), history=hist.reshape(-1, 5))

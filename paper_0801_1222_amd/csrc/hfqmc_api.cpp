@@ -1386,6 +1386,163 @@ extern "C" int dmft_solve(hfqmc_ctx* c, double U, double beta, double t, const d
   return HFQMC_OK;
 }
 
+extern "C" int bethe_lattice_bath(double beta, double t, double mu, int32_t n_iw, double* bath_iw) {
+  if (!bath_iw || !(beta > 0) || !(t > 0) || !std::isfinite(mu) || n_iw < 1)
+    return fail(HFQMC_EINVAL, "bethe_lattice_bath: bad argument");
+  host::bethe_lattice(beta, t, mu, n_iw, bath_iw);
+  return HFQMC_OK;
+}
+
+extern "C" int bath_to_tau_m2(const double* bath_iw, int32_t n_iw, double m2, double m3,
+                              double beta, int32_t L, double* g_tau) {
+  if (!bath_iw || !g_tau || n_iw < 16 || L < 2 || !(beta > 0) || !std::isfinite(m2) ||
+      !std::isfinite(m3))
+    return fail(HFQMC_EINVAL, "bath_to_tau_m2: bad argument");
+  std::vector<double> tau(L);
+  for (int k = 0; k < L; ++k) tau[k] = k * (beta / L);
+  host::iw_to_tau(bath_iw, n_iw, m3, beta, tau.data(), L, g_tau, m2);
+  return HFQMC_OK;
+}
+
+// The multigrid step at any filling: the bath's tail moments m2, m3 enter its
+// transform onto every grid, and the reference model of step (i) is taken at
+// the finest grid's density n = G(beta-).
+extern "C" int multigrid_solve_n(hfqmc_ctx* c, const double* bath_iw, int32_t n_iw, double m2,
+                                 double m3, double U, double beta, const double* dtaus,
+                                 int32_t n_grids, uint64_t seed, const hfqmc_opts* opts,
+                                 int32_t n_fine, double* g_fine, double* g_fine_err, double* docc,
+                                 double* n_ref) {
+  if (!bath_iw || !dtaus || !g_fine) return fail(HFQMC_EINVAL, "multigrid_solve_n: null pointer");
+  if (n_grids < 3) return fail(HFQMC_EINVAL, "multigrid_solve_n: n_grids=%d < 3", n_grids);
+  if (n_fine < 4) return fail(HFQMC_EINVAL, "multigrid_solve_n: n_fine=%d < 4", n_fine);
+  if (n_iw < 16) return fail(HFQMC_EINVAL, "multigrid_solve_n: n_iw=%d < 16", n_iw);
+  if (!(beta > 0) || !(U >= 0) || !std::isfinite(m2) || !std::isfinite(m3))
+    return fail(HFQMC_EINVAL, "multigrid_solve_n: U=%g beta=%g m2=%g m3=%g", U, beta, m2, m3);
+  if (opts && (opts->flags & HFQMC_FLAG_PH_SYMMETRIC))
+    return fail(HFQMC_EINVAL, "multigrid_solve_n: HFQMC_FLAG_PH_SYMMETRIC needs half filling");
+  std::vector<int32_t> Ls(n_grids);
+  std::vector<double> dts(n_grids);
+  long long Lsum = 0, Psum = 0;
+  int finest = 0;
+  for (int i = 0; i < n_grids; ++i) {
+    if (!(dtaus[i] > 0)) return fail(HFQMC_EINVAL, "dtau[%d]=%g", i, dtaus[i]);
+    Ls[i] = (int32_t)std::lround(beta / dtaus[i]);
+    dts[i] = beta / Ls[i];
+    Lsum += Ls[i];
+    Psum += Ls[i] + 1;
+    if (Ls[i] > Ls[finest]) finest = i;
+  }
+  std::vector<double> g0(Lsum), gg(Psum), ge(Psum), dd(2 * (size_t)n_grids);
+  long long off = 0;
+  for (int i = 0; i < n_grids; ++i) {
+    int rc = bath_to_tau_m2(bath_iw, n_iw, m2, m3, beta, Ls[i], g0.data() + off);
+    if (rc) return rc;
+    off += Ls[i];
+  }
+  int rc = solve_grids_impl(c, n_grids, Ls.data(), g0.data(), U, beta, seed, opts, gg.data(),
+                            ge.data(), dd.data(), nullptr, Call());
+  if (rc) return rc;
+  off = 0;
+  long long off_finest = 0;
+  for (int i = 0; i < n_grids; ++i) {
+    if (i == finest) off_finest = off;
+    off += Ls[i] + 1;
+  }
+  const double n = gg[off_finest + Ls[finest]];   // G(beta-) of the finest grid
+  std::vector<double> tf(n_fine), gref_f(n_fine);
+  for (int j = 0; j < n_fine; ++j) tf[j] = j * (beta / (n_fine - 1));
+  host::reference_tau_n(bath_iw, n_iw, m2, m3, U, beta, n, tf.data(), n_fine, gref_f.data());
+  std::vector<double> gi((size_t)n_grids * n_fine), ei((size_t)n_grids * n_fine);
+  off = 0;
+  for (int i = 0; i < n_grids; ++i) {
+    const int L = Ls[i];
+    std::vector<double> tk(L + 1), gref_k(L + 1), d(L + 1);
+    for (int k = 0; k <= L; ++k) tk[k] = k * (beta / L);
+    host::reference_tau_n(bath_iw, n_iw, m2, m3, U, beta, n, tk.data(), L + 1, gref_k.data());
+    for (int k = 0; k <= L; ++k) d[k] = gg[off + k] - gref_k[k];
+    host::Spline sp(tk.data(), d.data(), L + 1);
+    for (int j = 0; j < n_fine; ++j) {
+      gi[(size_t)i * n_fine + j] = gref_f[j] + sp(tf[j]);
+      const double x = tf[j] / (beta / L);
+      int k0 = (int)std::floor(x);
+      if (k0 < 0) k0 = 0;
+      if (k0 > L - 1) k0 = L - 1;
+      const double fr = x - k0;
+      ei[(size_t)i * n_fine + j] = ge[off + k0] * (1.0 - fr) + ge[off + k0 + 1] * fr;
+    }
+    off += L + 1;
+  }
+  std::vector<double> err(n_fine);
+  host::extrapolate(dts.data(), n_grids, gi.data(), ei.data(), n_fine, g_fine, err.data());
+  if (g_fine_err) std::memcpy(g_fine_err, err.data(), sizeof(double) * n_fine);
+  if (docc) {
+    std::vector<double> dv(n_grids), de(n_grids);
+    for (int i = 0; i < n_grids; ++i) {
+      dv[i] = dd[2 * i];
+      de[i] = dd[2 * i + 1];
+    }
+    host::extrapolate(dts.data(), n_grids, dv.data(), de.data(), 1, &docc[0], &docc[1]);
+  }
+  if (n_ref) *n_ref = n;
+  return HFQMC_OK;
+}
+
+extern "C" int dmft_bethe_step_mu(const double* g_fine, int32_t n_fine, const double* bath_iw_prev,
+                                  int32_t n_iw, double m2, double m3, double U, double beta,
+                                  double t, double mu, double* bath_iw_new) {
+  if (!g_fine || !bath_iw_prev || !bath_iw_new) return fail(HFQMC_EINVAL, "dmft_bethe_step_mu: null pointer");
+  if (n_fine < 4 || n_iw < 16 || !(beta > 0) || !(t > 0) || !(U >= 0) || !std::isfinite(mu))
+    return fail(HFQMC_EINVAL, "dmft_bethe_step_mu: bad size or parameter");
+  for (int j = 0; j < n_fine; ++j)
+    if (!std::isfinite(g_fine[j])) return fail(HFQMC_EINVAL, "dmft_bethe_step_mu: g_fine[%d] not finite", j);
+  return host::bethe_step_n(g_fine, n_fine, bath_iw_prev, n_iw, m2, m3, U, beta, t, mu, bath_iw_new);
+}
+
+extern "C" int dmft_solve_mu(hfqmc_ctx* c, double U, double mu, double beta, double t,
+                             const double* dtaus, int32_t n_grids, uint64_t seed,
+                             const hfqmc_opts* opts, int32_t n_fine, int32_t n_iw, int32_t n_iter,
+                             double mixing, double* bath_iw, double* g_fine, double* g_fine_err,
+                             double* history) {
+  if (!bath_iw || !g_fine || !dtaus || !opts) return fail(HFQMC_EINVAL, "dmft_solve_mu: null pointer");
+  if (n_iter < 1) return fail(HFQMC_EINVAL, "dmft_solve_mu: n_iter=%d", n_iter);
+  if (!(mixing >= 0.0 && mixing < 1.0)) return fail(HFQMC_EINVAL, "dmft_solve_mu: mixing=%g", mixing);
+  if (!(t > 0) || !std::isfinite(mu)) return fail(HFQMC_EINVAL, "dmft_solve_mu: t=%g mu=%g", t, mu);
+  if (n_fine < 4 || n_iw < 16) return fail(HFQMC_EINVAL, "dmft_solve_mu: n_fine=%d n_iw=%d", n_fine, n_iw);
+  // the closure at mu keeps the bath's tail moments at -mu and mu^2 + t^2
+  const double m2 = -mu, m3 = mu * mu + t * t;
+  std::vector<double> prev(n_fine), err(n_fine), nb(2 * (size_t)n_iw);
+  {
+    std::vector<double> tf(n_fine);
+    for (int j = 0; j < n_fine; ++j) tf[j] = j * (beta / (n_fine - 1));
+    host::reference_tau_n(bath_iw, n_iw, m2, m3, 0.0, beta, 0.5, tf.data(), n_fine, prev.data());
+  }
+  for (int it = 0; it < n_iter; ++it) {
+    const uint64_t s_it = seed + ((uint64_t)it << 32);
+    double dx[2] = {0.0, 0.0};
+    int rc = multigrid_solve_n(c, bath_iw, n_iw, m2, m3, U, beta, dtaus, n_grids, s_it, opts, n_fine,
+                               g_fine, err.data(), dx, nullptr);
+    if (rc) return rc;
+    double dmax = 0.0, emax = 0.0;
+    for (int j = 0; j < n_fine; ++j) {
+      dmax = std::max(dmax, std::fabs(g_fine[j] - prev[j]));
+      emax = std::max(emax, err[j]);
+      prev[j] = g_fine[j];
+    }
+    if (history) {
+      history[5 * it] = dmax;
+      history[5 * it + 1] = emax;
+      history[5 * it + 2] = dx[0];
+      history[5 * it + 3] = dx[1];
+      history[5 * it + 4] = g_fine[n_fine - 1];   // n = G(beta-)
+    }
+    rc = host::bethe_step_n(g_fine, n_fine, bath_iw, n_iw, m2, m3, U, beta, t, mu, nb.data());
+    if (rc) return fail(rc, "dmft_solve_mu: Bethe step failed in iteration %d", it);
+    for (size_t q = 0; q < nb.size(); ++q) bath_iw[q] = mixing * bath_iw[q] + (1.0 - mixing) * nb[q];
+  }
+  if (g_fine_err) std::memcpy(g_fine_err, err.data(), sizeof(double) * n_fine);
+  return HFQMC_OK;
+}
+
 // The multigrid step with spin-dependent baths: one batched spin-resolved
 // launch over the grids, then for each spin the reference-model spline onto
 // the fine grid (that spin's bath in the reference) and the extrapolation.

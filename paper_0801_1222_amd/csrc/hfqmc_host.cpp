@@ -44,16 +44,18 @@ void atomic_seed(double beta, double t, double U, int n_iw, double* out) {
 }
 
 // Positive-convention G(tau) from Matsubara data with the tail
-// 1/(i w) + m3/(i w)^3 summed in closed form:
-//   G_std(tau) = -1/2 + m3 tau (beta - tau)/4 + (2/beta) sum_n Re[e^{-i w tau} rem_n]
+// 1/(i w) + m2/(i w)^2 + m3/(i w)^3 summed in closed form:
+//   G_std(tau) = -1/2 + m2 (2 tau - beta)/4 + m3 tau (beta - tau)/4
+//                + (2/beta) sum_n Re[e^{-i w tau} rem_n]
+// (m2 = 0 at half filling).
 void iw_to_tau(const double* f_iw, int n_iw, double m3, double beta, const double* tau, int n_tau,
-               double* out) {
+               double* out, double m2) {
   std::vector<double> rr(n_iw), ri(n_iw), w(n_iw);
   for (int n = 0; n < n_iw; ++n) {
     w[n] = matsubara(beta, n);
     const cd iw(0.0, w[n]);
     const cd f(f_iw[2 * n], f_iw[2 * n + 1]);
-    const cd rem = f - 1.0 / iw - m3 / (iw * iw * iw);
+    const cd rem = f - 1.0 / iw - m2 / (iw * iw) - m3 / (iw * iw * iw);
     rr[n] = rem.real();
     ri[n] = rem.imag();
   }
@@ -65,7 +67,8 @@ void iw_to_tau(const double* f_iw, int n_iw, double m3, double beta, const doubl
       const double ph = w[n] * ta;
       s += std::cos(ph) * rr[n] + std::sin(ph) * ri[n];
     }
-    const double g_std = -0.5 + m3 * ta * (beta - ta) / 4.0 + 2.0 / beta * s;
+    const double g_std =
+        -0.5 + m2 * (2.0 * ta - beta) / 4.0 + m3 * ta * (beta - ta) / 4.0 + 2.0 / beta * s;
     out[a] = -g_std;
   }
 }
@@ -211,6 +214,74 @@ int bethe_step(const double* g_fine, int n_fine, const double* bath_prev, int n_
     const cd iw(0.0, matsubara(beta, q));
     const cd G = cd(ref[2 * q], ref[2 * q + 1]) - cd(ft[2 * q], ft[2 * q + 1]);
     const cd nb = 1.0 / (iw - t * t * G);
+    bath_new[2 * q] = nb.real();
+    bath_new[2 * q + 1] = nb.imag();
+  }
+  return 0;
+}
+
+// ---------------------------------------------- away from half filling ----
+// The closing remarks of the paper state the method's generality; the readings
+// for other fillings: the bath's tail carries a 1/(i w)^2 moment m2; the Bethe
+// closure has a chemical potential mu measured from half filling,
+// bath = 1/(i w + mu - t^2 G) (tail moments -mu, mu^2 + t^2); the reference
+// model at density n per spin is 1/(1/bath - s0 - s1/(i w)) with the first two
+// high-frequency terms of the self-energy of U (n_up n_dn - (n_up + n_dn)/2),
+// s0 = U (n - 1/2) and s1 = U^2 n (1 - n), which at n = 1/2 is the half-filled
+// reference above.
+
+// Noninteracting Bethe-lattice G at chemical potential mu, z = i w + mu:
+// (z - sqrt(z - 2t) sqrt(z + 2t)) / (2 t^2), principal roots (G ~ 1/z), written
+// 2 / (z + sqrt(z - 2t) sqrt(z + 2t)) to avoid the cancellation at large |z|.
+void bethe_lattice(double beta, double t, double mu, int n_iw, double* out) {
+  for (int n = 0; n < n_iw; ++n) {
+    const cd z(mu, matsubara(beta, n));
+    const cd g = 2.0 / (z + std::sqrt(z - 2.0 * t) * std::sqrt(z + 2.0 * t));
+    out[2 * n] = g.real();
+    out[2 * n + 1] = g.imag();
+  }
+}
+
+void reference_iw_n(const double* bath_iw, int n_iw, double U, double beta, double n, double* out) {
+  const double s0 = U * (n - 0.5), s1 = U * U * n * (1.0 - n);
+  for (int q = 0; q < n_iw; ++q) {
+    const cd iw(0.0, matsubara(beta, q));
+    const cd b(bath_iw[2 * q], bath_iw[2 * q + 1]);
+    const cd r = 1.0 / (1.0 / b - s0 - s1 / iw);
+    out[2 * q] = r.real();
+    out[2 * q + 1] = r.imag();
+  }
+}
+
+// With 1/bath = i w - m2 + (m2^2 - m3)/(i w) + ..., the reference's tail moments
+// are M2 = m2 + s0 and M3 = M2^2 - (m2^2 - m3 - s1).
+void reference_tau_n(const double* bath_iw, int n_iw, double m2, double m3, double U, double beta,
+                     double n, const double* tau, int n_tau, double* out) {
+  const double s0 = U * (n - 0.5), s1 = U * U * n * (1.0 - n);
+  const double M2 = m2 + s0;
+  const double M3 = M2 * M2 - (m2 * m2 - m3 - s1);
+  std::vector<double> r(2 * (size_t)n_iw);
+  reference_iw_n(bath_iw, n_iw, U, beta, n, r.data());
+  iw_to_tau(r.data(), n_iw, M3, beta, tau, n_tau, out, M2);
+}
+
+// The closure at mu: G(i w) = G_ref(i w) - FT[spline(G - G_ref)], the reference at
+// the density n = G(beta-) of g_fine, then 1/(i w + mu - t^2 G(i w)).
+int bethe_step_n(const double* g_fine, int n_fine, const double* bath_prev, int n_iw, double m2,
+                 double m3, double U, double beta, double t, double mu, double* bath_new) {
+  const double n = g_fine[n_fine - 1];
+  std::vector<double> tau(n_fine), gref(n_fine), diff(n_fine);
+  for (int j = 0; j < n_fine; ++j) tau[j] = j * (beta / (n_fine - 1));
+  reference_tau_n(bath_prev, n_iw, m2, m3, U, beta, n, tau.data(), n_fine, gref.data());
+  for (int j = 0; j < n_fine; ++j) diff[j] = g_fine[j] - gref[j];
+  Spline sp(tau.data(), diff.data(), n_fine);
+  std::vector<double> ft(2 * (size_t)n_iw), ref(2 * (size_t)n_iw);
+  sp.fourier(beta, n_iw, ft.data());
+  reference_iw_n(bath_prev, n_iw, U, beta, n, ref.data());
+  for (int q = 0; q < n_iw; ++q) {
+    const cd iw(0.0, matsubara(beta, q));
+    const cd G = cd(ref[2 * q], ref[2 * q + 1]) - cd(ft[2 * q], ft[2 * q + 1]);
+    const cd nb = 1.0 / (iw + mu - t * t * G);
     bath_new[2 * q] = nb.real();
     bath_new[2 * q + 1] = nb.imag();
   }

@@ -11,7 +11,7 @@ double matsubara(double beta, int n);
 void semicircle(double beta, double t, int n_iw, double* out);
 void atomic_seed(double beta, double t, double U, int n_iw, double* out);
 void iw_to_tau(const double* f_iw, int n_iw, double m3, double beta, const double* tau, int n_tau,
-               double* out);
+               double* out, double m2 = 0.0);
 void reference_iw(const double* bath_iw, int n_iw, double U, double beta, double* out);
 void reference_tau(const double* bath_iw, int n_iw, double m3, double U, double beta,
                    const double* tau, int n_tau, double* out);
@@ -19,6 +19,13 @@ void extrapolate(const double* dtaus, int n_grids, const double* g, const double
                  double* c0, double* err);
 int bethe_step(const double* g_fine, int n_fine, const double* bath_prev, int n_iw, double m3,
                double U, double beta, double t, double* bath_new);
+// away from half filling
+void bethe_lattice(double beta, double t, double mu, int n_iw, double* out);
+void reference_iw_n(const double* bath_iw, int n_iw, double U, double beta, double n, double* out);
+void reference_tau_n(const double* bath_iw, int n_iw, double m2, double m3, double U, double beta,
+                     double n, const double* tau, int n_tau, double* out);
+int bethe_step_n(const double* g_fine, int n_fine, const double* bath_prev, int n_iw, double m2,
+                 double m3, double U, double beta, double t, double mu, double* bath_new);
 
 class Spline {
  public:

@@ -20,6 +20,7 @@ import pytest
 
 from oracle import bath as OB
 from oracle import hfqmc as OH
+from stat_checks import compare_3sigma
 
 pytestmark = pytest.mark.gpu
 
@@ -39,16 +40,6 @@ def _bath(beta, L, t=1.0):
 
 def _codes(ref, L):
     return [sw * L + l for sw, l in ref["flips"]]
-
-
-def compare_3sigma(a, ea, b, eb, frac=0.01):
-    """Reading of 'within 3 sigma': |a - b| <= 3 sqrt(ea^2 + eb^2) per point, at
-    most `frac` of the points beyond, none beyond 5 sigma.  Returns the z-scores."""
-    z = np.abs(np.asarray(a) - np.asarray(b)) / np.sqrt(np.asarray(ea) ** 2 + np.asarray(eb) ** 2)
-    assert np.all(np.isfinite(z)), z
-    assert z.max() < 5.0, (z.max(), int(np.argmax(z)))
-    assert np.mean(z > 3.0) <= frac, (np.mean(z > 3.0), np.sort(z)[-5:])
-    return z
 
 
 @pytest.mark.parametrize("mode,k", [("rank1", 0), ("delayed", 32)])

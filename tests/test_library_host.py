@@ -80,3 +80,23 @@ def test_host_argument_errors():
         P.dmft_bethe_step(np.zeros(3), np.zeros(100, dtype=complex), 1.0, 0.0, 10.0, 1.0)
     with pytest.raises(P.HFQMCError):
         P.bethe_atomic_bath(10.0, 1.0, -1.0, 100)                  # U < 0
+
+
+def test_general_filling_host_routines_match_oracle():
+    # away from half filling: the lattice bath at mu, the transform with the 1/(i w)^2
+    # moment and the closure at mu (reference model at the density G(beta-))
+    import paper_0801_1222_amd as P
+    beta, t, U = 10.0, 1.0, 2.5
+    for mu in (0.6, -0.9):
+        b = P.bethe_lattice_bath(beta, t, mu, 4000)
+        bo = OB.bethe_lattice_iw(beta, t, mu, 4000)
+        assert np.abs(b - bo).max() < 1e-14
+        g = P.bath_to_tau_m2(b, -mu, mu * mu + t * t, beta, 57)
+        assert np.abs(g - OB.bath_to_tau(bo, mu * mu + t * t, beta, 57, m2=-mu)).max() < 1e-12
+        tau = OMG.fine_grid(beta, 101)
+        # an interacting-looking G: the reference model at n plus a smooth bump
+        gf = OMG.reference_tau_n(bo, -mu, mu * mu + t * t, U, beta, tau, 0.55) \
+            + 1e-3 * np.sin(np.pi * tau / beta)
+        new = P.dmft_bethe_step_mu(gf, b, -mu, mu * mu + t * t, U, beta, t, mu)
+        ref = OMG.dmft_bethe_step_n(gf, tau, bo, -mu, mu * mu + t * t, U, beta, t, mu)
+        assert np.abs(new - ref).max() < 1e-11
