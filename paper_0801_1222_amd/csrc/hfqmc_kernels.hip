@@ -1272,7 +1272,7 @@ __device__ __forceinline__ double dyson_solve(const Chain& ch, int sigma, GT* Gs
         for (int rb = wv; rb < nrb; rb += kThreads / 64) {
           // one 16-row block of R against every tile of the chunk; the A operand
           // is prefetched a batch of kGB steps ahead (two register batches in turn)
-          constexpr int kGB = 16;
+          constexpr int kGB = 8;
           const int arow = min(rb * 16 + li, nR - 1);
           const double2* arow2 = reinterpret_cast<const double2*>(Aq + (long long)arow * kr + lq * ks);
           int orow[4], oR[4];
