@@ -313,9 +313,10 @@ RANGES = {"[0.2,0.5]": [0.2, 0.25, 0.3, 0.4, 0.5],
           "[0.35,0.8]": [0.35, 0.45, 0.55, 0.65, 0.8]}
 
 
-def _cycle_opts(args, mode):
+def _cycle_opts(args, mode, balance=False):
     return dict(n_chains=args.chains, warmup=args.chain_warmup, sweeps=args.chain_sweeps,
-                mode=mode, delay_k=args.delay_k if mode != "rank1" else 0, ph=not args.two_matrix)
+                mode=mode, delay_k=args.delay_k if mode != "rank1" else 0, ph=not args.two_matrix,
+                balance=balance)
 
 
 def workload_c5(args):
@@ -335,11 +336,14 @@ def workload_c5(args):
         st = dict(beta=beta, U=U, iterations=0, history=[])
     ctx = P.Context(0)
     mode = args.mode
-    kw = _cycle_opts(args, mode)
+    kw = _cycle_opts(args, mode, balance=not args.no_balance)
     Ls = [int(round(beta / d)) for d in C5_DTAUS]
-    progress("c5: beta=%g U=%g L=%s, %d chains x (%d+%d) sweeps per grid and iteration, mode %s%s"
-             % (beta, U, Ls, kw["n_chains"], kw["warmup"], kw["sweeps"], mode,
-                ", single-matrix form" if kw["ph"] else ""))
+    # the split the library plans for one workgroup per CU (256 on MI355X)
+    split = (P.hfqmc_plan_balance(Ls, kw["n_chains"], kw["warmup"], kw["sweeps"], 1, 256)["factor"]
+             if kw["balance"] else [1] * len(Ls))
+    progress("c5: beta=%g U=%g L=%s, %d chains x (%d+%d) sweeps per grid and iteration, mode %s%s, "
+             "chain split %s" % (beta, U, Ls, kw["n_chains"], kw["warmup"], kw["sweeps"], mode,
+                                 ", single-matrix form" if kw["ph"] else "", split))
     for _ in range(args.iterations):
         it = st["iterations"]
         t0 = time.perf_counter()
@@ -349,24 +353,32 @@ def workload_c5(args):
         bath = r["bath"]
         h = r["history"][0]
         g = r["g"]
+        # the change of G(tau) against the previous iteration (a call of one
+        # iteration measures against the bath's own G0(tau), kept as max_dg_bath)
+        prev = st.get("g_prev")
+        max_dg = float(np.abs(g - np.array(prev)).max()) if prev is not None else None
         rec = dict(workload="c5", iteration=it, U=U, beta=beta, Ls=Ls, D=float(h[2]),
-                   D_err=float(h[3]), max_dg=float(h[0]), max_g_err=float(h[1]),
+                   D_err=float(h[3]), max_dg=max_dg, max_dg_bath=float(h[0]),
+                   max_g_err=float(h[1]),
                    g_beta_half=float(g[(n_fine - 1) // 2]),
                    g_beta_half_err=float(r["g_err"][(n_fine - 1) // 2]), seconds=dt,
-                   chains=kw["n_chains"], warmup=kw["warmup"], sweeps=kw["sweeps"], mode=mode,
+                   chains=kw["n_chains"], warmup=kw["warmup"], sweeps=kw["sweeps"],
+                   chain_split=split, mode=mode,
                    single_matrix=kw["ph"], mixing=args.mixing)
         st["history"].append(rec)
         st["iterations"] = it + 1
         st["bath_re"] = bath.real.tolist()
         st["bath_im"] = bath.imag.tolist()
+        st["g_prev"] = g.tolist()
         if args.state:
             tmp = args.state + ".tmp"
             with open(tmp, "w") as f:
                 json.dump(st, f)
             os.replace(tmp, args.state)
         print(json.dumps(rec), flush=True)
-        progress("c5 iteration %d: D = %.5f(%d), max |dG| %.2e, %.0f s"
-                 % (it, rec["D"], round(rec["D_err"] * 1e5), rec["max_dg"], dt))
+        progress("c5 iteration %d: D = %.5f(%d), max |dG| vs previous %s, %.0f s"
+                 % (it, rec["D"], round(rec["D_err"] * 1e5),
+                    "%.2e" % max_dg if max_dg is not None else "-", dt))
     ctx.close()
     hist = st["history"]
     print(json.dumps(dict(workload="c5", summary=True, iterations=st["iterations"],
@@ -441,6 +453,8 @@ def main():
     ap.add_argument("--chains", type=int, default=None)
     ap.add_argument("--mixing", type=float, default=0.5)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-balance", action="store_true",
+                    help="c5: every grid runs its chains end to end (no chain split)")
     ap.add_argument("--two-matrix", action="store_true",
                     help="c5 / range-scan: both Green matrices (default: single-matrix form)")
     args = ap.parse_args()

@@ -89,7 +89,17 @@ enum {
                                 recompute still compute in FP64, from the FP32-stored values;
                                 each flush and each recompute rounds its result to FP32 when
                                 storing it (the reduced recompute's product reads the solved
-                                rows back in that form) */
+                                rows back in that form) */,
+  HFQMC_FLAG_BALANCE = 32    /* batched launches of uneven grids: a grid whose chains would
+                                set the launch's length runs n_chains * f chains of
+                                sweeps / f measured sweeps each (f a power of two up to 64
+                                dividing sweeps, sweeps / f >= n_bins), every chain with its
+                                own warm-up: the same number of measurements per grid, spread
+                                over more workgroups.  f per grid from hfqmc_plan_balance with
+                                the device's workgroup count; chain c of a grid keeps the
+                                Philox key (seed + c, grid), c now up to n_chains * f - 1.
+                                EINVAL with any per-chain test hook (flip_log, replay_log,
+                                chain_*, final_green) */
 };
 
 typedef struct {
@@ -155,7 +165,9 @@ typedef struct {
   double seconds_autotune;  /* time spent in trial launches during this call (0 on a cache hit) */
   int64_t n_reduced_rows;   /* sum over reduced-form recomputes of the system size |S| */
   int32_t recompute_reduced;/* 1: reduced form (see hfqmc_solve), 0: full-size LU */
-  int32_t reserved;
+  int32_t chain_split;      /* HFQMC_FLAG_BALANCE: the grid's chain-split factor f (its
+                               chains ran sweeps / f measured sweeps each, n_chains * f of
+                               them; the largest f in a launch's total); 1 otherwise */
   double chain_s_lu_gemm;   /* recompute breakdown: the reduced form's GEMM (chain-seconds) */
   double chain_s_flush_vectors, chain_s_flush_gemm;  /* flush breakdown: X, Y and G += X Y */
   /* delayed-update breakdown (chain-seconds, part of chain_s_flush): opening a
@@ -247,6 +259,27 @@ int hfqmc_solve_spin(hfqmc_ctx *ctx, const double *g0_up, const double *g0_dn, i
 int hfqmc_solve_grids(hfqmc_ctx *ctx, int32_t n_grids, const int32_t *L, const double *g0_tau,
                       double U, double beta, uint64_t seed, const hfqmc_opts *opts,
                       double *g_tau, double *g_err, double *docc, hfqmc_stats *stats);
+
+/* Chain-split plan of HFQMC_FLAG_BALANCE (host only: callable without a GPU).
+ * The multigrid method averages independent impurity solutions per grid and
+ * runs every grid of a step side by side (Multigrid HF-QMC method), while the
+ * effort per sweep grows like dtau^-3 (Introduction): the long grids' chains
+ * then set a batched launch's length.  Models the launch as units (grid i,
+ * chain c) of cost (warmup + sweeps_i) L[i]^3, dispatched longest first to
+ * n_workgroups workers (the sweep kernel's queue).  It scores every
+ * threshold plan (for a target unit length, each grid split just enough for
+ * its units to fit under it), then moves one grid's factor up or down, or
+ * doubles the factors of all grids whose units are at least as long as a given
+ * grid's, while the simulated makespan falls by more than 0.5 % (equal spans:
+ * fewer chains); f_i stays a power of two <= 64 dividing sweeps with
+ * sweeps / f_i >= n_bins, and all f_i are 1 when no split shortens the span.  factor[n_grids] receives f_i; span (may be NULL)
+ * receives the makespan without and with the split, in units of one sweep at
+ * L = 1 (cost-model units).  EINVAL for n_grids < 1, NULL L or factor,
+ * n_chains outside 1..2^20-1, warmup < 0, sweeps < 1, n_bins outside
+ * 1..sweeps, n_workgroups < 1 or L outside 2..4096. */
+int hfqmc_plan_balance(int32_t n_grids, const int32_t *L, int32_t n_chains, int64_t warmup,
+                       int64_t sweeps, int32_t n_bins, int32_t n_workgroups, int32_t *factor,
+                       double *span);
 
 /* Achievable peaks of the context's device, the ceilings next to the
  * datasheet ones that the sweep kernel's roofline is quoted against (the

@@ -49,14 +49,14 @@ class Stats(C.Structure):
         ("chain_s_lu_back", _f64),
         ("delay_k", _i32), ("recompute_every", _i32), ("n_workgroups", _i32), ("lu_panel", _i32),
         ("graph", _i32), ("autotuned", _i32), ("seconds_autotune", _f64),
-        ("n_reduced_rows", _i64), ("recompute_reduced", _i32), ("reserved", _i32),
+        ("n_reduced_rows", _i64), ("recompute_reduced", _i32), ("chain_split", _i32),
         ("chain_s_lu_gemm", _f64), ("chain_s_flush_vectors", _f64), ("chain_s_flush_gemm", _f64),
         ("chain_s_window_apply", _f64), ("chain_s_fold", _f64), ("seconds_sweep_kernel", _f64),
         ("max_drift_gtau", _f64),
     ]
 
     def as_dict(self):
-        return {name: getattr(self, name) for name, _ in self._fields_ if name != "reserved"}
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class Peaks(C.Structure):
@@ -123,6 +123,8 @@ lib.dmft_bethe_step_mu.restype = C.c_int
 lib.dmft_solve_mu.argtypes = [_ctx_p, _f64, _f64, _f64, _f64, _pd, _i32, _u64, C.POINTER(Opts),
                               _i32, _i32, _i32, _f64, _pd, _pd, _pd, _pd]
 lib.dmft_solve_mu.restype = C.c_int
+lib.hfqmc_plan_balance.argtypes = [_i32, _pi32, _i32, _i64, _i64, _i32, _i32, _pi32, _pd]
+lib.hfqmc_plan_balance.restype = C.c_int
 lib.hfqmc_measure_peaks.argtypes = [_ctx_p, C.POINTER(Peaks)]
 lib.hfqmc_measure_peaks.restype = C.c_int
 
@@ -131,13 +133,14 @@ FLAG_HEAT_BATH = 2   # heat-bath acceptance u < R/(1+R)
 FLAG_DIRECT_RECOMPUTE = 4  # full-size LU recompute instead of the reduced system
 FLAG_PH_SYMMETRIC = 8      # particle-hole symmetric bath: only G_up stored (G_dn = 1 - G_up^T)
 FLAG_G_FP32 = 16           # mixed mode: G stored in FP32 between recomputes
+FLAG_BALANCE = 32          # split long grids' chains over more workgroups (same measurements)
 
 EXPORTED = ["hfqmc_create", "hfqmc_destroy", "hfqmc_set_stream", "hfqmc_last_error",
             "hfqmc_solve", "hfqmc_solve_spin", "hfqmc_solve_dev", "hfqmc_solve_grids", "multigrid_solve", "dmft_bethe_step",
             "bethe_semicircle_bath", "bethe_atomic_bath", "bath_to_tau", "hfqmc_measure_peaks", "dmft_solve",
             "multigrid_solve_spin", "dmft_solve_af", "hfqmc_solve_dev_noalloc",
             "bethe_lattice_bath", "bath_to_tau_m2", "multigrid_solve_n", "dmft_bethe_step_mu",
-            "dmft_solve_mu"]
+            "dmft_solve_mu", "hfqmc_plan_balance"]
 
 
 def ptr(a, ctype=C.c_double):

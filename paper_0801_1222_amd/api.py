@@ -61,10 +61,11 @@ class Context:
             pass
 
 
-def _flags(eager=False, heat_bath=False, direct=False, ph=False, g_fp32=False):
+def _flags(eager=False, heat_bath=False, direct=False, ph=False, g_fp32=False, balance=False):
     return ((N.FLAG_EAGER if eager else 0) | (N.FLAG_HEAT_BATH if heat_bath else 0)
             | (N.FLAG_DIRECT_RECOMPUTE if direct else 0)
-            | (N.FLAG_PH_SYMMETRIC if ph else 0) | (N.FLAG_G_FP32 if g_fp32 else 0))
+            | (N.FLAG_PH_SYMMETRIC if ph else 0) | (N.FLAG_G_FP32 if g_fp32 else 0)
+            | (N.FLAG_BALANCE if balance else 0))
 
 
 def _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drift_limit, flags=0,
@@ -157,12 +158,12 @@ class _Hooks:
 def hfqmc_solve(ctx, g0_tau, U, beta, dtau, seed, n_chains=1, warmup=0, sweeps=1,
                 mode="rank1", recompute_every=0, delay_k=0, n_bins=0, drift_limit=0.0, drift_every=0,
                 flip_cap=0, replay=None, want_chain=False, want_green=False, eager=False,
-                heat_bath=False, direct=False, ph=False, g_fp32=False):
+                heat_bath=False, direct=False, ph=False, g_fp32=False, balance=False):
     """Fixed-dtau solve; returns dict(g, g_err, D, D_err, stats, [hooks])."""
     g0 = np.ascontiguousarray(g0_tau, dtype=np.float64)
     L = g0.shape[0]
     o = _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drift_limit,
-              _flags(eager, heat_bath, direct, ph, g_fp32), drift_every=drift_every)
+              _flags(eager, heat_bath, direct, ph, g_fp32, balance), drift_every=drift_every)
     hk = _Hooks(o, 1, n_chains, [L], n_bins, flip_cap,
                 [replay] if replay is not None else None, want_chain, want_green)
     g = np.zeros(L + 1)
@@ -187,7 +188,7 @@ def hfqmc_solve(ctx, g0_tau, U, beta, dtau, seed, n_chains=1, warmup=0, sweeps=1
 def hfqmc_solve_spin(ctx, g0_up, g0_dn, U, beta, dtau, seed, n_chains=1, warmup=0, sweeps=1,
                      mode="rank1", recompute_every=0, delay_k=0, n_bins=0, drift_limit=0.0, drift_every=0,
                      flip_cap=0, replay=None, want_chain=False, want_green=False, eager=False,
-                     heat_bath=False, direct=False):
+                     heat_bath=False, direct=False, balance=False):
     """Fixed-dtau solve with spin-dependent baths; returns dict(g_up, g_dn,
     err_up, err_dn, D, D_err, stats, [hooks]); chain_g is [n_chains][n_bins][2][L+1]."""
     gu = np.ascontiguousarray(g0_up, dtype=np.float64)
@@ -196,7 +197,7 @@ def hfqmc_solve_spin(ctx, g0_up, g0_dn, U, beta, dtau, seed, n_chains=1, warmup=
         raise ValueError("g0_up and g0_dn differ in length")
     L = gu.shape[0]
     o = _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drift_limit,
-              _flags(eager, heat_bath, direct), drift_every=drift_every)
+              _flags(eager, heat_bath, direct, balance=balance), drift_every=drift_every)
     hk = _Hooks(o, 1, n_chains, [L], n_bins, flip_cap,
                 [replay] if replay is not None else None, want_chain, want_green, spins=2)
     g = np.zeros(2 * (L + 1))
@@ -220,11 +221,11 @@ def hfqmc_solve_spin(ctx, g0_up, g0_dn, U, beta, dtau, seed, n_chains=1, warmup=
 def hfqmc_solve_dev(ctx, g0_tau, L, U, beta, dtau, seed, g_tau, g_err=None, docc=None,
                     n_chains=1, warmup=0, sweeps=1, mode="rank1", recompute_every=0, delay_k=0,
                     n_bins=0, drift_limit=0.0, drift_every=0, eager=False, heat_bath=False, direct=False,
-                    ph=False, g_fp32=False):
+                    ph=False, g_fp32=False, balance=False):
     """hfqmc_solve on device buffers (raw device addresses as ints, e.g. a torch
     tensor's data_ptr(), on the context's device and stream); returns the stats."""
     o = _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drift_limit,
-              _flags(eager, heat_bath, direct, ph, g_fp32), drift_every=drift_every)
+              _flags(eager, heat_bath, direct, ph, g_fp32, balance), drift_every=drift_every)
     st = N.Stats()
     rc = N.lib.hfqmc_solve_dev(ctx.handle, C.c_void_p(int(g0_tau)), int(L), float(U), float(beta),
                                float(dtau), int(seed), C.byref(o), C.c_void_p(int(g_tau)),
@@ -252,6 +253,19 @@ def hfqmc_solve_dev_noalloc(ctx, g0_tau, L, U, beta, dtau, seed, g_tau, g_err=No
     return st.as_dict()
 
 
+def hfqmc_plan_balance(Ls, n_chains, warmup, sweeps, n_bins, n_workgroups):
+    """Chain-split factors of a batched launch (host only): dict(factor, span_before,
+    span_after), spans in the planner's cost units."""
+    L = np.ascontiguousarray(Ls, dtype=np.int32)
+    f = np.zeros(L.shape[0], dtype=np.int32)
+    sp = np.zeros(2)
+    rc = N.lib.hfqmc_plan_balance(L.shape[0], N.ptr(L, C.c_int32), int(n_chains), int(warmup),
+                                  int(sweeps), int(n_bins), int(n_workgroups),
+                                  N.ptr(f, C.c_int32), N.ptr(sp))
+    N.check(rc, "hfqmc_plan_balance")
+    return dict(factor=f.tolist(), span_before=float(sp[0]), span_after=float(sp[1]))
+
+
 def hfqmc_measure_peaks(ctx):
     """Achievable HBM bandwidth (GB/s) and matrix-core / FMA rates (TFLOP/s)
     of the context's device, from the library's probe kernels."""
@@ -263,7 +277,7 @@ def hfqmc_measure_peaks(ctx):
 def hfqmc_solve_grids(ctx, Ls, g0_taus, U, beta, seed, n_chains=1, warmup=0, sweeps=1,
                       mode="rank1", recompute_every=0, delay_k=0, n_bins=0, drift_limit=0.0, drift_every=0,
                       flip_cap=0, replay=None, want_chain=False, eager=False, heat_bath=False,
-                      direct=False, ph=False, g_fp32=False):
+                      direct=False, ph=False, g_fp32=False, balance=False):
     """Several grids in one persistent launch; per-grid lists in the result."""
     Ls = [int(L) for L in Ls]
     n = len(Ls)
@@ -271,7 +285,7 @@ def hfqmc_solve_grids(ctx, Ls, g0_taus, U, beta, seed, n_chains=1, warmup=0, swe
     g0 = np.ascontiguousarray(np.concatenate([np.asarray(x, dtype=np.float64) for x in g0_taus]))
     assert g0.shape[0] == sum(Ls)
     o = _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drift_limit,
-              _flags(eager, heat_bath, direct, ph, g_fp32), drift_every=drift_every)
+              _flags(eager, heat_bath, direct, ph, g_fp32, balance), drift_every=drift_every)
     hk = _Hooks(o, n, n_chains, Ls, n_bins, flip_cap, replay, want_chain, False)
     P = sum(L + 1 for L in Ls)
     g = np.zeros(P)
@@ -296,13 +310,13 @@ def hfqmc_solve_grids(ctx, Ls, g0_taus, U, beta, seed, n_chains=1, warmup=0, swe
 def multigrid_solve(ctx, bath_iw, bath_m3, U, beta, dtaus, seed, n_fine=200, n_chains=1,
                     warmup=0, sweeps=1, mode="rank1", recompute_every=0, delay_k=0, n_bins=0,
                     drift_limit=0.0, drift_every=0, eager=False, heat_bath=False, direct=False,
-                    ph=False, g_fp32=False):
+                    ph=False, g_fp32=False, balance=False):
     """dtau -> 0 extrapolated G(tau_j), tau_j = j beta/(n_fine-1)."""
     b = np.ascontiguousarray(np.asarray(bath_iw, dtype=np.complex128)).view(np.float64)
     n_iw = b.shape[0] // 2
     dt = np.ascontiguousarray(dtaus, dtype=np.float64)
     o = _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drift_limit,
-              _flags(eager, heat_bath, direct, ph, g_fp32), drift_every=drift_every)
+              _flags(eager, heat_bath, direct, ph, g_fp32, balance), drift_every=drift_every)
     Ls = [int(round(beta / x)) for x in dt]
     gf = np.zeros(n_fine)
     ef = np.zeros(n_fine)
@@ -327,7 +341,7 @@ def multigrid_solve(ctx, bath_iw, bath_m3, U, beta, dtaus, seed, n_fine=200, n_c
 def dmft_solve(ctx, U, beta, t, dtaus, seed, n_iter, bath_iw=None, n_iw=4096, n_fine=200,
                mixing=0.0, n_chains=1, warmup=0, sweeps=1, mode="rank1", recompute_every=0,
                delay_k=0, n_bins=0, drift_limit=0.0, drift_every=0, eager=False, heat_bath=False, direct=False,
-               ph=False, g_fp32=False):
+               ph=False, g_fp32=False, balance=False):
     """Multigrid DMFT cycle on the Bethe lattice; starts from bath_iw (default:
     the U = 0 semicircle).  Returns dict(bath, g, g_err, tau, history) with
     history[it] = (max |g - g_prev|, max g_err, D, D_err), D the extrapolated
@@ -338,7 +352,7 @@ def dmft_solve(ctx, U, beta, t, dtaus, seed, n_iter, bath_iw=None, n_iw=4096, n_
     n_iw = b.shape[0] // 2
     dt = np.ascontiguousarray(dtaus, dtype=np.float64)
     o = _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drift_limit,
-              _flags(eager, heat_bath, direct, ph, g_fp32), drift_every=drift_every)
+              _flags(eager, heat_bath, direct, ph, g_fp32, balance), drift_every=drift_every)
     gf = np.zeros(n_fine)
     ef = np.zeros(n_fine)
     hist = np.zeros(4 * int(n_iter))
@@ -353,7 +367,7 @@ def dmft_solve(ctx, U, beta, t, dtaus, seed, n_iter, bath_iw=None, n_iw=4096, n_
 def multigrid_solve_spin(ctx, bath_up, bath_dn, bath_m3, U, beta, dtaus, seed, n_fine=200,
                          n_chains=1, warmup=0, sweeps=1, mode="rank1", recompute_every=0,
                          delay_k=0, n_bins=0, drift_limit=0.0, drift_every=0, eager=False, heat_bath=False,
-                         direct=False):
+                         direct=False, balance=False):
     """multigrid_solve with spin-dependent baths: dict(g [2, n_fine] (up, down),
     g_err, tau, D, D_err)."""
     bu = np.ascontiguousarray(np.asarray(bath_up, dtype=np.complex128)).view(np.float64)
@@ -362,7 +376,7 @@ def multigrid_solve_spin(ctx, bath_up, bath_dn, bath_m3, U, beta, dtaus, seed, n
         raise ValueError("bath_up and bath_dn differ in length")
     dt = np.ascontiguousarray(dtaus, dtype=np.float64)
     o = _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drift_limit,
-              _flags(eager, heat_bath, direct), drift_every=drift_every)
+              _flags(eager, heat_bath, direct, balance=balance), drift_every=drift_every)
     gf = np.zeros(2 * n_fine)
     ef = np.zeros(2 * n_fine)
     dx = np.zeros(2)
@@ -377,7 +391,7 @@ def multigrid_solve_spin(ctx, bath_up, bath_dn, bath_m3, U, beta, dtaus, seed, n
 
 def dmft_solve_af(ctx, U, beta, t, dtaus, seed, n_iter, bath_up, bath_dn, n_fine=200, mixing=0.0,
                   n_chains=1, warmup=0, sweeps=1, mode="rank1", recompute_every=0, delay_k=0,
-                  n_bins=0, drift_limit=0.0, drift_every=0, eager=False, heat_bath=False, direct=False):
+                  n_bins=0, drift_limit=0.0, drift_every=0, eager=False, heat_bath=False, direct=False, balance=False):
     """Neel-order DMFT cycle on the Bethe lattice from the given spin baths;
     returns dict(baths (up, down), g [2, n_fine], g_err, tau, history [n_iter, 5])
     with history[it] = (max |g change|, max g_err, D, D_err, n_up - n_dn)."""
@@ -387,7 +401,7 @@ def dmft_solve_af(ctx, U, beta, t, dtaus, seed, n_iter, bath_up, bath_dn, n_fine
         raise ValueError("bath_up and bath_dn differ in length")
     dt = np.ascontiguousarray(dtaus, dtype=np.float64)
     o = _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drift_limit,
-              _flags(eager, heat_bath, direct), drift_every=drift_every)
+              _flags(eager, heat_bath, direct, balance=balance), drift_every=drift_every)
     gf = np.zeros(2 * n_fine)
     ef = np.zeros(2 * n_fine)
     hist = np.zeros(5 * int(n_iter))
@@ -455,12 +469,12 @@ def bath_to_tau_m2(bath_iw, m2, m3, beta, L):
 
 def multigrid_solve_n(ctx, bath_iw, m2, m3, U, beta, dtaus, seed, n_fine=200, n_chains=1,
                       warmup=0, sweeps=1, mode="rank1", recompute_every=0, delay_k=0, n_bins=0,
-                      drift_limit=0.0, drift_every=0, eager=False, heat_bath=False, direct=False):
+                      drift_limit=0.0, drift_every=0, eager=False, heat_bath=False, direct=False, balance=False):
     """multigrid_solve at any filling: dict(g, g_err, tau, D, D_err, n_ref)."""
     b = np.ascontiguousarray(np.asarray(bath_iw, dtype=np.complex128)).view(np.float64)
     dt = np.ascontiguousarray(dtaus, dtype=np.float64)
     o = _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drift_limit,
-              _flags(eager, heat_bath, direct), drift_every=drift_every)
+              _flags(eager, heat_bath, direct, balance=balance), drift_every=drift_every)
     gf = np.zeros(n_fine)
     ef = np.zeros(n_fine)
     dx = np.zeros(2)
@@ -488,7 +502,7 @@ def dmft_bethe_step_mu(g_fine, bath_iw_prev, m2, m3, U, beta, t, mu):
 def dmft_solve_mu(ctx, U, mu, beta, t, dtaus, seed, n_iter, bath_iw=None, n_iw=4096, n_fine=200,
                   mixing=0.0, n_chains=1, warmup=0, sweeps=1, mode="rank1", recompute_every=0,
                   delay_k=0, n_bins=0, drift_limit=0.0, drift_every=0, eager=False,
-                  heat_bath=False, direct=False):
+                  heat_bath=False, direct=False, balance=False):
     """Multigrid DMFT cycle at chemical potential mu, from bath_iw (default: the U = 0
     lattice at mu).  history[it] = (max |g change|, max g_err, D, D_err, n)."""
     if bath_iw is None:
@@ -496,7 +510,7 @@ def dmft_solve_mu(ctx, U, mu, beta, t, dtaus, seed, n_iter, bath_iw=None, n_iw=4
     b = np.ascontiguousarray(np.asarray(bath_iw, dtype=np.complex128)).copy().view(np.float64)
     dt = np.ascontiguousarray(dtaus, dtype=np.float64)
     o = _opts(n_chains, mode, warmup, sweeps, recompute_every, delay_k, n_bins, drift_limit,
-              _flags(eager, heat_bath, direct), drift_every=drift_every)
+              _flags(eager, heat_bath, direct, balance=balance), drift_every=drift_every)
     gf = np.zeros(n_fine)
     ef = np.zeros(n_fine)
     hist = np.zeros(5 * int(n_iter))

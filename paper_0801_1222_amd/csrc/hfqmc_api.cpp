@@ -200,8 +200,12 @@ int resolve_opts(const hfqmc_opts* o, Resolved* r) {
   r->warmup = o->warmup;
   r->sweeps = o->sweeps;
   if (o->flags & ~(HFQMC_FLAG_EAGER | HFQMC_FLAG_HEAT_BATH | HFQMC_FLAG_DIRECT_RECOMPUTE |
-                   HFQMC_FLAG_PH_SYMMETRIC | HFQMC_FLAG_G_FP32))
+                   HFQMC_FLAG_PH_SYMMETRIC | HFQMC_FLAG_G_FP32 | HFQMC_FLAG_BALANCE))
     return fail(HFQMC_EINVAL, "flags=0x%x", o->flags);
+  if ((o->flags & HFQMC_FLAG_BALANCE) &&
+      (o->flip_log || o->flip_count || o->replay_log || o->chain_g || o->chain_d || o->chain_n ||
+       o->chain_drift || o->final_green))
+    return fail(HFQMC_EINVAL, "HFQMC_FLAG_BALANCE changes the chain count: no per-chain hooks");
   if ((o->flags & HFQMC_FLAG_G_FP32) && o->mode != MODE_MIXED)
     return fail(HFQMC_EINVAL, "HFQMC_FLAG_G_FP32 needs the mixed mode (mode=%d)", o->mode);
   if (o->mode == MODE_RANK1) {
@@ -455,6 +459,19 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
       return fail(HFQMC_EUNSUPPORTED, "L=%d: reference solve needs %d bytes of LDS", Lmax, ref_lds);
   }
 
+  // workgroups per CU: limited by LDS (160 KiB per CU) and by 2048 threads per CU
+  const int occ = std::max(1, std::min(c->lds_max / (lds + 1024), 2048 / kThreads));
+  // chains per grid: as requested, or split where that shortens the launch
+  std::vector<int> g_split(n_grids, 1), g_nch(n_grids, nch);
+  if (opts->flags & HFQMC_FLAG_BALANCE)
+    plan_chain_split(n_grids, Ls, nch, r.warmup, r.sweeps, nbin, c->n_cu * occ, g_split.data(),
+                     nullptr, nullptr);
+  long long n_chains_all = 0;
+  for (int i = 0; i < n_grids; ++i) {
+    g_nch[i] = nch * g_split[i];
+    n_chains_all += g_nch[i];
+  }
+
   std::vector<GridDev> gd(n_grids);
   int* d_units = nullptr;
   int* d_queue = nullptr;
@@ -463,13 +480,14 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
   double* d_gtau_dn = nullptr;
   auto layout = [&](Bump& b) {
     d_grids = b.take<GridDev>(n_grids);
-    d_units = b.take<int>((size_t)n_grids * nch);
+    d_units = b.take<int>((size_t)n_chains_all);
     d_queue = b.take<int>(64);
     d_gtau = b.take<double>(Lsum);
     d_gtau_dn = spin ? b.take<double>(Lsum) : nullptr;
     for (int i = 0; i < n_grids; ++i) {
       const int L = Ls[i];
       const int ng = spin ? 2 * (L + 1) : L + 1;
+      const int nch = g_nch[i];   // the hooks below are excluded when it differs from the request
       GridDev& g = gd[i];
       g.G0 = b.take<double>((size_t)L * L);
       g.G0d = spin ? b.take<double>((size_t)L * L) : g.G0;
@@ -506,7 +524,7 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
   // ---- per-grid constants (transcendentals on the host)
   std::vector<GridHost> gh(n_grids);
   std::vector<long long> goff0(n_grids);
-  long long off = 0;
+  long long off = 0, unit_base = 0;
   for (int i = 0; i < n_grids; ++i) {
     const int L = Ls[i];
     const double dtau = beta / L;
@@ -514,9 +532,11 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
     gh[i] = {L, lam};
     GridDev& g = gd[i];
     g.L = L;
-    g.n_chains = nch;
+    g.n_chains = g_nch[i];
+    g.sweeps = r.sweeps / g_split[i];
     g.grid_id = i;
-    g.unit_base = i * nch;
+    g.unit_base = (int)unit_base;
+    unit_base += g_nch[i];
     g.lu_nb = g_nb[i];
     g.direct = direct;
     g.ref_nb = g_ref_nb[i];
@@ -563,19 +583,20 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
                             sizeof(long long) * nch, hipMemcpyHostToDevice, st));
     }
   }
-  // ---- dispatch order: longest chains first (cost per sweep ~ L^3), then grid, chain
+  // ---- dispatch order: longest chains first (the planner's cost model, L^3 per
+  // sweep), then grid, chain
   std::vector<int> units;
-  units.reserve((size_t)n_grids * nch);
+  units.reserve((size_t)n_chains_all);
   std::vector<int> order(n_grids);
   for (int i = 0; i < n_grids; ++i) order[i] = i;
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return Ls[a] > Ls[b]; });
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return unit_cost(Ls[a], r.warmup, gd[a].sweeps) > unit_cost(Ls[b], r.warmup, gd[b].sweeps);
+  });
   for (int i : order)
-    for (int ch = 0; ch < nch; ++ch) units.push_back((i << 20) | ch);
+    for (int ch = 0; ch < g_nch[i]; ++ch) units.push_back((i << 20) | ch);
   HIPCHK(hipMemcpyAsync(d_units, units.data(), sizeof(int) * units.size(), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(d_grids, gd.data(), sizeof(GridDev) * n_grids, hipMemcpyHostToDevice, st));
 
-  // workgroups per CU: limited by LDS (160 KiB per CU) and by 2048 threads per CU
-  const int occ = std::max(1, std::min(c->lds_max / (lds + 1024), 2048 / kThreads));
   const int n_units = (int)units.size();
   int n_wg = std::min(n_units, c->n_cu * occ);
   const long long wstride = workspace_doubles(Lmax, r.mode == MODE_RANK1 ? 1 : kMaxK);
@@ -626,6 +647,7 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
     for (int i = 0; i < n_grids && e == hipSuccess; ++i) {
       const int L = Ls[i];
       const GridDev& g = gd[i];
+      const int nch = g_nch[i];
       if ((e = launch_build_g0(d_gtau + goff0[i], L, const_cast<double*>(g.G0), s)) != hipSuccess) break;
       if (spin &&
           (e = launch_build_g0(d_gtau_dn + goff0[i], L, const_cast<double*>(g.G0d), s)) != hipSuccess)
@@ -662,6 +684,7 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
     key.push_back((unsigned long long)n_wg);
     key.push_back((unsigned long long)lds);
     for (int i = 0; i < n_grids; ++i) key.push_back((unsigned long long)Ls[i]);
+    for (int i = 0; i < n_grids; ++i) key.push_back((unsigned long long)g_nch[i]);
     {
       unsigned long long w[(sizeof(SweepParams) + 7) / 8] = {0};
       std::memcpy(w, &p, sizeof p);
@@ -770,8 +793,8 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
     return call.dev_io ? launch_copy(src, dst, n, st)
                        : hipMemcpyAsync(dst, src, sizeof(double) * n, hipMemcpyDeviceToHost, st);
   };
-  std::vector<long long> cst((size_t)nch * NSTAT);
-  std::vector<double> cdr(nch), cdg(nch);
+  std::vector<long long> cst;
+  std::vector<double> cdr, cdg;
   int ref_bad = 0;
   std::vector<double> gcheck;
   long long goff = 0;
@@ -783,6 +806,10 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
     const int L = Ls[i];
     const int ng = spin ? 2 * (L + 1) : L + 1;
     const GridDev& g = gd[i];
+    const int nchg = g_nch[i];
+    cst.assign((size_t)nchg * NSTAT, 0);
+    cdr.assign(nchg, 0.0);
+    cdg.assign(nchg, 0.0);
     HIPCHK(out_copy(g_tau + goff, g.g_out, ng));
     if (g_err) HIPCHK(out_copy(g_err + goff, g.g_err, ng));
     if (docc) HIPCHK(out_copy(docc + 2 * i, g.d_out, 2));
@@ -791,8 +818,8 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
       HIPCHK(hipMemcpyAsync(gcheck.data(), g.g_out, sizeof(double) * (L + 1), hipMemcpyDeviceToHost, st));
     }
     HIPCHK(hipMemcpyAsync(cst.data(), g.cstats, sizeof(long long) * cst.size(), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(cdr.data(), g.cdrift, sizeof(double) * nch, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(cdg.data(), g.cdrift_gt, sizeof(double) * nch, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(cdr.data(), g.cdrift, sizeof(double) * nchg, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(cdg.data(), g.cdrift_gt, sizeof(double) * nchg, hipMemcpyDeviceToHost, st));
     int rs = 0;
     if (!direct) HIPCHK(hipMemcpyAsync(&rs, g.ref_sing, sizeof(int), hipMemcpyDeviceToHost, st));
     const size_t cb = (size_t)i * nch;
@@ -814,7 +841,7 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
     hfqmc_stats gs;
     std::memset(&gs, 0, sizeof gs);
     double gdrift = 0.0, gdrift_gt = 0.0;
-    for (int ch = 0; ch < nch; ++ch) {
+    for (int ch = 0; ch < nchg; ++ch) {
       const long long* s = &cst[(size_t)ch * NSTAT];
       add_counters(s, c->wall_hz, &gs);
       gdrift = std::max(gdrift, cdr[ch]);
@@ -835,6 +862,8 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
     gs.autotuned = tuned ? 1 : 0;
     gs.seconds_autotune = t_tune;
     gs.recompute_reduced = direct ? 0 : 1;
+    gs.chain_split = g_split[i];
+    tot.chain_split = std::max(tot.chain_split, g_split[i]);
     if (stats && n_grids > 1) stats[i] = gs;
     tot.n_proposed += gs.n_proposed;
     tot.n_accepted += gs.n_accepted;
@@ -964,6 +993,9 @@ extern "C" int hfqmc_solve_dev_noalloc(hfqmc_ctx* c, const double* g0_tau, int32
       opts->chain_drift || opts->final_green)
     return fail(HFQMC_EINVAL, "hfqmc_solve_dev_noalloc: the test hooks are not available here "
                 "(their device copies would need allocations)");
+  if (opts->flags & HFQMC_FLAG_BALANCE)
+    return fail(HFQMC_EINVAL, "hfqmc_solve_dev_noalloc: HFQMC_FLAG_BALANCE is not available here "
+                "(the buffer is sized for n_chains chains)");
   if (r.mode != MODE_RANK1 && r.delay_k == 0)
     return fail(HFQMC_EINVAL, "hfqmc_solve_dev_noalloc: delay_k must be given in the delayed "
                 "modes (the autotuner's trial launches allocate)");
@@ -1053,6 +1085,7 @@ extern "C" int hfqmc_solve_dev_noalloc(hfqmc_ctx* c, const double* g0_tau, int32
   g.n_chains = nch;
   g.grid_id = 0;
   g.unit_base = 0;
+  g.sweeps = r.sweeps;
   g.lu_nb = nb;
   g.direct = direct;
   g.ref_nb = ref_nb;
@@ -1226,6 +1259,28 @@ extern "C" int hfqmc_solve_grids(hfqmc_ctx* c, int32_t n_grids, const int32_t* L
                                  const hfqmc_opts* opts, double* g_tau, double* g_err,
                                  double* docc, hfqmc_stats* stats) {
   return solve_grids_impl(c, n_grids, L, g0_tau, U, beta, seed, opts, g_tau, g_err, docc, stats, Call());
+}
+
+extern "C" int hfqmc_plan_balance(int32_t n_grids, const int32_t* L, int32_t n_chains,
+                                  int64_t warmup, int64_t sweeps, int32_t n_bins,
+                                  int32_t n_workgroups, int32_t* factor, double* span) {
+  if (n_grids < 1 || !L || !factor) return fail(HFQMC_EINVAL, "n_grids=%d, null L or factor", n_grids);
+  if (n_chains < 1 || n_chains >= (1 << 20)) return fail(HFQMC_EINVAL, "n_chains=%d", n_chains);
+  if (warmup < 0 || sweeps < 1) return fail(HFQMC_EINVAL, "warmup=%lld sweeps=%lld",
+                                            (long long)warmup, (long long)sweeps);
+  if (n_bins < 1 || n_bins > sweeps) return fail(HFQMC_EINVAL, "n_bins=%d", n_bins);
+  if (n_workgroups < 1) return fail(HFQMC_EINVAL, "n_workgroups=%d", n_workgroups);
+  for (int i = 0; i < n_grids; ++i)
+    if (L[i] < 2 || L[i] > 4096) return fail(HFQMC_EINVAL, "L[%d]=%d (2..4096)", i, L[i]);
+  std::vector<int> f(n_grids);
+  double s0 = 0.0, s1 = 0.0;
+  plan_chain_split(n_grids, L, n_chains, warmup, sweeps, n_bins, n_workgroups, f.data(), &s0, &s1);
+  for (int i = 0; i < n_grids; ++i) factor[i] = f[i];
+  if (span) {
+    span[0] = s0;
+    span[1] = s1;
+  }
+  return HFQMC_OK;
 }
 
 extern "C" int bethe_semicircle_bath(double beta, double t, int32_t n_iw, double* bath_iw) {

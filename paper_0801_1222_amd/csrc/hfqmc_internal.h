@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 namespace hfqmc {
 
 // Per-chain counters written by the sweep kernel.
@@ -38,7 +40,8 @@ enum { MODE_RANK1 = 0, MODE_DELAYED_FP64 = 1, MODE_MIXED = 2,
 // One Trotter grid of a (possibly batched) launch.  All pointers are device pointers.
 struct GridDev {
   int L;
-  int n_chains;
+  int n_chains;           // chains of this grid (more than requested when split)
+  long long sweeps;       // measured sweeps per chain of this grid
   int grid_id;            // Philox key word 1
   const double* refQ[2];  // L x L, Q_r = M_r^{-1} (1 - G0) for the uniform references
   const double* refH[2];  //   r = 0: D = e^{lambda} - 1, r = 1: D = e^{-lambda} - 1; H_r = M_r^{-1} G0
@@ -159,5 +162,17 @@ hipError_t launch_peak(int kind, const void* src, void* dst, long long n16, int 
                        double* out, hipStream_t s);
 double peak_flops(int kind, int blocks, int iters);
 int peak_threads();
+
+// Chain-split planner (hfqmc_sched.cpp): grid i of a launch runs
+// n_chains * factor[i] chains of sweeps / factor[i] measured sweeps each, factor[i]
+// a power of two up to kMaxChainSplit dividing sweeps with sweeps / factor[i] >=
+// n_bins, chosen to shorten the simulated longest-first dispatch over n_workers
+// workgroups.  The spans are in the cost model's units.
+constexpr int kMaxChainSplit = 64;
+double unit_cost(int L, long long warmup, long long sweeps);
+double lpt_makespan(const std::vector<double>& cost, int n_workers);
+int plan_chain_split(int n_grids, const int* Ls, int n_chains, long long warmup, long long sweeps,
+                     int n_bins, int n_workers, int* factor, double* span_before,
+                     double* span_after);
 
 }  // namespace hfqmc

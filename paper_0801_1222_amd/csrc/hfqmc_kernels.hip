@@ -2444,7 +2444,8 @@ __device__ __forceinline__ void run_chain(const SweepParams& p, const GridDev* g
   // site: recompute (initial, then whenever n_rec flips have been accepted,
   // right after the flip that completes the count), sweep segments, and the
   // measurement after each measured sweep.
-  const long long total = p.warmup + p.sweeps;
+  const long long n_meas = gd->sweeps;   // measured sweeps of this grid's chains
+  const long long total = p.warmup + n_meas;
   long long sw = 0;
   int l = 0;
   bool need_rec = true, first = true;
@@ -2458,7 +2459,7 @@ __device__ __forceinline__ void run_chain(const SweepParams& p, const GridDev* g
       if (sw >= p.warmup) {
         const long long t1 = wall_clock64();
         const long long msw = sw - p.warmup;
-        const int bin = (int)((msw * nb) / p.sweeps);
+        const int bin = (int)((msw * nb) / n_meas);
         measure<GT, SPIN>(ch, bin, p.ph != 0);
         stat_add(ch.st, ST_T_MEAS, wall_clock64() - t1);
       }

@@ -105,3 +105,20 @@ def test_mixed_free_running_matches_fp64(ctx):
     compare_3sigma(mx["g"][1:L], mx["g_err"][1:L], fp["g"][1:L], fp["g_err"][1:L])
     z = abs(mx["D"] - fp["D"]) / np.hypot(mx["D_err"], fp["D_err"])
     assert z < 3.0, (mx["D"], fp["D"], z)
+
+
+def test_mixed_free_running_matches_fp64_long_grid(ctx):
+    """L = 1000 (beta = 100, dtau = 0.1), the long-grid instantiation with the LU
+    panel in the workspace: mixed against FP64 delayed, 256 chains x (10 + 40)
+    sweeps each, independent seeds; D and G(tau) by the 3-sigma rule."""
+    import paper_0801_1222_amd as P
+    beta, U, L = 100.0, 4.8, 1000
+    g0 = _bath(beta, L)
+    kw = dict(n_chains=256, warmup=10, sweeps=40, delay_k=64)
+    mx = P.hfqmc_solve(ctx, g0, U, beta, 0.1, 7, mode="mixed", **kw)
+    fp = P.hfqmc_solve(ctx, g0, U, beta, 0.1, 7 + (1 << 32), mode="delayed", **kw)
+    assert mx["stats"]["n_bad_ratio"] == 0 and fp["stats"]["n_bad_ratio"] == 0
+    assert mx["stats"]["lu_panel"] in (16, 32)       # the matrix-core LU, panel in the workspace
+    compare_3sigma(mx["g"][1:L], mx["g_err"][1:L], fp["g"][1:L], fp["g_err"][1:L])
+    z = abs(mx["D"] - fp["D"]) / np.hypot(mx["D_err"], fp["D_err"])
+    assert z < 3.0, (mx["D"], fp["D"], z)
