@@ -1860,18 +1860,19 @@ __device__ __forceinline__ void flush_vectors(const GT* __restrict__ G, int L, i
   const int ks = (m + 3) >> 2;
   const int mb = (m + 15) >> 4;
   const int nb = (L + 15) >> 4;
-  // X: a wave per row, four rows in flight, lane i gathers column f_i
+  // X: a wave per row, eight rows in flight, lane i gathers column f_i
   {
+    constexpr int kXR = 8;
     const int fi = l0 + F[min(lane, m - 1)];
-    for (int q0 = wv; q0 < L; q0 += 4 * (kThreads / 64)) {
-      double v[4];
+    for (int q0 = wv; q0 < L; q0 += kXR * (kThreads / 64)) {
+      double v[kXR];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < kXR; ++u) {
         const int q = min(q0 + u * (kThreads / 64), L - 1);
         v[u] = G[q * L + fi] - (q == fi ? 1.0 : 0.0);
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < kXR; ++u) {
         const int q = q0 + u * (kThreads / 64);
         if (q < L && lane < m) X[q * kMaxK + lane] = (T)v[u];
       }
