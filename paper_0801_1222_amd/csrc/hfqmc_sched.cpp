@@ -72,6 +72,14 @@ int plan_chain_split(int n_grids, const int* Ls, int n_chains, long long warmup,
     for (int i = 0; i < n_grids; ++i) u += f[i];
     return u;
   };
+  // launches of many chains already keep every workgroup busy to the end (and
+  // would make each simulation long): they are not split, nor simulated
+  if ((long long)n_grids * n_chains > kMaxPlannedChains) {
+    for (int i = 0; i < n_grids; ++i) factor[i] = 1;
+    if (span_before) *span_before = 0.0;
+    if (span_after) *span_after = 0.0;
+    return 0;
+  }
   std::vector<int> f(n_grids, 1);
   double span = simulate(n_grids, Ls, n_chains, warmup, sweeps, f, n_workers);
   if (span_before) *span_before = span;

@@ -103,6 +103,13 @@ def test_split_respects_sweeps_and_bins():
     assert _plan([2000], 1, 0, 1 << 12, 1, 4096)["factor"] == [64]
 
 
+def test_large_launches_are_left_unsplit():
+    r = _plan([250, 2000], 1 << 16, 10, 96, 1, 256)
+    assert r["factor"] == [1, 1] and r["span_before"] == 0.0 and r["span_after"] == 0.0
+    # just below the limit the long grid still splits
+    assert _plan([2000], 8, 10, 96, 1, 256)["factor"][0] > 1
+
+
 def test_plan_argument_errors():
     import paper_0801_1222_amd as P
     bad = [([], 1, 0, 10, 1, 8), ([1], 1, 0, 10, 1, 8), ([100], 0, 0, 10, 1, 8),
