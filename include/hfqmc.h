@@ -273,7 +273,7 @@ int hfqmc_solve_grids(hfqmc_ctx *ctx, int32_t n_grids, const int32_t *L, const d
  * grid's, while the simulated makespan falls by more than 0.5 % (equal spans:
  * fewer chains); f_i stays a power of two <= 64 dividing sweeps with
  * sweeps / f_i >= n_bins, and all f_i are 1 when no split shortens the span
- * or when n_grids * n_chains exceeds 65536 (such launches already fill the
+ * or when n_grids * n_chains exceeds 8192 (such launches already fill the
  * device; span then receives 0, 0: they are not simulated).  factor[n_grids] receives f_i; span (may be NULL)
  * receives the makespan without and with the split, in units of one sweep at
  * L = 1 (cost-model units).  EINVAL for n_grids < 1, NULL L or factor,

@@ -169,7 +169,7 @@ int peak_threads();
 // n_bins, chosen to shorten the simulated longest-first dispatch over n_workers
 // workgroups.  The spans are in the cost model's units.
 constexpr int kMaxChainSplit = 64;
-constexpr long long kMaxPlannedChains = 1 << 16;   // larger launches are left unsplit
+constexpr long long kMaxPlannedChains = 1 << 13;   // larger launches are left unsplit
 double unit_cost(int L, long long warmup, long long sweeps);
 double lpt_makespan(const std::vector<double>& cost, int n_workers);
 int plan_chain_split(int n_grids, const int* Ls, int n_chains, long long warmup, long long sweeps,

@@ -104,8 +104,10 @@ def test_split_respects_sweeps_and_bins():
 
 
 def test_large_launches_are_left_unsplit():
-    r = _plan([250, 2000], 1 << 16, 10, 96, 1, 256)
+    # more than 8192 chains in all: not planned
+    r = _plan([250, 2000], 4097, 10, 96, 1, 256)
     assert r["factor"] == [1, 1] and r["span_before"] == 0.0 and r["span_after"] == 0.0
+    assert _plan([250, 2000], 4096, 10, 96, 1, 256)["span_before"] > 0.0
     # just below the limit the long grid still splits
     assert _plan([2000], 8, 10, 96, 1, 256)["factor"][0] > 1
 
