@@ -188,15 +188,20 @@ typedef struct {
  * beta, L = beta/dtau slices (|beta/dtau - L| <= 1e-9 L), HS coupling
  * cosh(lambda) = exp(dtau U/2).  The periodic recompute
  * G = (1 + (1 - G0)(e^V - 1))^{-1} G0 (FP64) uses, unless
- * HFQMC_FLAG_DIRECT_RECOMPUTE is set or L is too large for its LDS staging,
- * the exact block elimination against the uniform-field reference
+ * HFQMC_FLAG_DIRECT_RECOMPUTE is set, the exact block elimination against the
+ * uniform-field reference
  * M_r = 1 + d_r (1 - G0) (d_r the more frequent of e^{+-lambda} - 1 in the
  * field, Q_r = M_r^{-1}(1 - G0) and H_r = M_r^{-1} G0 computed once per grid on
  * the device): an LU of size |S| <= L/2 on the slices S where the field
  * differs from the reference, then one GEMM for the other rows.
  * Outputs (host): g_tau[L+1] on tau_k = k dtau,
  * k = 0..L (tau_L = beta-); g_err[L+1] (or NULL) standard error over chains
- * (or bins); docc[2] (or NULL) double occupancy and its error; stats (or NULL). */
+ * (or bins); docc[2] (or NULL) double occupancy and its error; stats (or NULL).
+ * Sizes: L from 2 to 4096 passes validation (EINVAL outside).  The LU panels
+ * of the recompute and of the reference solves (L-row systems) are staged in
+ * the LDS of one workgroup (160 KiB on gfx950), which bounds L at 3092 in
+ * the default form and with HFQMC_FLAG_DIRECT_RECOMPUTE: a larger L returns
+ * HFQMC_EUNSUPPORTED before any device work, naming the LDS it would need. */
 int hfqmc_solve(hfqmc_ctx *ctx, const double *g0_tau, int32_t L, double U, double beta,
                 double dtau, uint64_t seed, const hfqmc_opts *opts,
                 double *g_tau, double *g_err, double *docc, hfqmc_stats *stats);
