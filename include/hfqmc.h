@@ -197,11 +197,12 @@ typedef struct {
  * Outputs (host): g_tau[L+1] on tau_k = k dtau,
  * k = 0..L (tau_L = beta-); g_err[L+1] (or NULL) standard error over chains
  * (or bins); docc[2] (or NULL) double occupancy and its error; stats (or NULL).
- * Sizes: L from 2 to 4096 passes validation (EINVAL outside).  The LU panels
- * of the recompute and of the reference solves (L-row systems) are staged in
- * the LDS of one workgroup (160 KiB on gfx950), which bounds L at 3092 in
- * the default form and with HFQMC_FLAG_DIRECT_RECOMPUTE: a larger L returns
- * HFQMC_EUNSUPPORTED before any device work, naming the LDS it would need. */
+ * Sizes: L from 2 to 4096 (EINVAL outside).  The reference solves (L-row
+ * systems) keep their LU panel in LDS where it fits (160 KiB per workgroup on
+ * gfx950) and in the workspace beyond (L > 3092).  HFQMC_FLAG_DIRECT_RECOMPUTE
+ * stages an L-row panel in LDS in every recompute and is limited to L <= 3092:
+ * beyond it returns HFQMC_EUNSUPPORTED before any device work, naming the LDS
+ * it would need. */
 int hfqmc_solve(hfqmc_ctx *ctx, const double *g0_tau, int32_t L, double U, double beta,
                 double dtau, uint64_t seed, const hfqmc_opts *opts,
                 double *g_tau, double *g_err, double *docc, hfqmc_stats *stats);

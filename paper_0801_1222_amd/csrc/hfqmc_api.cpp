@@ -447,12 +447,19 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
   const int lu_nb = plan.lu_nb, scratch = plan.scratch, lds = plan.lds;
   if (lds + 1024 > c->lds_max)
     return fail(HFQMC_EUNSUPPORTED, "L=%d needs %d bytes of LDS, device allows %d", Lmax, lds, c->lds_max);
-  std::vector<int> g_ref_nb(n_grids, 0);
+  std::vector<int> g_ref_nb(n_grids, 0), g_ref_pg(n_grids, 0);
   int ref_scratch = 0, ref_lds = 0;
   if (!direct) {
     for (int i = 0; i < n_grids; ++i) {
+      // the reference solves are L-row systems: where their panel does not fit
+      // LDS it goes to the workspace
       int sc = 0;
-      ref_lds = std::max(ref_lds, lds_bytes(Lmax, Ls[i], -1, 0, 1, &g_ref_nb[i], &sc));
+      int l = lds_bytes(Lmax, Ls[i], -1, 0, 1, &g_ref_nb[i], &sc);
+      if (l + 1024 > c->lds_max) {
+        g_ref_pg[i] = 1;
+        l = lds_bytes(Lmax, Ls[i], -1, 0, 1, &g_ref_nb[i], &sc, 1);
+      }
+      ref_lds = std::max(ref_lds, l);
       ref_scratch = std::max(ref_scratch, sc);
     }
     if (ref_lds + 1024 > c->lds_max)
@@ -540,6 +547,7 @@ int solve_grids_impl(hfqmc_ctx* c, int n_grids, const int32_t* Ls, const double*
     g.lu_nb = g_nb[i];
     g.direct = direct;
     g.ref_nb = g_ref_nb[i];
+    g.ref_pg = g_ref_pg[i];
     g.gp = std::expm1(2.0 * lam);
     g.gm = std::expm1(-2.0 * lam);
     g.ep = std::expm1(lam);
@@ -1089,6 +1097,7 @@ extern "C" int hfqmc_solve_dev_noalloc(hfqmc_ctx* c, const double* g0_tau, int32
   g.lu_nb = nb;
   g.direct = direct;
   g.ref_nb = ref_nb;
+  g.ref_pg = 0;
   g.gp = std::expm1(2.0 * lam);
   g.gm = std::expm1(-2.0 * lam);
   g.ep = std::expm1(lam);

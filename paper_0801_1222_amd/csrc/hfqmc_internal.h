@@ -49,6 +49,7 @@ struct GridDev {
   int lu_nb;              // LU panel width of this grid's recomputes
   int direct;             // 1: full-size recompute (no references), 0: reduced form
   int ref_nb;             // LU panel width of this grid's reference solves
+  int ref_pg;             // 1: the reference solves keep their LU panel in the workspace
   int unit_base;          // index of chain 0 of this grid in the per-launch chain arrays
   double gp, gm;          // e^{2 lambda} - 1, e^{-2 lambda} - 1  (flip factors gamma)
   double ep, em;          // e^{lambda} - 1,   e^{-lambda} - 1    (Dyson matrix diagonal)

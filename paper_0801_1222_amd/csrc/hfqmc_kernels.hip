@@ -2545,14 +2545,22 @@ __global__ void __launch_bounds__(kThreads) k_reference(SweepParams p, int scrat
   if (dn && !gd->spin) return;
   const int nb = gd->ref_nb;
   Chain ch;
-  setup_chain(ch, p, gd, 0, p.work + (long long)blockIdx.x * p.work_stride, lds, nb, scratch_bytes);
+  double* ws = p.work + (long long)blockIdx.x * p.work_stride;
+  setup_chain(ch, p, gd, 0, ws, lds, nb, scratch_bytes);
   if (dn) ch.G0 = gd->G0d;
   for (int l = threadIdx.x; l < ch.L; l += kThreads) ch.s[l] = 1;
   if (threadIdx.x < NSTAT) ch.st[threadIdx.x] = 0;
   __syncthreads();
   double* out = const_cast<double*>(dn ? (kind ? gd->refQd[r] : gd->refHd[r])
                                        : (kind ? gd->refQ[r] : gd->refH[r]));
-  (void)dyson_solve(ch, r == 0 ? 1 : -1, out, nb, false, kind == 1);
+  if (gd->ref_pg) {
+    // long grids: the L-row system's panel does not fit LDS, it goes to the
+    // end of the workgroup's workspace slot (sized for it)
+    ch.Pg = ws + p.work_stride - panel_doubles(p.Lmax);
+    (void)dyson_solve<double, false, true>(ch, r == 0 ? 1 : -1, out, nb, false, kind == 1);
+  } else {
+    (void)dyson_solve(ch, r == 0 ? 1 : -1, out, nb, false, kind == 1);
+  }
   if (threadIdx.x == 0 && ch.st[ST_SINGULAR]) *gd->ref_sing = 1;
 }
 
