@@ -289,6 +289,21 @@ int hfqmc_plan_balance(int32_t n_grids, const int32_t *L, int32_t n_chains, int6
                        int64_t sweeps, int32_t n_bins, int32_t n_workgroups, int32_t *factor,
                        double *span);
 
+/* The uniforms the sweep kernels draw, written out on the device so that the
+ * generator can be checked bit for bit.  The Hubbard-Stratonovich field is
+ * sampled by Monte Carlo (Introduction); the method's draws come from the
+ * counter-based Philox4x64-10 generator (Salmon et al., SC'11) with key
+ * (seed + chain, grid) and counter (slice, sweep, 0, stream), u = (x0 >> 11) 2^-53
+ * of the first output word: stream 0 holds the acceptance draws of slice l in
+ * sweep s, stream 1 at sweep 0 the initial field (s_l = +1 iff u < 1/2).
+ * out[n_sweeps * L] (host) receives u for sweeps sweep0 .. sweep0 + n_sweeps - 1
+ * (row per sweep) and slices 0 .. L - 1.  Allocates and frees a device buffer
+ * of the same size.  EINVAL for a NULL argument, negative chain, grid or
+ * sweep0, n_sweeps or L below 1, stream outside 0..1, or more than 2^28
+ * values; EDEVICE on a runtime error. */
+int hfqmc_uniforms(hfqmc_ctx *ctx, uint64_t seed, int32_t chain, int32_t grid, int64_t sweep0,
+                   int64_t n_sweeps, int32_t L, int32_t stream, double *out);
+
 /* Achievable peaks of the context's device, the ceilings next to the
  * datasheet ones that the sweep kernel's roofline is quoted against (the
  * method's cost model: the update streams the L x L Green matrices through

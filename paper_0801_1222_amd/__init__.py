@@ -8,4 +8,5 @@ from .api import (Context, HFQMCError, bath_to_tau, bethe_atomic_bath,  # noqa: 
                   dmft_bethe_step, dmft_solve, dmft_solve_af, hfqmc_measure_peaks, hfqmc_solve,
                   hfqmc_solve_dev, hfqmc_solve_dev_noalloc, hfqmc_solve_grids, hfqmc_solve_spin,
                   multigrid_solve, multigrid_solve_spin, bethe_lattice_bath, bath_to_tau_m2,
-                  multigrid_solve_n, dmft_bethe_step_mu, dmft_solve_mu, hfqmc_plan_balance)
+                  multigrid_solve_n, dmft_bethe_step_mu, dmft_solve_mu, hfqmc_plan_balance,
+                  hfqmc_uniforms)

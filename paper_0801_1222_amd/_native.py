@@ -125,6 +125,8 @@ lib.dmft_solve_mu.argtypes = [_ctx_p, _f64, _f64, _f64, _f64, _pd, _i32, _u64, C
 lib.dmft_solve_mu.restype = C.c_int
 lib.hfqmc_plan_balance.argtypes = [_i32, _pi32, _i32, _i64, _i64, _i32, _i32, _pi32, _pd]
 lib.hfqmc_plan_balance.restype = C.c_int
+lib.hfqmc_uniforms.argtypes = [_ctx_p, _u64, _i32, _i32, _i64, _i64, _i32, _i32, _pd]
+lib.hfqmc_uniforms.restype = C.c_int
 lib.hfqmc_measure_peaks.argtypes = [_ctx_p, C.POINTER(Peaks)]
 lib.hfqmc_measure_peaks.restype = C.c_int
 
@@ -140,7 +142,7 @@ EXPORTED = ["hfqmc_create", "hfqmc_destroy", "hfqmc_set_stream", "hfqmc_last_err
             "bethe_semicircle_bath", "bethe_atomic_bath", "bath_to_tau", "hfqmc_measure_peaks", "dmft_solve",
             "multigrid_solve_spin", "dmft_solve_af", "hfqmc_solve_dev_noalloc",
             "bethe_lattice_bath", "bath_to_tau_m2", "multigrid_solve_n", "dmft_bethe_step_mu",
-            "dmft_solve_mu", "hfqmc_plan_balance"]
+            "dmft_solve_mu", "hfqmc_plan_balance", "hfqmc_uniforms"]
 
 
 def ptr(a, ctype=C.c_double):

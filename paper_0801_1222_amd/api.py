@@ -266,6 +266,15 @@ def hfqmc_plan_balance(Ls, n_chains, warmup, sweeps, n_bins, n_workgroups):
     return dict(factor=f.tolist(), span_before=float(sp[0]), span_after=float(sp[1]))
 
 
+def hfqmc_uniforms(ctx, seed, chain, grid, sweep0, n_sweeps, L, stream=0):
+    """The method's uniforms as the device draws them: array [n_sweeps, L]."""
+    out = np.zeros(int(n_sweeps) * int(L))
+    rc = N.lib.hfqmc_uniforms(ctx.handle, int(seed), int(chain), int(grid), int(sweep0),
+                              int(n_sweeps), int(L), int(stream), N.ptr(out))
+    N.check(rc, "hfqmc_uniforms")
+    return out.reshape(int(n_sweeps), int(L))
+
+
 def hfqmc_measure_peaks(ctx):
     """Achievable HBM bandwidth (GB/s) and matrix-core / FMA rates (TFLOP/s)
     of the context's device, from the library's probe kernels."""

@@ -12,7 +12,7 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libhfqmc.so")
 
 SOURCES = ["hfqmc_kernels.hip", "hfqmc_peaks.hip", "hfqmc_noalloc.hip", "hfqmc_api.cpp",
-           "hfqmc_host.cpp", "hfqmc_sched.cpp"]
+           "hfqmc_host.cpp", "hfqmc_sched.cpp", "hfqmc_rng.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -1263,6 +1263,28 @@ extern "C" int hfqmc_measure_peaks(hfqmc_ctx* c, hfqmc_peaks* out) {
   return HFQMC_OK;
 }
 
+extern "C" int hfqmc_uniforms(hfqmc_ctx* c, uint64_t seed, int32_t chain, int32_t grid,
+                              int64_t sweep0, int64_t n_sweeps, int32_t L, int32_t stream,
+                              double* out) {
+  if (!c || !out) return fail(HFQMC_EINVAL, "hfqmc_uniforms: NULL argument");
+  if (chain < 0 || grid < 0 || sweep0 < 0 || n_sweeps < 1 || L < 1 || stream < 0 || stream > 1)
+    return fail(HFQMC_EINVAL, "hfqmc_uniforms: chain=%d grid=%d sweep0=%lld n_sweeps=%lld L=%d stream=%d",
+                chain, grid, (long long)sweep0, (long long)n_sweeps, L, stream);
+  const long long n = (long long)n_sweeps * L;
+  if (n > (1LL << 28)) return fail(HFQMC_EINVAL, "hfqmc_uniforms: %lld values (at most 2^28)", n);
+  HIPCHK(hipSetDevice(c->device));
+  DevBuf buf;
+  if (int e = buf.ensure(sizeof(double) * n)) return e;
+  hipStream_t s = c->stream;
+  hipError_t he = launch_uniforms(seed + (uint64_t)chain, (uint64_t)grid, sweep0, n_sweeps, L,
+                                  (uint64_t)stream, (double*)buf.p, s);
+  if (he == hipSuccess) he = hipMemcpyAsync(out, buf.p, sizeof(double) * n, hipMemcpyDeviceToHost, s);
+  if (he == hipSuccess) he = hipStreamSynchronize(s);
+  buf.release();
+  if (he != hipSuccess) return fail(HFQMC_EDEVICE, "hfqmc_uniforms: %s", hipGetErrorString(he));
+  return HFQMC_OK;
+}
+
 extern "C" int hfqmc_solve_grids(hfqmc_ctx* c, int32_t n_grids, const int32_t* L,
                                  const double* g0_tau, double U, double beta, uint64_t seed,
                                  const hfqmc_opts* opts, double* g_tau, double* g_err,

@@ -156,6 +156,11 @@ hipError_t launch_put_grid(const GridDev& g, GridDev* dst, hipStream_t s);
 hipError_t launch_iota(int* p, int n, hipStream_t s);
 hipError_t launch_noalloc_summary(const GridDev* gd, NoAllocSummary* out, hipStream_t s);
 
+// The method's uniforms (hfqmc_rng.hip): out[s L + l] for slices l < L and
+// sweeps sweep0 .. sweep0 + n_sweeps - 1 of one (key0, grid, stream).
+hipError_t launch_uniforms(uint64_t key0, uint64_t grid, long long sweep0, long long n_sweeps,
+                           int L, uint64_t stream, double* out, hipStream_t s);
+
 // Achievable-peak probes (hfqmc_peaks.hip).  Copy / read: n16 16-byte
 // elements of src (and dst); out holds blocks * peak_threads() doubles.
 enum { PEAK_COPY = 0, PEAK_READ = 1, PEAK_MFMA64 = 2, PEAK_MFMA32 = 3, PEAK_FMA64 = 4 };
