@@ -185,3 +185,13 @@ def test_invalid_arguments_raise(ctx):
         P.hfqmc_solve(ctx, g0, 4.0, 10.0, 0.5, 0, sweeps=0)
     with pytest.raises(P.HFQMCError):
         P.hfqmc_solve(ctx, g0[:1], 4.0, 0.5, 0.5, 0)        # L < 2
+    # a non-finite bath in host memory is refused before any device work
+    for bad in (np.nan, np.inf):
+        gb = g0.copy()
+        gb[7] = bad
+        with pytest.raises(P.HFQMCError) as e:
+            P.hfqmc_solve(ctx, gb, 4.0, 10.0, 0.5, 0, n_chains=2, sweeps=4)
+        assert e.value.code == -1 and "not finite" in str(e.value)
+        with pytest.raises(P.HFQMCError) as e:
+            P.hfqmc_solve_grids(ctx, [20, 20], [g0, gb], 4.0, 10.0, 0, n_chains=2, sweeps=4)
+        assert e.value.code == -1 and "not finite" in str(e.value)
