@@ -100,3 +100,30 @@ def test_general_filling_host_routines_match_oracle():
         new = P.dmft_bethe_step_mu(gf, b, -mu, mu * mu + t * t, U, beta, t, mu)
         ref = OMG.dmft_bethe_step_n(gf, tau, bo, -mu, mu * mu + t * t, U, beta, t, mu)
         assert np.abs(new - ref).max() < 1e-11
+
+
+def test_plain_c_caller_of_the_host_entry_points(tmp_path):
+    """The C ABI from C: tests/c_abi/host_calls.c compiled with gcc against
+    include/hfqmc.h and linked to the library, its output equal to the Python
+    binding's (and the oracle's transform)."""
+    import shutil
+    import subprocess
+    import paper_0801_1222_amd as P
+    from paper_0801_1222_amd import _native as N
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    exe = str(tmp_path / "host_calls")
+    libdir = os.path.dirname(N.LIB_PATH)
+    subprocess.run(["gcc", "-std=c99", "-O1", "-I", os.path.join(ROOT, "include"),
+                    os.path.join(ROOT, "tests", "c_abi", "host_calls.c"), "-L", libdir, "-lhfqmc",
+                    "-Wl,-rpath," + libdir, "-o", exe], check=True)
+    out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout.split("\n")
+    g = [float(l.split()[2]) for l in out if l.startswith("g ")]
+    f = [int(l.split()[2]) for l in out if l.startswith("f ")]
+    bath = P.bethe_semicircle_bath(10.0, 1.0, 4096)
+    assert np.array_equal(np.array(g), P.bath_to_tau(bath, 1.0, 10.0, 20))
+    ref = OB.bath_to_tau(OB.semicircle_iw(10.0, 1.0, 4096), 1.0, 10.0, 20)
+    assert np.abs(np.array(g) - ref).max() < 1e-12
+    plan = P.hfqmc_plan_balance([250, 286, 333, 400, 500, 667, 1000, 2000], 32, 100, 1000, 1, 256)
+    assert f == plan["factor"]
+    assert any(l.startswith("error ") and "n_grids" in l for l in out)
